@@ -1,0 +1,149 @@
+/*
+ * teuk.h -- C ABI of libteuk.so, an MI355X (gfx950) implementation of the
+ * two-step Lax-Wendroff time evolution of the homogeneous (2+1)D Teukolsky
+ * equation for one azimuthal mode m on a Kerr background.
+ *
+ * Source of the operation: Choudhary, Navada, Ginjupalli & Khanna,
+ * "An exploration of OpenCL on multiple hardware platforms for a numerical
+ * relativity application" (arXiv:1010.3816), Sec. 3: Eq. (1) (Teukolsky
+ * master equation, Boyer-Lindquist coordinates), the decomposition
+ * Psi = sum_m exp(i m phi) r^3 Phi_m, the first-order system in (Phi, Pi),
+ * the two-step Lax-Wendroff scheme Eqs. (lw1) and (lw2), and the boundary
+ * conditions stated after them (angular: d_theta Phi = 0 at the poles for
+ * even |m|, Phi = 0 for odd |m|; radial: Phi = Pi = 0 at both r* ends).
+ *
+ * Units: M = 1.  Grid: r*_i = rstar_min + i dr, i = 0..nr-1,
+ * dr = (rstar_max - rstar_min)/(nr - 1); theta_j = (j + 1/2) pi/ntheta.
+ * Field arrays: complex128 (interleaved re, im doubles; torch.complex128),
+ * shape [ntheta][nr], r* fastest, dense (row stride nr).
+ *
+ * Conventions for every entry point:
+ *  - return value: TEUK_OK (0) or a negative TEUK_E_* code; the message of
+ *    the last failure on the calling thread is in teuk_last_error().
+ *  - "d_" pointers are device pointers on the grid's device, "h_" pointers
+ *    are host pointers.  Device work is enqueued on the stream given to
+ *    teuk_init_grid and is asynchronous unless stated otherwise.
+ *  - argument errors are detected on the host before any device work is
+ *    enqueued; the grid is then left unchanged.
+ *  - the library never allocates device memory: all device storage lives
+ *    in the caller's workspace (teuk_workspace_bytes) and in the caller's
+ *    arrays, which the caller keeps alive while work using them is queued.
+ *  - a grid handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef TEUK_H
+#define TEUK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TEUK_OK 0
+#define TEUK_E_INVALID_ARG (-1) /* an argument is out of range or NULL       */
+#define TEUK_E_HIP (-2)         /* a HIP runtime call failed                 */
+#define TEUK_E_NONFINITE (-3)   /* the state holds a NaN or an infinity      */
+#define TEUK_E_WORKSPACE (-4)   /* workspace too small or misaligned         */
+#define TEUK_E_STATE (-5)       /* call not valid in the grid's current state */
+
+#define TEUK_COEF_KERR 0 /* coefficients of Eq. (1) for (a, s, m)           */
+#define TEUK_COEF_USER 1 /* caller-supplied coefficient tables              */
+
+#define TEUK_NCOEF 9 /* b, Re c, Im c, Re Ct, Im Ct, A2, A1, Re V0, Im V0   */
+
+typedef struct teuk_grid teuk_grid;
+
+/* Problem description.  The coefficients of the first-order system
+ *   d_t Phi + b Phi'         = Pi
+ *   d_t Pi - b Pi' + c Phi'  = -Ct Pi + A2 Phi_thth + A1 Phi_th - V0 Phi
+ * (' = d/dr*) follow from Eq. (1) with Pi = d_t Phi + b Phi' and
+ * b = (r^2 + a^2)/Sigma, Sigma^2 = (r^2 + a^2)^2 - a^2 Delta sin^2 theta. */
+typedef struct teuk_params {
+    double a;                    /* spin, 0 <= a < 1                              */
+    int32_t s;                   /* spin weight, |s| <= 2                         */
+    int32_t m;                   /* azimuthal mode number                         */
+    int64_t nr;                  /* radial points, 3 <= nr <= 2^24                */
+    int64_t ntheta;              /* angular rows, 2 <= ntheta <= 2^20             */
+    double rstar_min, rstar_max; /* r* range, rstar_min < rstar_max               */
+    double dt;                   /* time step, > 0 (see teuk_suggest_dt)          */
+    int32_t coef_mode;           /* TEUK_COEF_KERR or TEUK_COEF_USER              */
+    int32_t n_extract;           /* number of extraction points, 0..4096          */
+    const double* extract_rstar; /* h_, n_extract entries, in [rstar_min, rstar_max] */
+    const double* extract_theta; /* h_, n_extract entries, in [0, pi]             */
+} teuk_params;
+
+/* Bytes of device workspace a grid with these parameters needs (0 and an
+ * error message if the parameters are invalid).  The workspace must be
+ * 256-byte aligned. */
+size_t teuk_workspace_bytes(const teuk_params* p);
+
+/* Create a grid.  Solves r*(r) on the host, builds the 1-D radial and angular
+ * coefficient tables of Eq. (1) (KERR mode) and uploads them into the
+ * workspace on `hip_stream` (a hipStream_t; NULL = default stream).  The
+ * call returns after the upload has completed.  The state is zero until
+ * teuk_set_initial_data.  *out receives the handle, owned by the caller
+ * (teuk_free).  The workspace must stay allocated until teuk_free. */
+int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, size_t workspace_bytes,
+                   teuk_grid** out);
+
+/* USER mode only: copy caller coefficient tables into the workspace.
+ * d_ci: [TEUK_NCOEF][ntheta][nr] doubles at r*_i; d_ch: [TEUK_NCOEF][ntheta][nr-1]
+ * at r*_{i+1/2}; order as in TEUK_NCOEF.  The arrays may be freed once the
+ * stream has passed this call. */
+int teuk_set_coefficients(teuk_grid* g, const double* d_ci, const double* d_ch);
+
+/* Set the state to (d_phi, d_pi) (complex128 [ntheta][nr], read only),
+ * applying the radial boundary condition (columns 0 and nr-1 set to 0), and
+ * reset the step counter to 0. */
+int teuk_set_initial_data(teuk_grid* g, const void* d_phi, const void* d_pi);
+
+/* Advance the state by n >= 0 Lax-Wendroff steps, Eqs. (lw1)-(lw2), each
+ * followed by the boundary conditions.  If d_series is not NULL it receives
+ * complex128 [n][n_extract]: entry [k][e] is Phi bilinearly interpolated at
+ * extraction point e after step k+1 of this call. */
+int teuk_step_n(teuk_grid* g, int64_t n, void* d_series);
+
+/* Bilinear interpolation of the current Phi at n points (h_rstar, h_theta:
+ * host arrays, r* in range, theta in [0, pi]; outside the first and last row
+ * centres the angular ghost rows are used) into d_out (complex128 [n]). */
+int teuk_extract(teuk_grid* g, int32_t n, const double* h_rstar, const double* h_theta, void* d_out);
+
+/* Copy the current state into caller arrays (complex128 [ntheta][nr]). */
+int teuk_get_state(teuk_grid* g, void* d_phi, void* d_pi);
+
+/* Synchronous check of the current state: TEUK_OK if every value is finite,
+ * TEUK_E_NONFINITE otherwise. */
+int teuk_check_finite(teuk_grid* g);
+
+/* Steps taken since the last teuk_set_initial_data, and the time step. */
+int64_t teuk_steps_taken(const teuk_grid* g);
+double teuk_get_dt(const teuk_grid* g);
+
+/* Launch shape of the step kernel: rows of theta per wavefront tile
+ * (1..ntheta) and wavefronts per workgroup (1, 2, 4 or 8).  Results do not
+ * depend on it (every point's arithmetic is the same). */
+int teuk_set_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per_block);
+int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per_block);
+
+/* Host-only: a time step for n_steps steps of this problem.  Returns
+ * min(courant * dr, dt_g), where dt_g bounds the growth of the fastest
+ * angular mode of the explicit scheme over n_steps to `growth` (for modes
+ * smooth in r* the two stages act as the midpoint rule, amplification
+ * 1 + z + z^2/2, |.|^2 = 1 + (w dt)^4/4).  The fastest angular frequency w is
+ * bounded by Gershgorin's theorem on the discrete theta operator of each
+ * column. */
+int teuk_suggest_dt(const teuk_params* p, int64_t n_steps, double growth, double courant, double* h_dt);
+
+/* Release the handle (host memory only; the workspace stays the caller's).
+ * Waits for work queued on the grid's stream. */
+int teuk_free(teuk_grid* g);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* teuk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TEUK_H */

@@ -1,0 +1,289 @@
+"""ctypes binding of libteuk.so (C ABI in include/teuk.h).
+
+The functions below carry the names of the C entry points and only marshal
+arguments; every step of the evolution runs in the library's gfx950 kernels.
+PyTorch supplies device memory (the workspace and the field tensors) and the
+HIP stream.  If the library has not been built this module raises at import:
+there is no CPU fallback.
+"""
+import ctypes
+
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libteuk.so")
+
+TEUK_OK = 0
+TEUK_E_INVALID_ARG = -1
+TEUK_E_HIP = -2
+TEUK_E_NONFINITE = -3
+TEUK_E_WORKSPACE = -4
+TEUK_E_STATE = -5
+TEUK_COEF_KERR = 0
+TEUK_COEF_USER = 1
+TEUK_NCOEF = 9
+
+_ERRNAMES = {-1: "TEUK_E_INVALID_ARG", -2: "TEUK_E_HIP", -3: "TEUK_E_NONFINITE",
+             -4: "TEUK_E_WORKSPACE", -5: "TEUK_E_STATE"}
+
+
+class TeukError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class teuk_params(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("s", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("nr", ctypes.c_int64), ("ntheta", ctypes.c_int64),
+                ("rstar_min", ctypes.c_double), ("rstar_max", ctypes.c_double),
+                ("dt", ctypes.c_double), ("coef_mode", ctypes.c_int32), ("n_extract", ctypes.c_int32),
+                ("extract_rstar", ctypes.POINTER(ctypes.c_double)),
+                ("extract_theta", ctypes.POINTER(ctypes.c_double))]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, V = ctypes.POINTER(teuk_params), ctypes.c_void_p
+    I32, I64, D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "teuk_workspace_bytes": (ctypes.c_size_t, [P]),
+        "teuk_init_grid": (ctypes.c_int, [P, V, V, ctypes.c_size_t, ctypes.POINTER(V)]),
+        "teuk_set_coefficients": (ctypes.c_int, [V, V, V]),
+        "teuk_set_initial_data": (ctypes.c_int, [V, V, V]),
+        "teuk_step_n": (ctypes.c_int, [V, I64, V]),
+        "teuk_extract": (ctypes.c_int, [V, I32, V, V, V]),
+        "teuk_get_state": (ctypes.c_int, [V, V, V]),
+        "teuk_check_finite": (ctypes.c_int, [V]),
+        "teuk_steps_taken": (I64, [V]),
+        "teuk_get_dt": (D, [V]),
+        "teuk_set_tile": (ctypes.c_int, [V, I32, I32]),
+        "teuk_get_tile": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "teuk_suggest_dt": (ctypes.c_int, [P, I64, D, D, ctypes.POINTER(D)]),
+        "teuk_free": (ctypes.c_int, [V]),
+        "teuk_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("teuk_workspace_bytes", "teuk_init_grid", "teuk_set_coefficients", "teuk_set_initial_data",
+            "teuk_step_n", "teuk_extract", "teuk_get_state", "teuk_check_finite", "teuk_steps_taken",
+            "teuk_get_dt", "teuk_set_tile", "teuk_get_tile", "teuk_suggest_dt", "teuk_free",
+            "teuk_last_error")
+
+
+def _check(rc):
+    if rc != TEUK_OK:
+        raise TeukError(rc, teuk_last_error())
+    return rc
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def teuk_last_error():
+    return _lib.teuk_last_error().decode()
+
+
+def make_params(a, s, m, nr, ntheta, rstar_min, rstar_max, dt, coef_mode=TEUK_COEF_KERR,
+                extract_rstar=(), extract_theta=()):
+    er = np.ascontiguousarray(extract_rstar, dtype=np.float64).ravel()
+    et = np.ascontiguousarray(extract_theta, dtype=np.float64).ravel()
+    if er.shape != et.shape:
+        raise ValueError("extraction coordinate arrays differ in length")
+    p = teuk_params(float(a), int(s), int(m), int(nr), int(ntheta), float(rstar_min), float(rstar_max),
+                    float(dt), int(coef_mode), int(er.size), None, None)
+    if er.size:
+        p.extract_rstar = er.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.extract_theta = et.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p._keep = (er, et)  # keep the host arrays alive as long as the struct
+    return p
+
+
+def teuk_workspace_bytes(p):
+    n = _lib.teuk_workspace_bytes(ctypes.byref(p))
+    if n == 0:
+        raise TeukError(TEUK_E_INVALID_ARG, teuk_last_error())
+    return n
+
+
+def teuk_suggest_dt(p, n_steps, growth=10.0, courant=0.5):
+    out = ctypes.c_double()
+    _check(_lib.teuk_suggest_dt(ctypes.byref(p), int(n_steps), float(growth), float(courant), ctypes.byref(out)))
+    return out.value
+
+
+def teuk_init_grid(p, stream_handle, workspace):
+    h = ctypes.c_void_p()
+    _check(_lib.teuk_init_grid(ctypes.byref(p), ctypes.c_void_p(stream_handle), _dptr(workspace),
+                               workspace.numel() * workspace.element_size(), ctypes.byref(h)))
+    return h
+
+
+def teuk_set_coefficients(h, ci, ch):
+    return _check(_lib.teuk_set_coefficients(h, _dptr(ci), _dptr(ch)))
+
+
+def teuk_set_initial_data(h, phi, pi):
+    return _check(_lib.teuk_set_initial_data(h, _dptr(phi), _dptr(pi)))
+
+
+def teuk_step_n(h, n, series=None):
+    return _check(_lib.teuk_step_n(h, int(n), _dptr(series)))
+
+
+def teuk_extract(h, rstar, theta, out):
+    r = np.ascontiguousarray(rstar, dtype=np.float64).ravel()
+    t = np.ascontiguousarray(theta, dtype=np.float64).ravel()
+    if r.shape != t.shape:
+        raise ValueError("coordinate arrays differ in length")
+    return _check(_lib.teuk_extract(h, int(r.size), r.ctypes.data_as(ctypes.c_void_p),
+                                    t.ctypes.data_as(ctypes.c_void_p), _dptr(out)))
+
+
+def teuk_get_state(h, phi, pi):
+    return _check(_lib.teuk_get_state(h, _dptr(phi), _dptr(pi)))
+
+
+def teuk_check_finite(h):
+    rc = _lib.teuk_check_finite(h)
+    if rc == TEUK_E_NONFINITE:
+        return False
+    _check(rc)
+    return True
+
+
+def teuk_steps_taken(h):
+    return _lib.teuk_steps_taken(h)
+
+
+def teuk_get_dt(h):
+    return _lib.teuk_get_dt(h)
+
+
+def teuk_set_tile(h, rows_per_tile, waves_per_block):
+    return _check(_lib.teuk_set_tile(h, int(rows_per_tile), int(waves_per_block)))
+
+
+def teuk_get_tile(h):
+    r, w = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.teuk_get_tile(h, ctypes.byref(r), ctypes.byref(w)))
+    return r.value, w.value
+
+
+def teuk_free(h):
+    return _check(_lib.teuk_free(h))
+
+
+class TeukGrid:
+    """One grid on the current CUDA/HIP device: owns its workspace tensor.
+
+    Field tensors are torch.complex128 of shape (ntheta, nr) on the device."""
+
+    def __init__(self, a, s, m, nr, ntheta, rstar_min, rstar_max, dt, coef_mode=TEUK_COEF_KERR,
+                 extract_rstar=(), extract_theta=(), device=None, stream=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.params = make_params(a, s, m, nr, ntheta, rstar_min, rstar_max, dt, coef_mode,
+                                  extract_rstar, extract_theta)
+        self.nr, self.ntheta = int(nr), int(ntheta)
+        self.n_extract = self.params.n_extract
+        nbytes = teuk_workspace_bytes(self.params)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.workspace = self.workspace[off:off + nbytes]
+        with torch.cuda.device(self.device):
+            self.handle = teuk_init_grid(self.params, self.stream.cuda_stream, self.workspace)
+
+    @property
+    def shape(self):
+        return (self.ntheta, self.nr)
+
+    @property
+    def dt(self):
+        return teuk_get_dt(self.handle)
+
+    @property
+    def steps(self):
+        return teuk_steps_taken(self.handle)
+
+    def _field(self, t):
+        t = self.torch.as_tensor(t, dtype=self.torch.complex128, device=self.device)
+        if tuple(t.shape) != self.shape:
+            raise ValueError(f"expected shape {self.shape}, got {tuple(t.shape)}")
+        return t.contiguous()
+
+    def set_coefficients(self, ci, ch):
+        ci = self.torch.as_tensor(ci, dtype=self.torch.float64, device=self.device).contiguous()
+        ch = self.torch.as_tensor(ch, dtype=self.torch.float64, device=self.device).contiguous()
+        if ci.numel() != TEUK_NCOEF * self.ntheta * self.nr or ch.numel() != TEUK_NCOEF * self.ntheta * (self.nr - 1):
+            raise ValueError("coefficient tables have the wrong size")
+        self._coef_keep = (ci, ch)
+        teuk_set_coefficients(self.handle, ci, ch)
+
+    def set_initial_data(self, phi, pi):
+        phi, pi = self._field(phi), self._field(pi)
+        self._init_keep = (phi, pi)
+        teuk_set_initial_data(self.handle, phi, pi)
+
+    def step(self, n, series=True):
+        """n steps; returns the extraction series (n, n_extract) complex128 or None."""
+        out = None
+        if series and self.n_extract > 0 and n > 0:
+            out = self.torch.empty((int(n), self.n_extract), dtype=self.torch.complex128, device=self.device)
+        teuk_step_n(self.handle, n, out)
+        return out
+
+    def state(self):
+        phi = self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
+        pi = self.torch.empty_like(phi)
+        teuk_get_state(self.handle, phi, pi)
+        return phi, pi
+
+    def extract(self, rstar, theta):
+        n = int(np.asarray(rstar).size)
+        out = self.torch.empty(n, dtype=self.torch.complex128, device=self.device)
+        teuk_extract(self.handle, rstar, theta, out)
+        return out
+
+    def check_finite(self):
+        return teuk_check_finite(self.handle)
+
+    def set_tile(self, rows_per_tile, waves_per_block):
+        teuk_set_tile(self.handle, rows_per_tile, waves_per_block)
+
+    def tile(self):
+        return teuk_get_tile(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            teuk_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def suggest_dt(a, s, m, nr, ntheta, rstar_min, rstar_max, n_steps, growth=10.0, courant=0.5):
+    p = make_params(a, s, m, nr, ntheta, rstar_min, rstar_max, 1.0)
+    return teuk_suggest_dt(p, n_steps, growth, courant)
+
+
+__all__ = [n for n in EXPORTED] + ["TeukGrid", "TeukError", "make_params", "suggest_dt", "teuk_params"]
+

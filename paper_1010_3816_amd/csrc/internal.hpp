@@ -1,0 +1,85 @@
+// Internal declarations shared by the host library (teuk_api.cpp) and the
+// gfx950 kernels (lw_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+namespace teuk {
+
+// Output columns per wavefront strip.  A wavefront's 64 lanes hold the 64
+// consecutive columns c0-1 .. c0+62 of its strip; lane L computes the
+// stage-1 value at the half point to the right of its column, so the
+// columns c0 .. c0+61 (lanes 1..62) have both neighbouring half points.
+constexpr int kWave = 64;
+constexpr int kStripCols = kWave - 2;
+
+// Radial table fields, each a row of `pitch` doubles, first for the integer
+// positions r*_i then for the half positions r*_{i+1/2}.  With r, Delta,
+// rho = r^2 + a^2 at the position (Sigma^2 = rho^2 - a^2 Delta sin^2 th):
+enum RadField : int {
+    R_RHO = 0,  // rho
+    R_RHO2,     // rho^2
+    R_A2D,      // a^2 Delta                     Sigma^2 = rho^2 - a^2 Delta sin^2
+    R_RB1,      // 2 r Delta / rho               b' = (RB1 - (RB2 - RB3 sin^2)/Sigma^2)/Sigma
+    R_RB2,      // 2 r rho Delta
+    R_RB3,      // a^2 (r - 1) Delta
+    R_CTR,      // 2 s (r Delta - (r^2 - a^2))   Re Ct = CTR / Sigma^2
+    R_CTI0,     // 4 a m r                       Im Ct = (CTI0 + CTI1 cos) / Sigma^2
+    R_CTI1,     // 2 s a Delta
+    R_B1N,      // rho (6 Delta/r + 2 s (r-1) + 2 r Delta/rho)     B1 = B1N / Sigma^2
+    R_DL2,      // Delta / dth^2                 A2/dth^2 = DL2 / Sigma^2
+    R_V0R,      // -m^2 a^2 - 6 Delta ((s+2) r^2 - (s+3) r + a^2) / r^2
+    R_V0I,      // -2 s m a (r - 1)              Im V0 = V0I / Sigma^2
+    kNumRad
+};
+
+// Angular table fields, each a row of ntheta doubles.
+enum AngField : int {
+    A_SN2 = 0,  // sin^2 th
+    A_CS,       // cos th
+    A_COTP,     // cot th * dth / 2               A1/(2 dth) = A2/dth^2 * COTP
+    A_PD,       // ((m + s cos th)^2 / sin^2 th - s) * dth^2   Re V0 = (DL2 PD + V0R)/Sigma^2
+    kNumAng
+};
+
+// USER-mode coefficient order (matches TEUK_NCOEF in teuk.h).
+enum UserCoef : int { U_B = 0, U_CRE, U_CIM, U_CTRE, U_CTIM, U_A2, U_A1, U_V0RE, U_V0IM, kNumUser };
+
+// One extraction point: bilinear weights between columns col, col+1 and the
+// rows rowa, rowb (rowb < 0: single row, ghost rows folded into the weights).
+struct ExtPoint {
+    int32_t col, rowa, rowb, pad;
+    double wr, wa, wb, pad2;
+};
+
+struct StepArgs {
+    const double2* phi_in;   // [nth][pitch]
+    const double2* pi_in;
+    double2* phi_out;
+    double2* pi_out;
+    const double* rad;       // [kNumRad][2][pitch] (KERR)
+    const double* ang;       // [kNumAng][nth]      (KERR)
+    const double* uci;       // [kNumUser][nth][pitch] (USER, integer positions)
+    const double* uch;       // [kNumUser][nth][pitch] (USER, half positions)
+    const ExtPoint* ext;     // [n_ext]
+    double2* series;         // n_ext samples of the input Phi, or nullptr
+    int32_t nr, nth, pitch, sigma;
+    int32_t rows, n_strips, n_tiles, n_ext;
+    double dt, hdt, dt_dr, hdt_dr;
+    double inv_dth2, inv_2dth;  // USER mode scalings
+};
+
+// Launchers (lw_kernels.hip).  All return the hipError_t of the launch.
+hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s);
+hipError_t launch_import(const double2* src, double2* dst, int nr, int nth, int pitch, hipStream_t s);
+hipError_t launch_export(const double2* src, double2* dst, int nr, int nth, int pitch, hipStream_t s);
+hipError_t launch_extract(const double2* phi, int pitch, int sigma, const ExtPoint* pts, int n, double2* out,
+                          hipStream_t s);
+hipError_t launch_nonfinite(const double2* phi, const double2* pi, int nr, int nth, int pitch, int* flag,
+                            hipStream_t s);
+hipError_t launch_pitch_copy(const double* src, double* dst, int rows, int cols, int pitch, hipStream_t s);
+
+}  // namespace teuk

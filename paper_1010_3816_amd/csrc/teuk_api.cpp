@@ -1,0 +1,486 @@
+// C ABI of libteuk.so (declared and documented in include/teuk.h).
+//
+// Host responsibilities: argument validation (before any device work),
+// workspace layout, the 1-D coefficient tables of Eq. (1), extraction
+// weights, launch geometry and ping-pong of the state buffers.  All step
+// arithmetic runs in the gfx950 kernels of lw_kernels.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/teuk.h"
+#include "geometry.hpp"
+#include "internal.hpp"
+
+using namespace teuk;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(TEUK_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxExtract = 4096;
+constexpr int64_t kMaxNr = int64_t(1) << 24;
+constexpr int64_t kMaxNth = int64_t(1) << 20;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    int pitch = 0;
+    size_t state = 0;                 // bytes of one complex field [nth][pitch]
+    size_t off_phi[2]{}, off_pi[2]{}; // ping-pong state
+    size_t off_rad = 0, off_ang = 0;  // KERR tables
+    size_t off_uci = 0, off_uch = 0;  // USER tables
+    size_t off_ext = 0, off_ext2 = 0, off_flag = 0;
+    size_t total = 0;
+};
+
+int validate(const teuk_params* p) {
+    if (!p) return fail(TEUK_E_INVALID_ARG, "params is NULL");
+    if (!(p->a >= 0.0 && p->a < 1.0)) return fail(TEUK_E_INVALID_ARG, "spin a=%g outside [0, 1)", p->a);
+    if (p->s < -2 || p->s > 2) return fail(TEUK_E_INVALID_ARG, "spin weight s=%d outside [-2, 2]", p->s);
+    if (p->m < -1000 || p->m > 1000) return fail(TEUK_E_INVALID_ARG, "m=%d out of range", p->m);
+    if (p->nr < 3 || p->nr > kMaxNr) return fail(TEUK_E_INVALID_ARG, "nr=%lld outside [3, 2^24]", (long long)p->nr);
+    if (p->ntheta < 2 || p->ntheta > kMaxNth)
+        return fail(TEUK_E_INVALID_ARG, "ntheta=%lld outside [2, 2^20]", (long long)p->ntheta);
+    if (!std::isfinite(p->rstar_min) || !std::isfinite(p->rstar_max) || !(p->rstar_min < p->rstar_max))
+        return fail(TEUK_E_INVALID_ARG, "need finite rstar_min < rstar_max");
+    if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(TEUK_E_INVALID_ARG, "dt=%g must be > 0", p->dt);
+    if (p->coef_mode != TEUK_COEF_KERR && p->coef_mode != TEUK_COEF_USER)
+        return fail(TEUK_E_INVALID_ARG, "coef_mode=%d unknown", p->coef_mode);
+    if (p->n_extract < 0 || p->n_extract > kMaxExtract)
+        return fail(TEUK_E_INVALID_ARG, "n_extract=%d outside [0, %d]", p->n_extract, kMaxExtract);
+    if (p->n_extract > 0 && (!p->extract_rstar || !p->extract_theta))
+        return fail(TEUK_E_INVALID_ARG, "extraction coordinates are NULL");
+    const double nptr = (double)p->nr * (double)p->ntheta;
+    if (nptr > 2.0e9) return fail(TEUK_E_INVALID_ARG, "nr*ntheta too large");
+    for (int e = 0; e < p->n_extract; ++e) {
+        const double r = p->extract_rstar[e], t = p->extract_theta[e];
+        if (!(r >= p->rstar_min && r <= p->rstar_max))
+            return fail(TEUK_E_INVALID_ARG, "extraction r*=%g outside the grid", r);
+        if (!(t >= 0.0 && t <= M_PI)) return fail(TEUK_E_INVALID_ARG, "extraction theta=%g outside [0, pi]", t);
+    }
+    return TEUK_OK;
+}
+
+Layout make_layout(const teuk_params* p) {
+    Layout L;
+    const int nr = (int)p->nr, nth = (int)p->ntheta;
+    L.pitch = (nr + 7) / 8 * 8;  // 128-byte rows of complex128
+    L.state = align_up((size_t)nth * L.pitch * sizeof(double2));
+    size_t o = 0;
+    for (int k = 0; k < 2; ++k) {
+        L.off_phi[k] = o;
+        o += L.state;
+        L.off_pi[k] = o;
+        o += L.state;
+    }
+    L.off_rad = o;
+    o += align_up((size_t)kNumRad * 2 * L.pitch * sizeof(double));
+    L.off_ang = o;
+    o += align_up((size_t)kNumAng * nth * sizeof(double));
+    if (p->coef_mode == TEUK_COEF_USER) {
+        L.off_uci = o;
+        o += align_up((size_t)kNumUser * nth * L.pitch * sizeof(double));
+        L.off_uch = o;
+        o += align_up((size_t)kNumUser * nth * L.pitch * sizeof(double));
+    }
+    L.off_ext = o;
+    o += align_up(std::max(1, p->n_extract) * sizeof(ExtPoint));
+    L.off_ext2 = o;
+    o += align_up(kMaxExtract * sizeof(ExtPoint));
+    L.off_flag = o;
+    o += kAlign;
+    L.total = o;
+    return L;
+}
+
+// Bilinear weights of Phi at (r*, theta): columns col, col+1; rows rowa and
+// rowb, with the pole ghost rows (sigma times the mirrored row) folded in.
+ExtPoint ext_point(double rstar, double theta, double rmin, double dr, int nr, int nth, int sigma) {
+    const double dth = M_PI / nth;
+    const double pcol = (rstar - rmin) / dr;
+    int col = (int)std::floor(pcol);
+    col = std::min(std::max(col, 0), nr - 2);
+    const double wr = pcol - col;
+    const double qrow = theta / dth - 0.5;
+    int j = (int)std::floor(qrow);
+    j = std::min(std::max(j, -1), nth - 1);
+    const double wt = qrow - j;
+    ExtPoint E{};
+    E.col = col;
+    E.wr = wr;
+    if (j < 0) {  // rows -1 (ghost of 0) and 0
+        E.rowa = 0;
+        E.wa = wt + sigma * (1.0 - wt);
+        E.rowb = -1;
+        E.wb = 0.0;
+    } else if (j == nth - 1) {  // rows nth-1 and nth (ghost of nth-1)
+        E.rowa = nth - 1;
+        E.wa = (1.0 - wt) + sigma * wt;
+        E.rowb = -1;
+        E.wb = 0.0;
+    } else {
+        E.rowa = j;
+        E.wa = 1.0 - wt;
+        E.rowb = j + 1;
+        E.wb = wt;
+    }
+    return E;
+}
+
+}  // namespace
+
+struct teuk_grid {
+    teuk_params p{};
+    std::vector<double> ext_r, ext_t;
+    std::vector<ExtPoint> ext;
+    Layout L;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    char* ws = nullptr;
+    double dr = 0.0, dth = 0.0;
+    int sigma = 1;
+    int cur = 0;          // which ping-pong buffer holds the state
+    int64_t steps = 0;
+    int rows = 64;        // theta rows per wavefront tile
+    int wpb = 4;          // wavefronts per workgroup
+    bool fused_ext = true;
+    bool coef_set = false;
+
+    double2* phi(int k) const { return reinterpret_cast<double2*>(ws + L.off_phi[k]); }
+    double2* pi(int k) const { return reinterpret_cast<double2*>(ws + L.off_pi[k]); }
+    template <class T>
+    T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+// Fused extraction needs at most one point per lane of a tile.
+bool fused_extraction_ok(const teuk_grid* g) {
+    const auto& E = g->ext;
+    for (size_t i = 0; i < E.size(); ++i)
+        for (size_t k = i + 1; k < E.size(); ++k)
+            if (E[i].col == E[k].col && E[i].rowa / g->rows == E[k].rowa / g->rows) return false;
+    return true;
+}
+
+StepArgs step_args(const teuk_grid* g) {
+    StepArgs a{};
+    a.nr = (int)g->p.nr;
+    a.nth = (int)g->p.ntheta;
+    a.pitch = g->L.pitch;
+    a.sigma = g->sigma;
+    a.rows = g->rows;
+    a.n_strips = (a.nr + kStripCols - 1) / kStripCols;
+    a.n_tiles = a.n_strips * ((a.nth + g->rows - 1) / g->rows);
+    a.dt = g->p.dt;
+    a.hdt = 0.5 * g->p.dt;
+    a.dt_dr = g->p.dt / g->dr;
+    a.hdt_dr = 0.5 * g->p.dt / g->dr;
+    a.inv_dth2 = 1.0 / (g->dth * g->dth);
+    a.inv_2dth = 1.0 / (2.0 * g->dth);
+    a.rad = g->at<double>(g->L.off_rad);
+    a.ang = g->at<double>(g->L.off_ang);
+    if (g->p.coef_mode == TEUK_COEF_USER) {
+        a.uci = g->at<double>(g->L.off_uci);
+        a.uch = g->at<double>(g->L.off_uch);
+    }
+    a.ext = g->at<ExtPoint>(g->L.off_ext);
+    a.n_ext = g->fused_ext ? g->p.n_extract : 0;
+    return a;
+}
+
+int check_grid(const teuk_grid* g) {
+    if (!g) return fail(TEUK_E_INVALID_ARG, "grid handle is NULL");
+    return TEUK_OK;
+}
+
+int set_device(const teuk_grid* g) {
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != g->device) HIP_TRY(hipSetDevice(g->device));
+    return TEUK_OK;
+}
+
+// Gershgorin bound of the largest |eigenvalue| of the discrete theta operator
+// (rows of A2 (f+ - 2 f + f-)/dth^2 + A1 (f+ - f-)/(2 dth) - V0 f, ghost rows
+// folded in) over all integer columns.
+double angular_eig_bound(const teuk_params* p, double dr) {
+    const int nr = (int)p->nr, nth = (int)p->ntheta;
+    const double dth = M_PI / nth;
+    const int sigma = (std::abs(p->m) % 2 == 0) ? 1 : -1;
+    std::vector<double> ang((size_t)nth * kNumAng);
+    for (int j = 0; j < nth; ++j) angular_fields(p->s, p->m, j, dth, &ang[(size_t)j * kNumAng]);
+    double best = 0.0;
+    for (int i = 0; i < nr; ++i) {
+        double x;
+        if (!tortoise_inverse(p->a, p->rstar_min + i * dr, &x)) continue;
+        double R[kNumRad];
+        radial_fields<double>(p->a, p->s, p->m, x, dth, R);
+        for (int j = 0; j < nth; ++j) {
+            const double* G = &ang[(size_t)j * kNumAng];
+            const double inv = 1.0 / (R[R_RHO2] - R[R_A2D] * G[A_SN2]);
+            const double a2 = R[R_DL2] * inv, a1 = a2 * G[A_COTP];
+            const double v0 = std::hypot((R[R_DL2] * G[A_PD] + R[R_V0R]) * inv, R[R_V0I] * inv);
+            double lo = a2 - a1, hi = a2 + a1, diag = -2.0 * a2;  // weights of f-, f+, f
+            if (j == 0) diag += sigma * lo, lo = 0.0;
+            if (j == nth - 1) diag += sigma * hi, hi = 0.0;
+            best = std::max(best, std::fabs(diag) + v0 + std::fabs(lo) + std::fabs(hi));
+        }
+    }
+    return best;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* teuk_last_error(void) { return g_last_error.c_str(); }
+
+size_t teuk_workspace_bytes(const teuk_params* p) {
+    if (validate(p) != TEUK_OK) return 0;
+    return make_layout(p).total;
+}
+
+int teuk_suggest_dt(const teuk_params* p, int64_t n_steps, double growth, double courant, double* h_dt) {
+    if (validate(p) != TEUK_OK) return TEUK_E_INVALID_ARG;
+    if (!h_dt) return fail(TEUK_E_INVALID_ARG, "h_dt is NULL");
+    if (n_steps < 1 || !(growth > 1.0) || !(courant > 0.0))
+        return fail(TEUK_E_INVALID_ARG, "need n_steps >= 1, growth > 1, courant > 0");
+    const double dr = (p->rstar_max - p->rstar_min) / (double)(p->nr - 1);
+    const double w = std::sqrt(angular_eig_bound(p, dr));
+    double dt = courant * dr;
+    if (w > 0.0) dt = std::min(dt, std::pow(8.0 * std::log(growth) / (double)n_steps, 0.25) / w);
+    *h_dt = dt;
+    return TEUK_OK;
+}
+
+int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, size_t workspace_bytes,
+                   teuk_grid** out) {
+    if (int rc = validate(p)) return rc;
+    if (!out) return fail(TEUK_E_INVALID_ARG, "out is NULL");
+    if (!d_workspace) return fail(TEUK_E_INVALID_ARG, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign)
+        return fail(TEUK_E_WORKSPACE, "workspace not %zu-byte aligned", kAlign);
+    const Layout L = make_layout(p);
+    if (workspace_bytes < L.total)
+        return fail(TEUK_E_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+
+    const int nr = (int)p->nr, nth = (int)p->ntheta;
+    const double dr = (p->rstar_max - p->rstar_min) / (double)(nr - 1);
+    const double dth = M_PI / nth;
+
+    // 1-D tables on the host
+    std::vector<double> rad, ang((size_t)kNumAng * nth);
+    if (p->coef_mode == TEUK_COEF_KERR) {
+        rad.assign((size_t)kNumRad * 2 * L.pitch, 0.0);
+        for (int kind = 0; kind < 2; ++kind) {
+            const int npos = kind == 0 ? nr : nr - 1;
+            for (int i = 0; i < npos; ++i) {
+                const double rs = p->rstar_min + (i + 0.5 * kind) * dr;
+                double x;
+                if (!tortoise_inverse(p->a, rs, &x))
+                    return fail(TEUK_E_INVALID_ARG, "tortoise inversion failed at r*=%g", rs);
+                double R[kNumRad];
+                radial_fields<double>(p->a, p->s, p->m, x, dth, R);
+                for (int f = 0; f < kNumRad; ++f) rad[((size_t)f * 2 + kind) * L.pitch + i] = R[f];
+            }
+        }
+    }
+    for (int j = 0; j < nth; ++j) {
+        double G[kNumAng];
+        angular_fields(p->s, p->m, j, dth, G);
+        for (int f = 0; f < kNumAng; ++f) ang[(size_t)f * nth + j] = G[f];
+    }
+
+    teuk_grid* g = new teuk_grid();
+    g->p = *p;
+    g->L = L;
+    g->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    g->ws = reinterpret_cast<char*>(d_workspace);
+    g->dr = dr;
+    g->dth = dth;
+    g->sigma = (std::abs(p->m) % 2 == 0) ? 1 : -1;
+    g->rows = std::min(nth, 64);
+    g->ext_r.assign(p->extract_rstar, p->extract_rstar + p->n_extract);
+    g->ext_t.assign(p->extract_theta, p->extract_theta + p->n_extract);
+    g->p.extract_rstar = g->ext_r.data();
+    g->p.extract_theta = g->ext_t.data();
+    for (int e = 0; e < p->n_extract; ++e)
+        g->ext.push_back(ext_point(g->ext_r[e], g->ext_t[e], p->rstar_min, dr, nr, nth, g->sigma));
+    g->fused_ext = fused_extraction_ok(g);
+    g->coef_set = p->coef_mode == TEUK_COEF_KERR;
+
+    auto bail = [&](int rc) {
+        delete g;
+        return rc;
+    };
+    hipError_t e = hipGetDevice(&g->device);
+    if (e != hipSuccess) return bail(fail(TEUK_E_HIP, "hipGetDevice: %s", hipGetErrorString(e)));
+    hipStream_t s = g->stream;
+    e = hipMemsetAsync(g->ws, 0, L.off_rad, s);
+    if (e == hipSuccess && !rad.empty())
+        e = hipMemcpyAsync(g->ws + L.off_rad, rad.data(), rad.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->ws + L.off_ang, ang.data(), ang.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !g->ext.empty())
+        e = hipMemcpyAsync(g->ws + L.off_ext, g->ext.data(), g->ext.size() * sizeof(ExtPoint),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bail(fail(TEUK_E_HIP, "uploading tables: %s", hipGetErrorString(e)));
+    *out = g;
+    return TEUK_OK;
+}
+
+int teuk_set_coefficients(teuk_grid* g, const double* d_ci, const double* d_ch) {
+    if (int rc = check_grid(g)) return rc;
+    if (g->p.coef_mode != TEUK_COEF_USER) return fail(TEUK_E_STATE, "grid is not in TEUK_COEF_USER mode");
+    if (!d_ci || !d_ch) return fail(TEUK_E_INVALID_ARG, "coefficient pointers are NULL");
+    if (int rc = set_device(g)) return rc;
+    const int nr = (int)g->p.nr, nth = (int)g->p.ntheta;
+    HIP_TRY(launch_pitch_copy(d_ci, g->at<double>(g->L.off_uci), kNumUser * nth, nr, g->L.pitch, g->stream));
+    HIP_TRY(launch_pitch_copy(d_ch, g->at<double>(g->L.off_uch), kNumUser * nth, nr - 1, g->L.pitch, g->stream));
+    g->coef_set = true;
+    return TEUK_OK;
+}
+
+int teuk_set_initial_data(teuk_grid* g, const void* d_phi, const void* d_pi) {
+    if (int rc = check_grid(g)) return rc;
+    if (!d_phi || !d_pi) return fail(TEUK_E_INVALID_ARG, "initial data pointers are NULL");
+    if (int rc = set_device(g)) return rc;
+    const int nr = (int)g->p.nr, nth = (int)g->p.ntheta;
+    HIP_TRY(launch_import(static_cast<const double2*>(d_phi), g->phi(0), nr, nth, g->L.pitch, g->stream));
+    HIP_TRY(launch_import(static_cast<const double2*>(d_pi), g->pi(0), nr, nth, g->L.pitch, g->stream));
+    g->cur = 0;
+    g->steps = 0;
+    return TEUK_OK;
+}
+
+int teuk_step_n(teuk_grid* g, int64_t n, void* d_series) {
+    if (int rc = check_grid(g)) return rc;
+    if (n < 0) return fail(TEUK_E_INVALID_ARG, "n=%lld < 0", (long long)n);
+    if (!g->coef_set) return fail(TEUK_E_STATE, "USER-mode coefficients not set");
+    if (n == 0) return TEUK_OK;
+    if (int rc = set_device(g)) return rc;
+    const int ne = g->p.n_extract;
+    double2* series = (ne > 0) ? static_cast<double2*>(d_series) : nullptr;
+    StepArgs a = step_args(g);
+    const bool kerr = g->p.coef_mode == TEUK_COEF_KERR;
+    const ExtPoint* ext = g->at<ExtPoint>(g->L.off_ext);
+    for (int64_t k = 0; k < n; ++k) {
+        a.phi_in = g->phi(g->cur);
+        a.pi_in = g->pi(g->cur);
+        a.phi_out = g->phi(1 - g->cur);
+        a.pi_out = g->pi(1 - g->cur);
+        // fused: step k samples its input, i.e. the state after step k-1
+        a.series = (series && g->fused_ext && k > 0) ? series + (k - 1) * ne : nullptr;
+        HIP_TRY(launch_step(a, kerr, g->wpb, g->stream));
+        g->cur = 1 - g->cur;
+        g->steps += 1;
+        if (series && !g->fused_ext)
+            HIP_TRY(launch_extract(g->phi(g->cur), g->L.pitch, g->sigma, ext, ne, series + k * ne, g->stream));
+    }
+    if (series && g->fused_ext)
+        HIP_TRY(launch_extract(g->phi(g->cur), g->L.pitch, g->sigma, ext, ne, series + (n - 1) * ne, g->stream));
+    return TEUK_OK;
+}
+
+int teuk_extract(teuk_grid* g, int32_t n, const double* h_rstar, const double* h_theta, void* d_out) {
+    if (int rc = check_grid(g)) return rc;
+    if (n < 0 || n > kMaxExtract) return fail(TEUK_E_INVALID_ARG, "n=%d outside [0, %d]", n, kMaxExtract);
+    if (n == 0) return TEUK_OK;
+    if (!h_rstar || !h_theta || !d_out) return fail(TEUK_E_INVALID_ARG, "NULL pointer");
+    const int nr = (int)g->p.nr, nth = (int)g->p.ntheta;
+    std::vector<ExtPoint> pts(n);
+    for (int e = 0; e < n; ++e) {
+        if (!(h_rstar[e] >= g->p.rstar_min && h_rstar[e] <= g->p.rstar_max))
+            return fail(TEUK_E_INVALID_ARG, "r*=%g outside the grid", h_rstar[e]);
+        if (!(h_theta[e] >= 0.0 && h_theta[e] <= M_PI))
+            return fail(TEUK_E_INVALID_ARG, "theta=%g outside [0, pi]", h_theta[e]);
+        pts[e] = ext_point(h_rstar[e], h_theta[e], g->p.rstar_min, g->dr, nr, nth, g->sigma);
+    }
+    if (int rc = set_device(g)) return rc;
+    ExtPoint* dp = g->at<ExtPoint>(g->L.off_ext2);
+    HIP_TRY(hipMemcpyAsync(dp, pts.data(), n * sizeof(ExtPoint), hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(launch_extract(g->phi(g->cur), g->L.pitch, g->sigma, dp, n, static_cast<double2*>(d_out), g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));  // `pts` is released on return
+    return TEUK_OK;
+}
+
+int teuk_get_state(teuk_grid* g, void* d_phi, void* d_pi) {
+    if (int rc = check_grid(g)) return rc;
+    if (!d_phi || !d_pi) return fail(TEUK_E_INVALID_ARG, "output pointers are NULL");
+    if (int rc = set_device(g)) return rc;
+    const int nr = (int)g->p.nr, nth = (int)g->p.ntheta;
+    HIP_TRY(launch_export(g->phi(g->cur), static_cast<double2*>(d_phi), nr, nth, g->L.pitch, g->stream));
+    HIP_TRY(launch_export(g->pi(g->cur), static_cast<double2*>(d_pi), nr, nth, g->L.pitch, g->stream));
+    return TEUK_OK;
+}
+
+int teuk_check_finite(teuk_grid* g) {
+    if (int rc = check_grid(g)) return rc;
+    if (int rc = set_device(g)) return rc;
+    int* flag = g->at<int>(g->L.off_flag);
+    HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), g->stream));
+    HIP_TRY(launch_nonfinite(g->phi(g->cur), g->pi(g->cur), (int)g->p.nr, (int)g->p.ntheta, g->L.pitch, flag,
+                             g->stream));
+    int h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    if (h) return fail(TEUK_E_NONFINITE, "state holds a non-finite value after %lld steps", (long long)g->steps);
+    return TEUK_OK;
+}
+
+int64_t teuk_steps_taken(const teuk_grid* g) { return g ? g->steps : -1; }
+
+double teuk_get_dt(const teuk_grid* g) { return g ? g->p.dt : 0.0; }
+
+int teuk_set_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per_block) {
+    if (int rc = check_grid(g)) return rc;
+    if (rows_per_tile < 1 || rows_per_tile > g->p.ntheta)
+        return fail(TEUK_E_INVALID_ARG, "rows_per_tile=%d outside [1, ntheta]", rows_per_tile);
+    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4 && waves_per_block != 8)
+        return fail(TEUK_E_INVALID_ARG, "waves_per_block=%d not in {1, 2, 4, 8}", waves_per_block);
+    g->rows = rows_per_tile;
+    g->wpb = waves_per_block;
+    g->fused_ext = fused_extraction_ok(g);
+    return TEUK_OK;
+}
+
+int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per_block) {
+    if (int rc = check_grid(g)) return rc;
+    if (rows_per_tile) *rows_per_tile = g->rows;
+    if (waves_per_block) *waves_per_block = g->wpb;
+    return TEUK_OK;
+}
+
+int teuk_free(teuk_grid* g) {
+    if (!g) return TEUK_OK;
+    hipError_t e = hipStreamSynchronize(g->stream);
+    delete g;
+    if (e != hipSuccess) return fail(TEUK_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    return TEUK_OK;
+}
+
+}  // extern "C"

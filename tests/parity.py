@@ -1,0 +1,52 @@
+"""Shared helpers of the GPU parity tests: run the same seeded input through
+the HIP library (C ABI) and through the oracle, and compare."""
+import math
+
+import numpy as np
+
+import oracle
+from paper_1010_3816_amd import inputs
+
+
+def rel_err(gpu, ref):
+    """Normwise relative error: max |gpu - ref| / max |ref| over all entries."""
+    ref = np.asarray(ref)
+    scale = np.max(np.abs(ref))
+    return float(np.max(np.abs(np.asarray(gpu) - ref)) / (scale if scale > 0 else 1.0))
+
+
+def run_gpu(binding, w, phi0, pi0, n, tile=None, coef=None, mode=None):
+    import torch
+
+    g = binding.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"],
+                         coef_mode=binding.TEUK_COEF_USER if coef is not None else binding.TEUK_COEF_KERR,
+                         extract_rstar=w.get("extract_rstar", []), extract_theta=w.get("extract_theta", []))
+    if coef is not None:
+        g.set_coefficients(torch.from_numpy(coef[0]).cuda(), torch.from_numpy(coef[1]).cuda())
+    if tile is not None:
+        g.set_tile(*tile)
+    g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
+    ser = g.step(n)
+    phi, pi = g.state()
+    torch.cuda.synchronize()
+    out = (phi.cpu().numpy(), pi.cpu().numpy(), None if ser is None else ser.cpu().numpy())
+    g.close()
+    return out
+
+
+def run_oracle(w, phi0, pi0, n, coef=None):
+    o = oracle.OracleGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"],
+                          kerr=coef is None)
+    if coef is not None:
+        o.set_coefficients(*coef)
+    p, q = o.project(phi0, pi0)
+    p, q, ser = o.evolve(p, q, n, w.get("extract_rstar", []), w.get("extract_theta", []))
+    return p, q, ser
+
+
+def small_case(a, s, m, nr, nth, rmin=-30.0, rmax=60.0, dt=None, ext=((20.0, math.pi / 2),)):
+    dr = (rmax - rmin) / (nr - 1)
+    w = dict(a=a, s=s, m=m, nr=nr, ntheta=nth, rstar_min=rmin, rstar_max=rmax,
+             extract_rstar=[e[0] for e in ext], extract_theta=[e[1] for e in ext])
+    w["dt"] = dt if dt is not None else inputs.stable_dt(dr, nth, m, s, 200)
+    return w

@@ -1,0 +1,92 @@
+"""CPU tests of the C-ABI boundary: the library loads, exports every symbol
+declared in include/teuk.h, and rejects invalid arguments on the host before
+touching a device."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "teuk.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(teuk_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def b():
+    import __graft_entry__ as ge
+    from paper_1010_3816_amd import build
+
+    if not os.path.exists(build.LIB):
+        ge.build_hip()
+    from paper_1010_3816_amd import binding
+
+    return binding
+
+
+def test_every_declared_symbol_is_exported(b):
+    lib = ctypes.CDLL(b.LIB_PATH)
+    names = _declared_symbols()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) <= set(b.EXPORTED)
+
+
+def test_workspace_bytes_and_validation(b):
+    p = b.make_params(0.9, -2, 2, 6400, 256, -100.0, 600.0, 1e-3, extract_rstar=[500.0], extract_theta=[math.pi / 2])
+    n = b.teuk_workspace_bytes(p)
+    assert n >= 4 * 6400 * 256 * 16
+    bad = [
+        dict(a=1.0), dict(a=-0.1), dict(s=3), dict(nr=2), dict(ntheta=1), dict(rstar_min=5.0, rstar_max=5.0),
+        dict(dt=0.0), dict(dt=float("nan")),
+    ]
+    base = dict(a=0.5, s=-2, m=2, nr=100, ntheta=8, rstar_min=-10.0, rstar_max=10.0, dt=0.01)
+    for kw in bad:
+        args = dict(base, **kw)
+        with pytest.raises(b.TeukError) as ei:
+            b.teuk_workspace_bytes(b.make_params(**args))
+        assert ei.value.code == b.TEUK_E_INVALID_ARG
+    with pytest.raises(b.TeukError):
+        b.teuk_workspace_bytes(b.make_params(**base, extract_rstar=[11.0], extract_theta=[1.0]))
+    with pytest.raises(b.TeukError):
+        b.teuk_workspace_bytes(b.make_params(**base, extract_rstar=[0.0], extract_theta=[4.0]))
+
+
+def test_init_rejects_before_device_work(b):
+    lib = ctypes.CDLL(b.LIB_PATH)
+    lib.teuk_init_grid.argtypes = [ctypes.POINTER(b.teuk_params), ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]
+    p = b.make_params(0.5, -2, 2, 100, 8, -10.0, 10.0, 0.01)
+    h = ctypes.c_void_p()
+    # NULL workspace, misaligned workspace, too small workspace: all host-side errors
+    assert lib.teuk_init_grid(ctypes.byref(p), None, None, 0, ctypes.byref(h)) == b.TEUK_E_INVALID_ARG
+    assert lib.teuk_init_grid(ctypes.byref(p), None, ctypes.c_void_p(0x1001), 1 << 30,
+                              ctypes.byref(h)) == b.TEUK_E_WORKSPACE
+    assert lib.teuk_init_grid(ctypes.byref(p), None, ctypes.c_void_p(0x100000), 16,
+                              ctypes.byref(h)) == b.TEUK_E_WORKSPACE
+    assert "workspace" in b.teuk_last_error()
+
+
+def test_null_handle_errors(b):
+    lib = ctypes.CDLL(b.LIB_PATH)
+    lib.teuk_step_n.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    assert lib.teuk_step_n(None, 1, None) == b.TEUK_E_INVALID_ARG
+    assert lib.teuk_free(None) == b.TEUK_OK
+
+
+def test_suggest_dt_host_only(b):
+    from paper_1010_3816_amd import inputs
+
+    w = inputs.workload("schwarzschild_400x32")
+    dt = b.suggest_dt(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["steps"])
+    assert 0.0 < dt < 0.5 * w["dr"]
+    # longer runs need smaller steps; growth 10 over n steps scales as n^(-1/4)
+    dt2 = b.suggest_dt(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"],
+                       16 * w["steps"])
+    assert dt2 == pytest.approx(dt / 2, rel=1e-12)

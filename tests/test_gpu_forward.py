@@ -1,0 +1,152 @@
+"""GPU parity of the forward Lax-Wendroff step (C ABI) against the oracle.
+
+Bar: normwise relative error max|gpu - oracle| / max|oracle| <= 1e-11 on the
+state after N steps and on the extraction series (the tolerance named for
+this method; both sides compute in IEEE binary64, so the difference is
+accumulated rounding of differently ordered but identical arithmetic).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1010_3816_amd import inputs
+from parity import rel_err, run_gpu, run_oracle, small_case
+
+TOL = 1e-11
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("a,s,m,nr,nth", [
+    (0.0, -2, 2, 130, 20),     # ragged last strip (130 = 2*62 + 6)
+    (0.7, -2, 1, 200, 17),     # odd |m|: anti-mirror ghosts, odd ntheta
+    (0.9, 0, -3, 187, 70),     # two theta chunks of 64 plus a tail of 6
+    (0.99, -1, 4, 64, 9),
+    (0.5, 2, 0, 3, 2),         # smallest grid: one interior column
+    (0.3, -2, -2, 63, 2),
+])
+def test_random_state_parity(gpu, a, s, m, nr, nth):
+    w = small_case(a, s, m, nr, nth)
+    phi0, pi0 = inputs.random_state(nr, nth, seed=nr * 131 + nth)
+    n = 25
+    g = run_gpu(gpu, w, phi0, pi0, n)
+    o = run_oracle(w, phi0, pi0, n)
+    assert rel_err(g[0], o[0]) <= TOL
+    assert rel_err(g[1], o[1]) <= TOL
+    assert rel_err(g[2], o[2]) <= TOL
+
+
+def test_schwarzschild_400x32_full_run(gpu):
+    """The small standard workload, all 1000 steps, at the policy time step."""
+    w = inputs.workload("schwarzschild_400x32")
+    phi0, pi0 = inputs.initial_data(w)
+    g = run_gpu(gpu, w, phi0, pi0, w["steps"])
+    o = run_oracle(w, phi0, pi0, w["steps"])
+    assert np.all(np.isfinite(g[0]))
+    assert rel_err(g[0], o[0]) <= TOL
+    assert rel_err(g[1], o[1]) <= TOL
+    assert rel_err(g[2], o[2]) <= TOL
+
+
+@pytest.mark.parametrize("tile", [(1, 1), (3, 2), (41, 4), (5, 8), (20, 4)])
+def test_tile_shapes_bit_identical(gpu, tile):
+    """Every point's arithmetic is independent of the launch shape."""
+    w = small_case(0.8, -2, 2, 300, 41, ext=((20.0, 1.0), (-10.0, 2.9), (55.5, 0.01)))
+    phi0, pi0 = inputs.random_state(300, 41, seed=5)
+    ref = run_gpu(gpu, w, phi0, pi0, 7, tile=(41, 1))
+    out = run_gpu(gpu, w, phi0, pi0, 7, tile=tile)
+    for k in range(3):
+        assert np.array_equal(out[k], ref[k])
+
+
+def test_extraction_points_and_fallback(gpu):
+    """Poles, grid ends and two points sharing a column (separate-kernel path)."""
+    ext = ((20.0, math.pi / 2), (20.0, math.pi / 2 + 0.2), (-30.0, 0.0), (60.0, math.pi), (1.23, 0.05))
+    for m in (2, 3):
+        w = small_case(0.6, -2, m, 150, 24, ext=ext)
+        phi0, pi0 = inputs.random_state(150, 24, seed=m)
+        g = run_gpu(gpu, w, phi0, pi0, 9)
+        o = run_oracle(w, phi0, pi0, 9)
+        assert g[2].shape == (9, len(ext))
+        assert rel_err(g[2], o[2]) <= TOL
+
+
+def test_user_coefficients_dalembert(gpu):
+    """USER mode with the d'Alembert coefficients: exact translation at Courant 1."""
+    nr, nth = 200, 4
+    w = dict(a=0.0, s=0, m=0, nr=nr, ntheta=nth, rstar_min=-10.0, rstar_max=10.0)
+    w["dt"] = (w["rstar_max"] - w["rstar_min"]) / (nr - 1)
+    ci = np.zeros((9, nth, nr))
+    ch = np.zeros((9, nth, nr - 1))
+    ci[0] = 1.0
+    ch[0] = 1.0
+    x = np.linspace(-10.0, 10.0, nr)
+    phi0 = np.tile(np.exp(-((x + 4.0) ** 2)) * (1 + 0.3j), (nth, 1))
+    pi0 = np.zeros_like(phi0)
+    g = run_gpu(gpu, w, phi0, pi0, 40, coef=(ci, ch))
+    o = run_oracle(w, phi0, pi0, 40, coef=(ci, ch))
+    assert rel_err(g[0], o[0]) <= TOL
+    p0 = phi0.copy()
+    p0[:, 0] = p0[:, -1] = 0
+    expect = np.zeros_like(p0)
+    expect[:, 41:nr - 1] = p0[:, 1:nr - 41]
+    assert np.max(np.abs(g[0] - expect)) < 1e-14
+
+
+def test_user_coefficients_random(gpu):
+    """USER mode with arbitrary 2-D coefficient tables."""
+    nr, nth = 90, 13
+    rng = np.random.default_rng(11)
+    ci = rng.uniform(-0.5, 0.5, (9, nth, nr))
+    ch = rng.uniform(-0.5, 0.5, (9, nth, nr - 1))
+    ci[0] += 1.0
+    ch[0] += 1.0
+    w = dict(a=0.0, s=0, m=1, nr=nr, ntheta=nth, rstar_min=0.0, rstar_max=30.0, dt=0.01,
+             extract_rstar=[12.3], extract_theta=[0.7])
+    phi0, pi0 = inputs.random_state(nr, nth, seed=4)
+    g = run_gpu(gpu, w, phi0, pi0, 12, coef=(ci, ch))
+    o = run_oracle(w, phi0, pi0, 12, coef=(ci, ch))
+    assert rel_err(g[0], o[0]) <= TOL
+    assert rel_err(g[1], o[1]) <= TOL
+    assert rel_err(g[2], o[2]) <= TOL
+
+
+@pytest.mark.parametrize("name,steps", [("kerr_a0.9_6400x256", 3), ("kerr_a0.99_25600x512", 2)])
+def test_full_size_workloads(gpu, name, steps):
+    """Full-size grids in the default launch configuration: the whole state
+    after a few steps against the oracle."""
+    w = inputs.workload(name)
+    phi0, pi0 = inputs.initial_data(w)
+    rnd = inputs.random_state(w["nr"], w["ntheta"], seed=3)
+    phi0 = phi0 + 1e-3 * rnd[0]
+    pi0 = pi0 + 1e-3 * rnd[1]
+    g = run_gpu(gpu, w, phi0, pi0, steps)
+    o = run_oracle(w, phi0, pi0, steps)
+    assert rel_err(g[0], o[0]) <= TOL
+    assert rel_err(g[1], o[1]) <= TOL
+    if g[2] is not None:
+        assert rel_err(g[2], o[2]) <= TOL
+
+
+def test_state_round_trip_and_finite_check(gpu):
+    import torch
+
+    w = small_case(0.4, 0, 1, 77, 6)
+    phi0, pi0 = inputs.random_state(77, 6, seed=9)
+    g = gpu.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"])
+    g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
+    p, q = g.state()
+    exp_p, exp_q = phi0.copy(), pi0.copy()
+    for arr in (exp_p, exp_q):
+        arr[:, 0] = 0
+        arr[:, -1] = 0
+    assert np.array_equal(p.cpu().numpy(), exp_p) and np.array_equal(q.cpu().numpy(), exp_q)
+    assert g.check_finite()
+    assert g.steps == 0
+    g.step(3)
+    assert g.steps == 3
+    bad = phi0.copy()
+    bad[3, 40] = np.nan
+    g.set_initial_data(torch.from_numpy(bad).cuda(), torch.from_numpy(pi0).cuda())
+    assert not g.check_finite()
+    g.close()
