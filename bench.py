@@ -1,0 +1,173 @@
+"""Throughput benchmark of the fused Lax-Wendroff step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+One "step" is one Lax-Wendroff time step (Eqs. (lw1)-(lw2) of
+arXiv:1010.3816 with the boundary updates) of the whole grid, launched
+through the C ABI (teuk_step_n).  The default workload is the 25600 x 512
+Kerr a = 0.99 grid (13.1 M points, 419 MB per state copy): it does not fit
+in the 256 MB Infinity Cache, so it is the grid on which HBM bandwidth bounds
+the step.  The state is resident in HBM before the timed region starts.
+
+Prints one JSON line.  `value` is grid-point updates per second (one update
+= one (r*, theta) point advanced one full step).  `roofline` prices the step
+kernel at its algorithmic traffic, 64 bytes per update (read Phi, Pi and
+write Phi, Pi once, complex128), against the 8 TB/s HBM peak.  `cpu_baseline`
+times the CPU oracle (test infrastructure, plain C + OpenMP) on a bounded
+number of steps of the same grid.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP64 grid-point updates/s + % HBM roofline; adjoint/forward time ratio"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = 64
+KERNEL_SRC = os.path.join(ROOT, "paper_1010_3816_amd", "csrc", "lw_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lw_step_kerr_a0.99_25600x512_traffic.txt")
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per step launch from the committed rocprofv3 counter summary,
+    if it was taken on this workload with the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("workload") != workload:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, target_seconds=12.0):
+    """The oracle as it stands, on the same grid, for as many whole steps as
+    fit in about `target_seconds` (at least one)."""
+    import numpy as np
+
+    import oracle
+    from paper_1010_3816_amd import inputs
+
+    o = oracle.OracleGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"])
+    phi, pi = inputs.initial_data(w)
+    phi, pi = o.project(phi, pi)
+    t0 = time.perf_counter()
+    phi, pi = o.step(phi, pi, 1)
+    one = time.perf_counter() - t0
+    n = max(1, int(target_seconds / max(one, 1e-6)))
+    t0 = time.perf_counter()
+    phi, pi = o.step(phi, pi, n)
+    el = time.perf_counter() - t0
+    assert np.isfinite(phi).all()
+    pts = w["nr"] * w["ntheta"]
+    return {"value": pts * n / el, "unit": "grid-point updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} steps of the full {w['nr']}x{w['ntheta']} grid ({el:.1f} s), after 1 untimed step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="kerr_a0.99_25600x512")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run a plain 1 GiB streaming kernel (for counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(independent grids and m-modes shard across GPUs without communication)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1010_3816_amd import binding, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    w = inputs.workload(args.workload)
+    g = binding.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"],
+                         extract_rstar=w["extract_rstar"], extract_theta=w["extract_theta"])
+    phi0, pi0 = inputs.initial_data(w)
+    g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
+    series = torch.empty((max(args.steps, args.warmup, 1), max(g.n_extract, 1)), dtype=torch.complex128,
+                         device="cuda")
+    stream = g.stream
+
+    def run(n):
+        binding.teuk_step_n(g.handle, n, series if g.n_extract else None)
+
+    run(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    run(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    assert g.check_finite(), "state became non-finite"
+
+    pts = w["nr"] * w["ntheta"]
+    ms_step = ms / args.steps
+    ups = pts / (ms_step * 1e-3)
+    achieved = BYTES_PER_UPDATE * pts / (ms_step * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload)
+    rows, wpb = g.tile()
+
+    if args.calibrate:
+        n = 1 << 27  # 1 GiB of float64
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+
+    out = {
+        "metric": METRIC,
+        "value": ups,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "nr": w["nr"], "ntheta": w["ntheta"], "a": w["a"], "s": w["s"],
+                   "m": w["m"], "rstar": [w["rstar_min"], w["rstar_max"]], "dt": w["dt"],
+                   "n_extract": g.n_extract, "tile_rows": rows, "waves_per_block": wpb},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "wall_s_timed_region": wall,
+    }
+    g.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

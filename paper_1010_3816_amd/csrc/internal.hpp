@@ -55,6 +55,14 @@ struct ExtPoint {
     double wr, wa, wb, pad2;
 };
 
+// Scalar launch parameters of the step kernel (passed by value).
+struct StepScalars {
+    int32_t nr, nth, pitch, sigma;
+    int32_t rows, n_strips, n_tiles, n_ext;
+    double dt, hdt, dt_dr, hdt_dr;
+    double inv_dth2, inv_2dth;  // USER mode scalings
+};
+
 struct StepArgs {
     const double2* phi_in;   // [nth][pitch]
     const double2* pi_in;
@@ -66,10 +74,7 @@ struct StepArgs {
     const double* uch;       // [kNumUser][nth][pitch] (USER, half positions)
     const ExtPoint* ext;     // [n_ext]
     double2* series;         // n_ext samples of the input Phi, or nullptr
-    int32_t nr, nth, pitch, sigma;
-    int32_t rows, n_strips, n_tiles, n_ext;
-    double dt, hdt, dt_dr, hdt_dr;
-    double inv_dth2, inv_2dth;  // USER mode scalings
+    StepScalars k;
 };
 
 // Launchers (lw_kernels.hip).  All return the hipError_t of the launch.

@@ -37,9 +37,21 @@ __device__ __forceinline__ cd csub(cd a, cd b) { return {a.re - b.re, a.im - b.i
 __device__ __forceinline__ cd cscale(double s, cd a) { return {s * a.re, s * a.im}; }
 __device__ __forceinline__ cd cavg(cd a, cd b) { return {0.5 * (a.re + b.re), 0.5 * (a.im + b.im)}; }
 
-// Cross-lane moves: lane L receives the value held by lane L+1 / lane L-1.
-__device__ __forceinline__ double from_right(double v) { return __shfl_down(v, 1, kWave); }
-__device__ __forceinline__ double from_left(double v) { return __shfl_up(v, 1, kWave); }
+// Cross-lane moves: lane L receives the value held by lane L+1 / lane L-1,
+// as two 32-bit DPP wavefront shifts (wave_shl:1 / wave_shr:1).  The edge
+// lanes (63 and 0) receive 0; their results are never stored.
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kRowsInFlight = 3;  // rows of input loaded ahead of the row being finished
+constexpr int kDppWaveShr1 = 0x138;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_right(double v) { return dpp_move<kDppWaveShl1>(v); }
+__device__ __forceinline__ double from_left(double v) { return dpp_move<kDppWaveShr1>(v); }
 __device__ __forceinline__ cd from_right(cd v) { return {from_right(v.re), from_right(v.im)}; }
 __device__ __forceinline__ cd from_left(cd v) { return {from_left(v.re), from_left(v.im)}; }
 
@@ -160,9 +172,17 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * per + min(x, rem) + idx;
 }
 
-__device__ __forceinline__ cd ld(const double2* p, size_t o, bool in) {
+// Loads always read a valid (clamped) address; where the column lies
+// outside the grid the value is zeroed by a bit mask at its point of use, so
+// the load itself is unconditional and stays in flight until it is needed.
+__device__ __forceinline__ cd ld(const double2* __restrict__ p, size_t o) {
     const double2 v = p[o];
-    return in ? cd{v.x, v.y} : cd{0.0, 0.0};
+    return {v.x, v.y};
+}
+
+__device__ __forceinline__ cd masked(cd v, unsigned long long mask) {
+    return {__longlong_as_double(__double_as_longlong(v.re) & mask),
+            __longlong_as_double(__double_as_longlong(v.im) & mask)};
 }
 
 typedef double v2d __attribute__((ext_vector_type(2)));
@@ -176,17 +196,25 @@ __device__ __forceinline__ void st(double2* p, size_t o, cd v) {
     __builtin_nontemporal_store(w, reinterpret_cast<v2d*>(p + o));
 }
 
+// All pointers are distinct allocations (restrict): the uniform reads of
+// the angular tables and extraction descriptors become scalar loads.
 template <bool KERR>
-__global__ void __launch_bounds__(512) lw_step_kernel(StepArgs A) {
+__global__ void __launch_bounds__(512)
+    lw_step_kernel(const double2* __restrict__ phi_in, const double2* __restrict__ pi_in,
+                   double2* __restrict__ phi_out, double2* __restrict__ pi_out, const double* __restrict__ rad,
+                   const double* __restrict__ ang, const double* __restrict__ uci, const double* __restrict__ uch,
+                   const ExtPoint* __restrict__ ext, double2* __restrict__ series, StepScalars A) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
-    const int tile = xcd_block(blockIdx.x, gridDim.x) * wpb + (threadIdx.x / kWave);
-    if (tile >= A.n_tiles) return;  // wavefront-uniform
+    // wavefront-uniform tile index, made explicit so that everything derived
+    // from it (rows, table reads, loop control) is scalar
+    const int tile = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * wpb + (threadIdx.x / kWave));
+    if (tile >= A.n_tiles) return;
     const int strip = tile % A.n_strips;
     const int chunk = tile / A.n_strips;
     const int nr = A.nr, nth = A.nth, P = A.pitch;
     const int col = strip * kStripCols - 1 + lane;
-    const bool in = (col >= 0) && (col < nr);
+    const unsigned long long in = ((col >= 0) && (col < nr)) ? ~0ull : 0ull;
     const int ci = min(max(col, 0), nr - 1);  // clamped integer column
     const int hi = min(max(col, 0), nr - 2);  // clamped half point col + 1/2
     const bool store_ok = (lane >= 1) && (lane <= kWave - 2) && (col < nr);
@@ -198,8 +226,8 @@ __global__ void __launch_bounds__(512) lw_step_kernel(StepArgs A) {
 
     Rad Ri, Rh;
     if constexpr (KERR) {
-        Ri = load_rad(A.rad, P, 0, ci);
-        Rh = load_rad(A.rad, P, 1, hi);
+        Ri = load_rad(rad, P, 0, ci);
+        Rh = load_rad(rad, P, 1, hi);
     }
 
     // extraction point owned by this lane, if any
@@ -207,7 +235,7 @@ __global__ void __launch_bounds__(512) lw_step_kernel(StepArgs A) {
     double my_wr = 0.0, my_wa = 0.0, my_wb = 0.0;
     cd acc = {0.0, 0.0};
     for (int e = 0; e < A.n_ext; ++e) {
-        const ExtPoint E = A.ext[e];
+        const ExtPoint E = ext[e];
         const int es = E.col / kStripCols;
         if (es == strip && E.rowa / A.rows == chunk && lane == E.col - es * kStripCols + 1) {
             my_e = e;
@@ -231,6 +259,8 @@ __global__ void __launch_bounds__(512) lw_step_kernel(StepArgs A) {
     };
 
     auto fresh = [&](int t, cd p, cd q) -> Row {
+        p = masked(p, in);
+        q = masked(q, in);
         Row R;
         R.p = p;
         R.q = q;
@@ -241,12 +271,12 @@ __global__ void __launch_bounds__(512) lw_step_kernel(StepArgs A) {
         R.dq = csub(qr, q);
         double bh;
         if constexpr (KERR) {
-            const Ang G = load_ang(A.ang, nth, t);
+            const Ang G = load_ang(ang, nth, t);
             R.sh = kerr_sigma(Rh, G);
             bh = Rh.rho * R.sh.isig;
         } else {
             R.sh = {0.0, 0.0};
-            bh = A.uch[((size_t)U_B * nth + t) * P + hi];
+            bh = uch[((size_t)U_B * nth + t) * P + hi];
         }
         // h_Phi = ubar_Phi - dt/2 (b delta_Phi / dr - ubar_Pi)
         const double tb = A.hdt_dr * bh;
@@ -270,57 +300,56 @@ __global__ void __launch_bounds__(512) lw_step_kernel(StepArgs A) {
     {
         if (j0 > 0) {
             const size_t o = (size_t)(j0 - 1) * P + ci;
-            const Row rm = fresh(j0 - 1, ld(A.phi_in, o, in), ld(A.pi_in, o, in));
+            const Row rm = fresh(j0 - 1, ld(phi_in, o), ld(pi_in, o));
             ubp_m = rm.ubp;
             hbp_m = rm.hbp;
         }
         const size_t o = (size_t)j0 * P + ci;
-        cur = fresh(j0, ld(A.phi_in, o, in), ld(A.pi_in, o, in));
+        cur = fresh(j0, ld(phi_in, o), ld(pi_in, o));
         if (j0 == 0) {
             ubp_m = cscale(sg, cur.ubp);
             hbp_m = cscale(sg, cur.hbp);
         }
     }
-    // two rows of loads in flight ahead of the row being finished
-    cd b1p, b1q, b2p, b2q;
-    {
-        const size_t o1 = (size_t)min(j0 + 1, last) * P + ci;
-        const size_t o2 = (size_t)min(j0 + 2, last) * P + ci;
-        b1p = ld(A.phi_in, o1, in);
-        b1q = ld(A.pi_in, o1, in);
-        b2p = ld(A.phi_in, o2, in);
-        b2q = ld(A.pi_in, o2, in);
+    // Ring of D row buffers: buffer u holds row t+1 when row t (t - j0 = u
+    // mod D) is finished, and is refilled with row t+1+D right after.  The
+    // loop is unrolled by D so that loaded registers are never copied (a copy
+    // would have to wait for the load), keeping D rows in flight.
+    cd bp[kRowsInFlight], bq[kRowsInFlight];
+#pragma unroll
+    for (int u = 0; u < kRowsInFlight; ++u) {
+        const size_t o = (size_t)min(j0 + 1 + u, last) * P + ci;
+        bp[u] = ld(phi_in, o);
+        bq[u] = ld(pi_in, o);
     }
 
-    for (int t = j0; t < j1; ++t) {
+    auto finish_row = [&](int t, cd& rp, cd& rq) {
         // row t+1: streamed, or the pole ghost row
         Row nxt;
         cd ubp_p, hbp_p;
         if (t + 1 < nth) {
-            nxt = fresh(t + 1, b1p, b1q);
+            nxt = fresh(t + 1, rp, rq);
             ubp_p = nxt.ubp;
             hbp_p = nxt.hbp;
         } else {
             ubp_p = cscale(sg, cur.ubp);
             hbp_p = cscale(sg, cur.hbp);
         }
-        b1p = b2p;
-        b1q = b2q;
         {
-            const size_t o = (size_t)min(t + 3, last) * P + ci;
-            b2p = ld(A.phi_in, o, in);
-            b2q = ld(A.pi_in, o, in);
+            const size_t o = (size_t)min(t + 1 + kRowsInFlight, last) * P + ci;
+            rp = ld(phi_in, o);
+            rq = ld(pi_in, o);
         }
 
         // stage 1, Pi component at (half, t)
         Coef kh, ki;
         if constexpr (KERR) {
-            const Ang G = load_ang(A.ang, nth, t);
+            const Ang G = load_ang(ang, nth, t);
             kh = kerr_coef(Rh, G, cur.sh);
             ki = kerr_coef(Ri, G, kerr_sigma(Ri, G));
         } else {
-            kh = user_coef(A.uch, nth, P, t, hi, A.inv_dth2, A.inv_2dth);
-            ki = user_coef(A.uci, nth, P, t, ci, A.inv_dth2, A.inv_2dth);
+            kh = user_coef(uch, nth, P, t, hi, A.inv_dth2, A.inv_2dth);
+            ki = user_coef(uci, nth, P, t, ci, A.inv_dth2, A.inv_2dth);
         }
         // h_Pi = ubar_Pi - dt/2 [ (c delta_Phi - b delta_Pi)/dr - S_Pi(ubar) ]
         const cd dq1 = d_pi(kh, cur.dp, cur.dq);
@@ -347,20 +376,30 @@ __global__ void __launch_bounds__(512) lw_step_kernel(StepArgs A) {
         }
         if (store_ok) {
             const size_t o = (size_t)t * P + col;
-            st(A.phi_out, o, np);
-            st(A.pi_out, o, nq);
+            st(phi_out, o, np);
+            st(pi_out, o, nq);
         }
 
         ubp_m = cur.ubp;
         hbp_m = cur.hbp;
         if (t + 1 < nth) cur = nxt;
-    }
+    };
 
-    if (my_e >= 0 && A.series != nullptr) {
+    // whole groups of kRowsInFlight rows, then the ragged tail
+    int t0 = j0;
+    for (; t0 + kRowsInFlight <= j1; t0 += kRowsInFlight) {
+#pragma unroll
+        for (int u = 0; u < kRowsInFlight; ++u) finish_row(t0 + u, bp[u], bq[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kRowsInFlight; ++u)
+        if (t0 + u < j1) finish_row(t0 + u, bp[u], bq[u]);
+
+    if (my_e >= 0 && series != nullptr) {
         double2 w;
         w.x = acc.re;
         w.y = acc.im;
-        A.series[my_e] = w;
+        series[my_e] = w;
     }
 }
 
@@ -428,12 +467,11 @@ __global__ void pitch_copy_kernel(const double* __restrict__ src, double* __rest
 }  // namespace
 
 hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s) {
-    const int nb = (a.n_tiles + waves_per_block - 1) / waves_per_block;
+    const int nb = (a.k.n_tiles + waves_per_block - 1) / waves_per_block;
     const dim3 block(kWave * waves_per_block), grid(nb);
-    if (kerr)
-        hipLaunchKernelGGL(lw_step_kernel<true>, grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL(lw_step_kernel<false>, grid, block, 0, s, a);
+    auto kern = kerr ? lw_step_kernel<true> : lw_step_kernel<false>;
+    hipLaunchKernelGGL(kern, grid, block, 0, s, a.phi_in, a.pi_in, a.phi_out, a.pi_out, a.rad, a.ang, a.uci, a.uch,
+                       a.ext, a.series, a.k);
     return hipGetLastError();
 }
 

@@ -187,19 +187,20 @@ bool fused_extraction_ok(const teuk_grid* g) {
 
 StepArgs step_args(const teuk_grid* g) {
     StepArgs a{};
-    a.nr = (int)g->p.nr;
-    a.nth = (int)g->p.ntheta;
-    a.pitch = g->L.pitch;
-    a.sigma = g->sigma;
-    a.rows = g->rows;
-    a.n_strips = (a.nr + kStripCols - 1) / kStripCols;
-    a.n_tiles = a.n_strips * ((a.nth + g->rows - 1) / g->rows);
-    a.dt = g->p.dt;
-    a.hdt = 0.5 * g->p.dt;
-    a.dt_dr = g->p.dt / g->dr;
-    a.hdt_dr = 0.5 * g->p.dt / g->dr;
-    a.inv_dth2 = 1.0 / (g->dth * g->dth);
-    a.inv_2dth = 1.0 / (2.0 * g->dth);
+    StepScalars& k = a.k;
+    k.nr = (int)g->p.nr;
+    k.nth = (int)g->p.ntheta;
+    k.pitch = g->L.pitch;
+    k.sigma = g->sigma;
+    k.rows = g->rows;
+    k.n_strips = (k.nr + kStripCols - 1) / kStripCols;
+    k.n_tiles = k.n_strips * ((k.nth + g->rows - 1) / g->rows);
+    k.dt = g->p.dt;
+    k.hdt = 0.5 * g->p.dt;
+    k.dt_dr = g->p.dt / g->dr;
+    k.hdt_dr = 0.5 * g->p.dt / g->dr;
+    k.inv_dth2 = 1.0 / (g->dth * g->dth);
+    k.inv_2dth = 1.0 / (2.0 * g->dth);
     a.rad = g->at<double>(g->L.off_rad);
     a.ang = g->at<double>(g->L.off_ang);
     if (g->p.coef_mode == TEUK_COEF_USER) {
@@ -207,7 +208,7 @@ StepArgs step_args(const teuk_grid* g) {
         a.uch = g->at<double>(g->L.off_uch);
     }
     a.ext = g->at<ExtPoint>(g->L.off_ext);
-    a.n_ext = g->fused_ext ? g->p.n_extract : 0;
+    k.n_ext = g->fused_ext ? g->p.n_extract : 0;
     return a;
 }
 
