@@ -70,7 +70,7 @@ def _load():
 _P = ctypes.c_void_p
 _ADJOINT_SIGS = {
     "orc_adjoint_step": [_P, _P, _P],
-    "orc_tangent_a_step": [_P, _P, _P, _P, _P],
+    "orc_tangent_a": [_P, _P, _P, _P, _P],
     "orc_extract_adjoint": [_P, _P, ctypes.c_double, ctypes.c_double, _P],
     "orc_adjoint_evolve": [_P, _P, _P, ctypes.c_int64, ctypes.c_int, _P, _P, _P, _P, _P, _P],
 }
@@ -213,3 +213,42 @@ class OracleGrid:
         out = np.zeros(1, dtype=np.complex128)
         self._lib.orc_extract(self._h, _ptr(phi), float(rstar), float(theta), _ptr(out))
         return complex(out[0])
+
+    # ---- adjoint -----------------------------------------------------------
+    def adjoint_step(self, lam_phi, lam_pi):
+        """A^H applied to the cotangent of the state after one step."""
+        lp = _c128(lam_phi, self.shape).copy()
+        lq = _c128(lam_pi, self.shape).copy()
+        self._lib.orc_adjoint_step(self._h, _ptr(lp), _ptr(lq))
+        return lp, lq
+
+    def tangent_a(self, phi, pi):
+        """(dA/da) u: derivative of one step with respect to the spin at fixed u."""
+        phi = _c128(phi, self.shape)
+        pi = _c128(pi, self.shape)
+        tp = np.zeros(self.shape, dtype=np.complex128)
+        tq = np.zeros(self.shape, dtype=np.complex128)
+        self._lib.orc_tangent_a(self._h, _ptr(phi), _ptr(pi), _ptr(tp), _ptr(tq))
+        return tp, tq
+
+    def extract_adjoint(self, lam_phi, rstar, theta, gval):
+        lp = _c128(lam_phi, self.shape).copy()
+        g = np.array([gval], dtype=np.complex128)
+        self._lib.orc_extract_adjoint(self._h, _ptr(lp), float(rstar), float(theta), _ptr(g))
+        return lp
+
+    def adjoint_evolve(self, phi0, pi0, n, ext_rstar, ext_theta, grad_series):
+        """Reverse pass of n steps: (dL/dphi0, dL/dpi0, dL/da) for a loss with
+        gradient grad_series (n x n_ext, PyTorch complex convention) with
+        respect to the extraction series of evolve()."""
+        phi0 = _c128(phi0, self.shape)
+        pi0 = _c128(pi0, self.shape)
+        er = np.ascontiguousarray(ext_rstar, dtype=np.float64).ravel()
+        et = np.ascontiguousarray(ext_theta, dtype=np.float64).ravel()
+        gs = np.ascontiguousarray(grad_series, dtype=np.complex128).reshape(int(n), er.size)
+        lp = np.zeros(self.shape, dtype=np.complex128)
+        lq = np.zeros(self.shape, dtype=np.complex128)
+        out = ctypes.c_double()
+        self._lib.orc_adjoint_evolve(self._h, _ptr(phi0), _ptr(pi0), int(n), int(er.size), _ptr(er), _ptr(et),
+                                     _ptr(gs), _ptr(lp), _ptr(lq), ctypes.byref(out))
+        return lp, lq, out.value

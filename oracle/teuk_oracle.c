@@ -534,3 +534,241 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint (conjugate transpose) of the step and its spin derivative          */
+/* ------------------------------------------------------------------------ */
+/* The step u -> u' is complex-linear in u.  For a real loss L and the
+ * gradient convention dL/dRe + i dL/dIm, the cotangent of u is A^H applied
+ * to the cotangent of u'.  Each sub-operation of the step is transposed
+ * separately below, in scatter form (every forward read becomes an
+ * accumulation into the location that was read), in the reverse order of
+ * the forward step. */
+
+/* Transpose of apply_S: (oP, oQ) is the cotangent of S's output; the
+ * cotangent of its input is ADDED to (fP, fQ).  The theta stencil scatters
+ * into rows j-1, j, j+1; a contribution to a ghost row lands on the row it
+ * mirrors, times sigma. */
+static void apply_S_adj(const orc_grid* g, const double* coef, int ncol,
+                        const cplx* oP, const cplx* oQ, cplx* fP, cplx* fQ)
+{
+    const int nth = g->nth;
+    const double dth = g->dth, sg = g->sigma;
+    const size_t plane = (size_t)nth * ncol;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < ncol; ++i) {          /* columns are independent */
+        for (int j = 0; j < nth; ++j) {
+            size_t k = (size_t)j * ncol + i;
+            cplx Ct = coef[K_CTRE * plane + k] + I * coef[K_CTIM * plane + k];
+            cplx V0 = coef[K_V0RE * plane + k] + I * coef[K_V0IM * plane + k];
+            double A2 = coef[K_A2 * plane + k] / (dth * dth), A1 = coef[K_A1 * plane + k] / (2.0 * dth);
+            cplx w = oQ[k];
+            fQ[k] += oP[k] + conj(-Ct) * w;
+            fP[k] += (-2.0 * A2 - conj(V0)) * w;
+            /* f_{j+1} with weight A2 + A1, f_{j-1} with weight A2 - A1 */
+            if (j < nth - 1) fP[k + ncol] += (A2 + A1) * w; else fP[k] += sg * (A2 + A1) * w;
+            if (j > 0) fP[k - ncol] += (A2 - A1) * w; else fP[k] += sg * (A2 - A1) * w;
+        }
+    }
+}
+
+/* In place: (lp, lq) = cotangent of u^{n+1}  ->  cotangent of u^n. */
+void orc_adjoint_step(const orc_grid* g, cplx* lp, cplx* lq)
+{
+    const int nr = g->nr, nth = g->nth, nh = nr - 1;
+    const size_t ni = (size_t)nth * nr, nhs = (size_t)nth * nh;
+    const size_t pi_ = ni, ph = nhs;
+    const double dt = g->dt, dr = g->dr, hdt = 0.5 * g->dt;
+    cplx *nuP = calloc(ni, sizeof(cplx)), *nuQ = calloc(ni, sizeof(cplx));
+    cplx *sP = calloc(ni, sizeof(cplx)), *sQ = calloc(ni, sizeof(cplx));
+    cplx *hbP = calloc(ni, sizeof(cplx)), *hbQ = calloc(ni, sizeof(cplx));
+    cplx *dhP = calloc(ni, sizeof(cplx)), *dhQ = calloc(ni, sizeof(cplx));
+    cplx *hP = calloc(nhs, sizeof(cplx)), *hQ = calloc(nhs, sizeof(cplx));
+    cplx *s1P = calloc(nhs, sizeof(cplx)), *s1Q = calloc(nhs, sizeof(cplx));
+    cplx *ubP = calloc(nhs, sizeof(cplx)), *ubQ = calloc(nhs, sizeof(cplx));
+    cplx *dP = calloc(nhs, sizeof(cplx)), *dQ = calloc(nhs, sizeof(cplx));
+
+    /* radial boundary condition of the output: those entries are constants */
+    for (int j = 0; j < nth; ++j)
+        for (int i = 1; i < nr - 1; ++i) {
+            size_t u = (size_t)j * nr + i;
+            nuP[u] = lp[u];
+            nuQ[u] = lq[u];
+        }
+    /* stage 2: Phi' = Phi - dt [ b dhP/dr - S_P ],  Pi' = Pi - dt [ (c dhP - b dhQ)/dr - S_Q ] */
+    for (int j = 0; j < nth; ++j)
+        for (int i = 1; i < nr - 1; ++i) {
+            size_t u = (size_t)j * nr + i;
+            double b = g->ci[K_B * pi_ + u];
+            cplx c = g->ci[K_CRE * pi_ + u] + I * g->ci[K_CIM * pi_ + u];
+            dhP[u] = -(dt / dr) * (b * nuP[u] + conj(c) * nuQ[u]);
+            dhQ[u] = (dt / dr) * b * nuQ[u];
+            sP[u] = dt * nuP[u];
+            sQ[u] = dt * nuQ[u];
+        }
+    apply_S_adj(g, g->ci, nr, sP, sQ, hbP, hbQ);
+    /* hbar_i = (h_{i+1/2} + h_{i-1/2})/2, dh_i = h_{i+1/2} - h_{i-1/2} */
+    for (int j = 0; j < nth; ++j)
+        for (int i = 1; i < nr - 1; ++i) {
+            size_t u = (size_t)j * nr + i, kr = (size_t)j * nh + i, kl = kr - 1;
+            hP[kr] += 0.5 * hbP[u] + dhP[u];
+            hP[kl] += 0.5 * hbP[u] - dhP[u];
+            hQ[kr] += 0.5 * hbQ[u] + dhQ[u];
+            hQ[kl] += 0.5 * hbQ[u] - dhQ[u];
+        }
+    /* stage 1: hP = ubP - dt/2 [ b dP/dr - S_P ],  hQ = ubQ - dt/2 [ (c dP - b dQ)/dr - S_Q ] */
+    for (int j = 0; j < nth; ++j)
+        for (int i = 0; i < nh; ++i) {
+            size_t k = (size_t)j * nh + i;
+            double b = g->ch[K_B * ph + k];
+            cplx c = g->ch[K_CRE * ph + k] + I * g->ch[K_CIM * ph + k];
+            ubP[k] = hP[k];
+            ubQ[k] = hQ[k];
+            dP[k] = -(hdt / dr) * (b * hP[k] + conj(c) * hQ[k]);
+            dQ[k] = (hdt / dr) * b * hQ[k];
+            s1P[k] = hdt * hP[k];
+            s1Q[k] = hdt * hQ[k];
+        }
+    apply_S_adj(g, g->ch, nh, s1P, s1Q, ubP, ubQ);
+    /* ubar = (u_{i+1} + u_i)/2, delta = u_{i+1} - u_i; plus the direct term u of stage 2 */
+    for (int j = 0; j < nth; ++j) {
+        for (int i = 0; i < nr; ++i) {
+            size_t u = (size_t)j * nr + i;
+            lp[u] = nuP[u];
+            lq[u] = nuQ[u];
+        }
+        for (int i = 0; i < nh; ++i) {
+            size_t k = (size_t)j * nh + i, u = (size_t)j * nr + i;
+            lp[u] += 0.5 * ubP[k] - dP[k];
+            lp[u + 1] += 0.5 * ubP[k] + dP[k];
+            lq[u] += 0.5 * ubQ[k] - dQ[k];
+            lq[u + 1] += 0.5 * ubQ[k] + dQ[k];
+        }
+    }
+    cplx* all[] = {nuP, nuQ, sP, sQ, hbP, hbQ, dhP, dhQ, hP, hQ, s1P, s1Q, ubP, ubQ, dP, dQ};
+    for (int k = 0; k < 16; ++k) free(all[k]);
+}
+
+/* d/da of one step at a fixed state: the step with every coefficient
+ * replaced, where it appears, by its derivative (forward-mode tangent;
+ * the state does not depend on a).  Output (tp, tq) = (dA/da) u. */
+void orc_tangent_a(const orc_grid* g, const cplx* phi, const cplx* pi, cplx* tp, cplx* tq)
+{
+    const int nr = g->nr, nth = g->nth, nh = nr - 1;
+    const size_t ni = (size_t)nth * nr, nhs = (size_t)nth * nh;
+    const double dt = g->dt, dr = g->dr, hdt = 0.5 * g->dt;
+    work w;
+    work_alloc(g, &w);
+    cplx *dsP = calloc(nhs, sizeof(cplx)), *dsQ = calloc(nhs, sizeof(cplx));
+    cplx *thP = calloc(nhs, sizeof(cplx)), *thQ = calloc(nhs, sizeof(cplx));
+    cplx *tbP = calloc(ni, sizeof(cplx)), *tbQ = calloc(ni, sizeof(cplx));
+    cplx *tdP = calloc(ni, sizeof(cplx)), *tdQ = calloc(ni, sizeof(cplx));
+    cplx *s2P = calloc(ni, sizeof(cplx)), *s2Q = calloc(ni, sizeof(cplx));
+    cplx *d2P = calloc(ni, sizeof(cplx)), *d2Q = calloc(ni, sizeof(cplx));
+    /* values of stage 1 (h) and its tangent th = -dt/2 [ dD delta/dr - dS(ubar) ] */
+    stage1(g, phi, pi, &w);
+    apply_S(g, g->dch, nh, w.ubP, w.ubQ, dsP, dsQ);   /* coefficient part only: */
+    for (size_t k = 0; k < nhs; ++k) dsP[k] = 0.0;    /* the Phi row of S has no coefficient */
+    for (int j = 0; j < nth; ++j)
+        for (int i = 0; i < nh; ++i) {
+            size_t k = (size_t)j * nh + i;
+            double db = g->dch[K_B * nhs + k];
+            cplx dc = g->dch[K_CRE * nhs + k] + I * g->dch[K_CIM * nhs + k];
+            thP[k] = -hdt * (db * w.dP[k] / dr - dsP[k]);
+            thQ[k] = -hdt * ((dc * w.dP[k] - db * w.dQ[k]) / dr - dsQ[k]);
+        }
+    /* stage 2 values (hbar, dh) and tangents (tbar, td) at interior points */
+    for (int j = 0; j < nth; ++j)
+        for (int i = 1; i < nr - 1; ++i) {
+            size_t u = (size_t)j * nr + i, kr = (size_t)j * nh + i, kl = kr - 1;
+            w.hbP[u] = 0.5 * (w.hP[kr] + w.hP[kl]);
+            w.hbQ[u] = 0.5 * (w.hQ[kr] + w.hQ[kl]);
+            w.dhP[u] = w.hP[kr] - w.hP[kl];
+            w.dhQ[u] = w.hQ[kr] - w.hQ[kl];
+            tbP[u] = 0.5 * (thP[kr] + thP[kl]);
+            tbQ[u] = 0.5 * (thQ[kr] + thQ[kl]);
+            tdP[u] = thP[kr] - thP[kl];
+            tdQ[u] = thQ[kr] - thQ[kl];
+        }
+    /* d/da [ -dt (D_i dh/dr - S_i(hbar)) ] = -dt (dD dh/dr + D td/dr - dS(hbar) - S(tbar)) */
+    apply_S(g, g->dci, nr, w.hbP, w.hbQ, s2P, s2Q);
+    for (size_t u = 0; u < ni; ++u) s2P[u] = 0.0;
+    apply_S(g, g->ci, nr, tbP, tbQ, d2P, d2Q);
+    for (int j = 0; j < nth; ++j)
+        for (int i = 0; i < nr; ++i) {
+            size_t u = (size_t)j * nr + i;
+            if (i == 0 || i == nr - 1) { tp[u] = 0.0; tq[u] = 0.0; continue; }
+            double b = g->ci[K_B * ni + u], db = g->dci[K_B * ni + u];
+            cplx c = g->ci[K_CRE * ni + u] + I * g->ci[K_CIM * ni + u];
+            cplx dc = g->dci[K_CRE * ni + u] + I * g->dci[K_CIM * ni + u];
+            tp[u] = -dt * ((db * w.dhP[u] + b * tdP[u]) / dr - s2P[u] - d2P[u]);
+            tq[u] = -dt * ((dc * w.dhP[u] - db * w.dhQ[u] + c * tdP[u] - b * tdQ[u]) / dr - s2Q[u] - d2Q[u]);
+        }
+    cplx* all[] = {dsP, dsQ, thP, thQ, tbP, tbQ, tdP, tdQ, s2P, s2Q, d2P, d2Q};
+    for (int k = 0; k < 12; ++k) free(all[k]);
+    work_free(&w);
+}
+
+/* Transpose of the bilinear extraction: lam_phi += E^T gval. */
+void orc_extract_adjoint(const orc_grid* g, cplx* lam_phi, double rs, double th, const cplx* gval)
+{
+    double p = (rs - g->rmin) / g->dr;
+    int i0 = (int)floor(p);
+    if (i0 < 0) i0 = 0;
+    if (i0 > g->nr - 2) i0 = g->nr - 2;
+    double wr = p - i0;
+    double q = th / g->dth - 0.5;
+    int j0 = (int)floor(q);
+    if (j0 < -1) j0 = -1;
+    if (j0 > g->nth - 1) j0 = g->nth - 1;
+    double wt = q - j0;
+    for (int t = 0; t < 2; ++t) {
+        int j = j0 + t;
+        double sgn = 1.0;
+        if (j < 0) { j = 0; sgn = g->sigma; }
+        if (j > g->nth - 1) { j = g->nth - 1; sgn = g->sigma; }
+        double wrow = (t == 0 ? 1.0 - wt : wt) * sgn;
+        size_t u = (size_t)j * g->nr + i0;
+        lam_phi[u] += wrow * (1.0 - wr) * (*gval);
+        lam_phi[u + 1] += wrow * wr * (*gval);
+    }
+}
+
+/* Reverse pass of n steps from (phi0, pi0) for a loss whose gradient with
+ * respect to the extraction series (n x n_ext, sample k taken after step
+ * k+1) is gser.  Returns the cotangent of the initial data (projected by
+ * the radial boundary condition of the initial data) and dL/da.  Keeps all
+ * n states in memory: small grids only. */
+void orc_adjoint_evolve(const orc_grid* g, const cplx* phi0, const cplx* pi0, int64_t n, int n_ext,
+                        const double* ext_r, const double* ext_th, const cplx* gser,
+                        cplx* lam_phi, cplx* lam_pi, double* dLda)
+{
+    const size_t ni = (size_t)g->nth * g->nr;
+    cplx* states = malloc(sizeof(cplx) * 2 * ni * (size_t)(n > 0 ? n : 1));
+    cplx *p = malloc(sizeof(cplx) * ni), *q = malloc(sizeof(cplx) * ni);
+    cplx *tp = malloc(sizeof(cplx) * ni), *tq = malloc(sizeof(cplx) * ni);
+    memcpy(p, phi0, sizeof(cplx) * ni);
+    memcpy(q, pi0, sizeof(cplx) * ni);
+    orc_project(g, p, q);
+    for (int64_t k = 0; k < n; ++k) {
+        memcpy(states + 2 * ni * k, p, sizeof(cplx) * ni);
+        memcpy(states + 2 * ni * k + ni, q, sizeof(cplx) * ni);
+        orc_step(g, p, q);
+    }
+    memset(lam_phi, 0, sizeof(cplx) * ni);
+    memset(lam_pi, 0, sizeof(cplx) * ni);
+    double acc = 0.0;
+    if (n > 0)
+        for (int e = 0; e < n_ext; ++e) orc_extract_adjoint(g, lam_phi, ext_r[e], ext_th[e], &gser[(n - 1) * n_ext + e]);
+    for (int64_t m = n - 1; m >= 0; --m) {
+        orc_tangent_a(g, states + 2 * ni * m, states + 2 * ni * m + ni, tp, tq);
+        for (size_t u = 0; u < ni; ++u) acc += creal(conj(lam_phi[u]) * tp[u] + conj(lam_pi[u]) * tq[u]);
+        orc_adjoint_step(g, lam_phi, lam_pi);
+        if (m >= 1)
+            for (int e = 0; e < n_ext; ++e)
+                orc_extract_adjoint(g, lam_phi, ext_r[e], ext_th[e], &gser[(m - 1) * n_ext + e]);
+    }
+    orc_project(g, lam_phi, lam_pi);
+    *dLda = acc;
+    free(states); free(p); free(q); free(tp); free(tq);
+}
