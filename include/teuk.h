@@ -135,6 +135,49 @@ int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per
  * column. */
 int teuk_suggest_dt(const teuk_params* p, int64_t n_steps, double growth, double courant, double* h_dt);
 
+/* ---- Forward states kept for the adjoint ------------------------------ */
+
+/* Bytes of a window holding n states (one slot per state, layout internal
+ * to the library; 256-byte aligned, caller-allocated). */
+size_t teuk_window_bytes(const teuk_grid* g, int64_t n);
+
+/* As teuk_step_n, and also copy the state before step k (k = 0..n-1) into
+ * window slot k.  d_window may be reused by later calls once the stream has
+ * passed the adjoint call that reads it. */
+int teuk_step_n_store(teuk_grid* g, int64_t n, void* d_series, void* d_window);
+
+/* ---- Adjoint (gradients of a loss of the extraction series) ------------
+ * The Lax-Wendroff step with its boundary conditions is a complex-linear
+ * map u^{k+1} = A u^k; for a real loss L with the gradient convention
+ * dL/dRe + i dL/dIm, cotangents propagate by the conjugate transpose A^H,
+ * and the spin enters through the coefficients of Eq. (1) (and r(r*; a)),
+ * dL/da = sum_k Re <lambda^{k+1}, (dA/da) u^k>. */
+
+#define TEUK_ADJ_PROJECT_INITIAL 1 /* zero the radial boundary columns of the result,
+                                      giving the gradient w.r.t. the arguments of
+                                      teuk_set_initial_data */
+
+/* Device bytes for teuk_enable_adjoint (256-byte aligned, caller-allocated). */
+size_t teuk_adjoint_workspace_bytes(teuk_grid* g);
+
+/* Build the a-derivative tables (dual numbers on the host) and attach the
+ * adjoint workspace.  KERR mode only.  Synchronous. */
+int teuk_enable_adjoint(teuk_grid* g, void* d_adj_workspace, size_t bytes);
+
+/* Reverse of one segment of n forward steps whose input states are in
+ * d_window (as written by teuk_step_n_store; slot k = state s0+k).
+ *   d_lam_phi, d_lam_pi  (complex128 [ntheta][nr], in/out): in, the
+ *       cotangent of state s0+n from everything after the segment; out, the
+ *       cotangent of state s0 including the segment's samples.
+ *   d_dL_dseries (complex128 [n][n_extract], or NULL = 0): gradient of L
+ *       with respect to the series written by the forward call.
+ *   flags: 0 or TEUK_ADJ_PROJECT_INITIAL.
+ *   h_dL_da_accum: += this segment's part of dL/da (the call synchronises).
+ * Segments are processed last to first; the result of one is the input of
+ * the previous one. */
+int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi, const void* d_dL_dseries,
+                        const void* d_window, int32_t flags, double* h_dL_da_accum);
+
 /* Release the handle (host memory only; the workspace stays the caller's).
  * Waits for work queued on the grid's stream. */
 int teuk_free(teuk_grid* g);

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libteuk.so")
+# TEUK_LIBRARY may point at another build of the same sources (tuning runs).
+LIB_PATH = os.environ.get("TEUK_LIBRARY", os.path.join(_PKG, "libteuk.so"))
 
 TEUK_OK = 0
 TEUK_E_INVALID_ARG = -1
@@ -24,6 +25,7 @@ TEUK_E_STATE = -5
 TEUK_COEF_KERR = 0
 TEUK_COEF_USER = 1
 TEUK_NCOEF = 9
+TEUK_ADJ_PROJECT_INITIAL = 1
 
 _ERRNAMES = {-1: "TEUK_E_INVALID_ARG", -2: "TEUK_E_HIP", -3: "TEUK_E_NONFINITE",
              -4: "TEUK_E_WORKSPACE", -5: "TEUK_E_STATE"}
@@ -66,6 +68,11 @@ def _load():
         "teuk_suggest_dt": (ctypes.c_int, [P, I64, D, D, ctypes.POINTER(D)]),
         "teuk_free": (ctypes.c_int, [V]),
         "teuk_last_error": (ctypes.c_char_p, []),
+        "teuk_window_bytes": (ctypes.c_size_t, [V, I64]),
+        "teuk_step_n_store": (ctypes.c_int, [V, I64, V, V]),
+        "teuk_adjoint_workspace_bytes": (ctypes.c_size_t, [V]),
+        "teuk_enable_adjoint": (ctypes.c_int, [V, V, ctypes.c_size_t]),
+        "teuk_adjoint_step_n": (ctypes.c_int, [V, I64, V, V, V, V, I32, ctypes.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -78,7 +85,8 @@ _lib = _load()
 EXPORTED = ("teuk_workspace_bytes", "teuk_init_grid", "teuk_set_coefficients", "teuk_set_initial_data",
             "teuk_step_n", "teuk_extract", "teuk_get_state", "teuk_check_finite", "teuk_steps_taken",
             "teuk_get_dt", "teuk_set_tile", "teuk_get_tile", "teuk_suggest_dt", "teuk_free",
-            "teuk_last_error")
+            "teuk_last_error", "teuk_window_bytes", "teuk_step_n_store", "teuk_adjoint_workspace_bytes",
+            "teuk_enable_adjoint", "teuk_adjoint_step_n")
 
 
 def _check(rc):
@@ -185,6 +193,42 @@ def teuk_free(h):
     return _check(_lib.teuk_free(h))
 
 
+def teuk_window_bytes(h, n):
+    nb = _lib.teuk_window_bytes(h, int(n))
+    if nb == 0 and n > 0:
+        raise TeukError(TEUK_E_INVALID_ARG, teuk_last_error())
+    return nb
+
+
+def teuk_step_n_store(h, n, series, window):
+    return _check(_lib.teuk_step_n_store(h, int(n), _dptr(series), _dptr(window)))
+
+
+def teuk_adjoint_workspace_bytes(h):
+    nb = _lib.teuk_adjoint_workspace_bytes(h)
+    if nb == 0:
+        raise TeukError(TEUK_E_INVALID_ARG, teuk_last_error())
+    return nb
+
+
+def teuk_enable_adjoint(h, workspace):
+    return _check(_lib.teuk_enable_adjoint(h, _dptr(workspace), workspace.numel() * workspace.element_size()))
+
+
+def teuk_adjoint_step_n(h, n, lam_phi, lam_pi, dseries, window, flags=0):
+    """Returns this segment's contribution to dL/da; lam_phi, lam_pi are updated in place."""
+    acc = ctypes.c_double(0.0)
+    _check(_lib.teuk_adjoint_step_n(h, int(n), _dptr(lam_phi), _dptr(lam_pi), _dptr(dseries), _dptr(window),
+                                    int(flags), ctypes.byref(acc)))
+    return acc.value
+
+
+def _aligned_bytes(torch, nbytes, device):
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + nbytes]
+
+
 class TeukGrid:
     """One grid on the current CUDA/HIP device: owns its workspace tensor.
 
@@ -202,9 +246,8 @@ class TeukGrid:
         self.nr, self.ntheta = int(nr), int(ntheta)
         self.n_extract = self.params.n_extract
         nbytes = teuk_workspace_bytes(self.params)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        off = (-self.workspace.data_ptr()) % 256
-        self.workspace = self.workspace[off:off + nbytes]
+        self.workspace = _aligned_bytes(torch, nbytes, self.device)
+        self.adjoint_workspace = None
         with torch.cuda.device(self.device):
             self.handle = teuk_init_grid(self.params, self.stream.cuda_stream, self.workspace)
 
@@ -258,6 +301,34 @@ class TeukGrid:
         out = self.torch.empty(n, dtype=self.torch.complex128, device=self.device)
         teuk_extract(self.handle, rstar, theta, out)
         return out
+
+    # ---- adjoint ---------------------------------------------------------
+    def enable_adjoint(self):
+        if self.adjoint_workspace is None:
+            ws = _aligned_bytes(self.torch, teuk_adjoint_workspace_bytes(self.handle), self.device)
+            teuk_enable_adjoint(self.handle, ws)
+            self.adjoint_workspace = ws
+
+    def new_window(self, n):
+        """Device buffer for n stored states."""
+        return _aligned_bytes(self.torch, max(teuk_window_bytes(self.handle, n), 1), self.device)
+
+    def step_store(self, n, window, series=True):
+        out = None
+        if series and self.n_extract > 0 and n > 0:
+            out = self.torch.empty((int(n), self.n_extract), dtype=self.torch.complex128, device=self.device)
+        teuk_step_n_store(self.handle, n, out, window)
+        return out
+
+    def adjoint(self, n, lam_phi, lam_pi, dseries, window, project_initial=False):
+        """Reverse of n stored steps; updates (lam_phi, lam_pi) in place, returns the dL/da part."""
+        self.enable_adjoint()
+        if dseries is not None:
+            dseries = self.torch.as_tensor(dseries, dtype=self.torch.complex128, device=self.device).contiguous()
+            if tuple(dseries.shape) != (int(n), self.n_extract):
+                raise ValueError("dseries must have shape (n, n_extract)")
+        flags = TEUK_ADJ_PROJECT_INITIAL if project_initial else 0
+        return teuk_adjoint_step_n(self.handle, n, lam_phi, lam_pi, dseries, window, flags)
 
     def check_finite(self):
         return teuk_check_finite(self.handle)

@@ -5,7 +5,7 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libteuk.so")
-SOURCES = ["lw_kernels.hip", "teuk_api.cpp"]
+SOURCES = ["lw_kernels.hip", "adjoint_kernels.hip", "teuk_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: no packed FP32 instructions are generated (all arithmetic
@@ -15,13 +15,20 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wal
          "-x", "hip"]
 
 
-def build(extra=()):
-    tmp = LIB + ".tmp"
+def build(extra=(), out=None):
+    lib = out or LIB
+    tmp = lib + ".tmp"
     cmd = [HIPCC, *FLAGS, *extra, *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
     print("+", " ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True, cwd=PKG)
-    os.replace(tmp, LIB)
-    return LIB
+    r = subprocess.run(cmd, cwd=PKG, capture_output=True, text=True)
+    noise = "is not a recognized feature for this target"
+    msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if noise not in l)
+    if msg.strip():
+        print(msg, flush=True)
+    if r.returncode != 0:
+        raise subprocess.CalledProcessError(r.returncode, cmd)
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

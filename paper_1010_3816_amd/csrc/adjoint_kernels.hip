@@ -1,0 +1,419 @@
+// gfx950 adjoint of the Lax-Wendroff step (arXiv:1010.3816, Eqs. (lw1)-(lw2)
+// with the boundary conditions): lambda^m = A^H lambda^{m+1} and the spin
+// gradient contribution Re <lambda^{m+1}, (dA/da) u^m>.
+//
+// The step is complex-linear, so its adjoint for a real loss (gradient
+// convention dL/dRe + i dL/dIm) is the conjugate transpose.  The kernel is
+// the gather form of the transposed step and sweeps the same tiles as the
+// forward kernel (64 r* columns per wavefront, theta rows in order):
+//   * stage 2 transposed at integer points: nu = lambda^{m+1} with the
+//     radial boundary columns zeroed gives the cotangents of hbar and dh;
+//     the theta stencil of S becomes a stencil over the cotangents of rows
+//     t-1, t, t+1 (each row emits an "up", "mid" and "down" part);
+//   * hbar/dh transposed to the half points: lane L adds lane L+1's share;
+//   * stage 1 transposed at half points, again with a row stencil;
+//   * averaging/difference transposed back to integer points: lane L adds
+//     lane L-1's share; plus the direct term nu.
+// The spin gradient needs the forward intermediates of step m (ubar, delta,
+// hbar, dh), which are recomputed from u^m exactly as in the forward
+// kernel, and the a-derivatives of the coefficients, obtained by forward
+// differentiation of their reconstruction from the radial tables and their
+// a-derivative tables (held in LDS for the workgroup's strip).
+#include "device_common.hpp"
+
+namespace teuk {
+namespace {
+
+// d/da of kerr_coef: R, dR are the radial factors and their a-derivatives
+// at the position, s = (1/Sigma, 1/Sigma^2), c the coefficient values.
+__device__ __forceinline__ Coef kerr_coef_da(const Rad& R, const Rad& dR, const Ang& G, Sig s, const Coef& c) {
+    const double dsig2 = fma(-dR.a2d, G.sn2, dR.rho2);
+    const double dinv = -s.inv * s.inv * dsig2;
+    const double disig = -0.5 * s.isig * s.inv * dsig2;
+    Coef d;
+    d.b = fma(dR.rho, s.isig, R.rho * disig);
+    const double T = fma(-R.rb3, G.sn2, R.rb2);
+    const double dT = fma(-dR.rb3, G.sn2, dR.rb2);
+    const double Q = fma(-T, s.inv, R.rb1);
+    const double dQ = dR.rb1 - fma(dT, s.inv, T * dinv);
+    const double bp = s.isig * Q;
+    const double dbp = fma(disig, Q, s.isig * dQ);
+    d.ctr = fma(dR.ctr, s.inv, R.ctr * dinv);
+    const double CI = fma(R.cti1, G.cs, R.cti0);
+    const double dCI = fma(dR.cti1, G.cs, dR.cti0);
+    d.cti = fma(dCI, s.inv, CI * dinv);
+    const double db1 = fma(dR.b1n, s.inv, R.b1n * dinv);
+    d.cre = fma(d.b, bp - c.ctr, c.b * (dbp - d.ctr)) - db1;
+    d.cim = -fma(d.b, c.cti, c.b * d.cti);
+    d.a2s = fma(dR.dl2, s.inv, R.dl2 * dinv);
+    d.a1s = d.a2s * G.cotp;
+    const double V = fma(R.dl2, G.pd, R.v0r);
+    const double dV = fma(dR.dl2, G.pd, dR.v0r);
+    d.v0r = fma(dV, s.inv, V * dinv);
+    d.v0i = fma(dR.v0i, s.inv, R.v0i * dinv);
+    return d;
+}
+
+// LDS copy of a strip's radial tables: [value/derivative][integer/half][field][lane].
+// `o` is a row-dependent offset that is 0 at run time (row & zero): it keeps
+// the reads inside the row loop instead of in (scarce) registers.
+typedef const __attribute__((address_space(3))) double* lds_cptr;
+
+__device__ __forceinline__ Rad rad_from_lds(lds_cptr rs, int o) {
+    Rad R;
+    R.rho = rs[o + R_RHO * kWave];
+    R.rho2 = rs[o + R_RHO2 * kWave];
+    R.a2d = rs[o + R_A2D * kWave];
+    R.rb1 = rs[o + R_RB1 * kWave];
+    R.rb2 = rs[o + R_RB2 * kWave];
+    R.rb3 = rs[o + R_RB3 * kWave];
+    R.ctr = rs[o + R_CTR * kWave];
+    R.cti0 = rs[o + R_CTI0 * kWave];
+    R.cti1 = rs[o + R_CTI1 * kWave];
+    R.b1n = rs[o + R_B1N * kWave];
+    R.dl2 = rs[o + R_DL2 * kWave];
+    R.v0r = rs[o + R_V0R * kWave];
+    R.v0i = rs[o + R_V0I * kWave];
+    return R;
+}
+
+// complex helpers for the transposed operators
+__device__ __forceinline__ cd cadd3(cd a, cd b, cd c) { return {a.re + b.re + c.re, a.im + b.im + c.im}; }
+// (x + i y) * (re + i im)
+__device__ __forceinline__ cd cmul(double x, double y, cd v) {
+    return {fma(x, v.re, -y * v.im), fma(x, v.im, y * v.re)};
+}
+
+constexpr int kAdjRowsInFlight = 2;
+
+// Per-row state carried from the row's arrival to its completion.
+struct AdjRow {
+    // forward recompute of step m at this row
+    cd ubp, ubq, dp, dq;  // half point i+1/2
+    cd hbp, dhp;          // integer point i
+    cd x;                 // stage-1 Pi value at the half, minus its row-(t+1) term
+    double wp;
+    // adjoint
+    cd np, nq;            // nu at (i, t), radial boundary columns zeroed
+    cd lhq;               // cotangent of the stage-1 Pi value at the half
+    cd mid, up, dn;       // stage-2 theta-stencil pieces (to rows t, t+1, t-1)
+    cd ldhp;              // cotangent of dh_Phi at i
+    cd midh, uph, dnh;    // stage-1 theta-stencil pieces
+};
+
+__global__ void __launch_bounds__(256)
+    lw_adjoint_kernel(const double2* __restrict__ nu_in, const double2* __restrict__ u_in,
+                      double2* __restrict__ lam_out, const double* __restrict__ rad,
+                      const double* __restrict__ rad_da, const double* __restrict__ ang,
+                      double* __restrict__ dlda_slots, AdjScalars A) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wpb = blockDim.x / kWave;
+    // a workgroup owns one strip and wpb consecutive theta chunks, so that it
+    // shares one LDS copy of the strip's radial tables
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
+    const int strip = bid % A.n_strips;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int chunk = (bid / A.n_strips) * wpb + wave;
+    const int nr = A.nr, nth = A.nth, P = A.pitch;
+    const int col = strip * kStripCols - 1 + lane;
+    const unsigned long long in = ((col >= 0) && (col < nr)) ? ~0ull : 0ull;
+    const unsigned long long interior = ((col >= 1) && (col < nr - 1)) ? ~0ull : 0ull;
+    const int ci = min(max(col, 0), nr - 1);
+    const int hi = min(max(col, 0), nr - 2);
+
+    __shared__ double rad_s[4 * kNumRad * kWave];
+    for (int f = wave; f < 4 * kNumRad; f += wpb) {
+        const int deriv = f / (2 * kNumRad), kind = (f / kNumRad) % 2, field = f % kNumRad;
+        const double* src = deriv ? rad_da : rad;
+        rad_s[f * kWave + lane] = src[((size_t)field * 2 + kind) * P + (kind == 0 ? ci : hi)];
+    }
+    __syncthreads();
+    if (chunk >= A.n_chunks) return;  // wavefront-uniform
+    lds_cptr rvi = (lds_cptr)(rad_s + 0 * kNumRad * kWave + lane);
+    lds_cptr rvh = (lds_cptr)(rad_s + 1 * kNumRad * kWave + lane);
+    lds_cptr rdi = (lds_cptr)(rad_s + 2 * kNumRad * kWave + lane);
+    lds_cptr rdh = (lds_cptr)(rad_s + 3 * kNumRad * kWave + lane);
+
+    const bool own = (lane >= 1) && (lane <= kWave - 2) && (col < nr);  // columns and halves this tile owns
+    const int j0 = chunk * A.rows;
+    const int j1 = min(j0 + A.rows, nth);
+    const double sg = (double)A.sigma;
+    const int last = (j1 < nth) ? j1 : nth - 1;
+    double acc = 0.0;  // spin-gradient partial sum of this lane
+
+    auto coefs = [&](int t, Coef& ki, Coef& kh, Sig& si, Sig& sh) {
+        const Ang G = load_ang(ang, nth, t);
+        const int o = t & A.zero;
+        const Rad Ri = rad_from_lds(rvi, o), Rh = rad_from_lds(rvh, o);
+        si = kerr_sigma(Ri, G);
+        sh = kerr_sigma(Rh, G);
+        ki = kerr_coef(Ri, G, si);
+        kh = kerr_coef(Rh, G, sh);
+    };
+
+    // Arrival of row t: forward stage-1 pieces of u^m and the same-row part
+    // of the transposed step applied to nu.
+    auto fresh = [&](int t, cd p, cd q, cd np, cd nq, cd ubp_prev) -> AdjRow {
+        AdjRow R;
+        Coef ki, kh;
+        Sig si, sh;
+        coefs(t, ki, kh, si, sh);
+        // forward (as in the step kernel)
+        p = masked(p, in);
+        q = masked(q, in);
+        const cd pr = from_right(p), qr = from_right(q);
+        R.ubp = cavg(p, pr);
+        R.ubq = cavg(q, qr);
+        R.dp = csub(pr, p);
+        R.dq = csub(qr, q);
+        const double tb = A.hdt_dr * kh.b;
+        const cd hp = {fma(-tb, R.dp.re, fma(A.hdt, R.ubq.re, R.ubp.re)),
+                       fma(-tb, R.dp.im, fma(A.hdt, R.ubq.im, R.ubp.im))};
+        const cd hpl = from_left(hp);
+        R.hbp = cavg(hp, hpl);
+        R.dhp = csub(hp, hpl);
+        const cd um = (t == 0) ? cscale(sg, R.ubp) : ubp_prev;
+        const cd dq1 = d_pi(kh, R.dp, R.dq);
+        const cd s1 = s_pi(kh, um, R.ubp, cd{0.0, 0.0}, R.ubq);
+        R.x = {fma(A.hdt, s1.re, fma(-A.hdt_dr, dq1.re, R.ubq.re)),
+               fma(A.hdt, s1.im, fma(-A.hdt_dr, dq1.im, R.ubq.im))};
+        R.wp = A.hdt * (kh.a2s + kh.a1s);
+        // adjoint, stage 2 at (i, t):
+        //   Phi' = Phi + dt hbar_Pi - dt/dr b dh_Phi
+        //   Pi'  = Pi - dt/dr (c dh_Phi - b dh_Pi) + dt S_Pi(hbar)
+        R.np = masked(np, interior);
+        R.nq = masked(nq, interior);
+        const cd sq = cscale(A.dt, R.nq);                                   // cotangent of S_Pi(hbar)
+        R.mid = cmul(-2.0 * ki.a2s - ki.v0r, ki.v0i, sq);                   // (-2 A2 - conj V0) sq
+        R.up = cscale(ki.a2s + ki.a1s, sq);
+        R.dn = cscale(ki.a2s - ki.a1s, sq);
+        const cd lhbq = cadd(cscale(A.dt, R.np), cmul(-ki.ctr, ki.cti, sq));  // + conj(-Ct) sq
+        const cd cnq = cmul(ki.cre, -ki.cim, R.nq);                          // conj(c) nq
+        R.ldhp = {-A.dt_dr * fma(ki.b, R.np.re, cnq.re), -A.dt_dr * fma(ki.b, R.np.im, cnq.im)};
+        const cd ldhq = cscale(A.dt_dr * ki.b, R.nq);
+        // hbar/dh -> half point i+1/2: own (1/2 hbar + dh) + right neighbour's (1/2 hbar - dh)
+        const cd aq = {fma(0.5, lhbq.re, ldhq.re), fma(0.5, lhbq.im, ldhq.im)};
+        const cd bq = {fma(0.5, lhbq.re, -ldhq.re), fma(0.5, lhbq.im, -ldhq.im)};
+        R.lhq = cadd(aq, from_right(bq));
+        // stage 1 at (i+1/2, t): h_Pi = ubar_Pi - dt/2dr (c delta_Phi - b delta_Pi) + dt/2 S_Pi(ubar)
+        const cd tq = cscale(A.hdt, R.lhq);
+        R.midh = cmul(-2.0 * kh.a2s - kh.v0r, kh.v0i, tq);
+        R.uph = cscale(kh.a2s + kh.a1s, tq);
+        R.dnh = cscale(kh.a2s - kh.a1s, tq);
+        return R;
+    };
+
+    // ---- prologue ----------------------------------------------------------
+    AdjRow cur;
+    cd ubp_m, hbp_m, below, below_h;
+    {
+        cd ubp_prev = {0.0, 0.0};
+        if (j0 > 0) {
+            const size_t o = (size_t)(j0 - 1) * P + ci;
+            const AdjRow rm = fresh(j0 - 1, ld(u_in, o), ld(u_in, o + A.plane), ld(nu_in, o), ld(nu_in, o + A.plane),
+                                    ubp_prev);
+            ubp_prev = rm.ubp;
+            ubp_m = rm.ubp;
+            hbp_m = rm.hbp;
+            below = rm.up;
+            below_h = rm.uph;
+        }
+        const size_t o = (size_t)j0 * P + ci;
+        cur = fresh(j0, ld(u_in, o), ld(u_in, o + A.plane), ld(nu_in, o), ld(nu_in, o + A.plane), ubp_prev);
+        if (j0 == 0) {
+            ubp_m = cscale(sg, cur.ubp);
+            hbp_m = cscale(sg, cur.hbp);
+            below = cscale(sg, cur.dn);
+            below_h = cscale(sg, cur.dnh);
+        }
+    }
+    cd bu[kAdjRowsInFlight][2], bn[kAdjRowsInFlight][2];
+#pragma unroll
+    for (int k = 0; k < kAdjRowsInFlight; ++k) {
+        const size_t o = (size_t)min(j0 + 1 + k, last) * P + ci;
+        bu[k][0] = ld(u_in, o);
+        bu[k][1] = ld(u_in, o + A.plane);
+        bn[k][0] = ld(nu_in, o);
+        bn[k][1] = ld(nu_in, o + A.plane);
+    }
+
+    auto finish_row = [&](int t, cd* ru, cd* rn) {
+        AdjRow nxt;
+        cd ubp_p, hbp_p, above, above_h;
+        if (t + 1 < nth) {
+            nxt = fresh(t + 1, ru[0], ru[1], rn[0], rn[1], cur.ubp);
+            ubp_p = nxt.ubp;
+            hbp_p = nxt.hbp;
+            above = nxt.dn;
+            above_h = nxt.dnh;
+        } else {
+            ubp_p = cscale(sg, cur.ubp);
+            hbp_p = cscale(sg, cur.hbp);
+            above = cscale(sg, cur.up);
+            above_h = cscale(sg, cur.uph);
+        }
+        {
+            const size_t o = (size_t)min(t + 1 + kAdjRowsInFlight, last) * P + ci;
+            ru[0] = ld(u_in, o);
+            ru[1] = ld(u_in, o + A.plane);
+            rn[0] = ld(nu_in, o);
+            rn[1] = ld(nu_in, o + A.plane);
+        }
+        Coef ki, kh;
+        Sig si, sh;
+        coefs(t, ki, kh, si, sh);
+
+        // forward stage-1 Pi value at the halves i+1/2, i-1/2 of row t
+        const cd hq = {fma(cur.wp, ubp_p.re, cur.x.re), fma(cur.wp, ubp_p.im, cur.x.im)};
+        const cd hql = from_left(hq);
+        const cd hbq = cavg(hq, hql);
+        const cd dhq = csub(hq, hql);
+
+        // adjoint: hbar_Phi cotangent complete, then stage 1 transposed at the half
+        const cd lhbp = cadd3(cur.mid, below, above);
+        const cd ap = {fma(0.5, lhbp.re, cur.ldhp.re), fma(0.5, lhbp.im, cur.ldhp.im)};
+        const cd bp = {fma(0.5, lhbp.re, -cur.ldhp.re), fma(0.5, lhbp.im, -cur.ldhp.im)};
+        const cd lhp = cadd(ap, from_right(bp));
+        //   h_Phi = ubar_Phi + dt/2 ubar_Pi - dt/2dr b delta_Phi
+        const cd lubp = cadd(lhp, cadd3(cur.midh, below_h, above_h));
+        const cd ctq = cmul(-kh.ctr, kh.cti, cur.lhq);                      // conj(-Ct) lhq
+        const cd lubq = {fma(A.hdt, lhp.re, fma(A.hdt, ctq.re, cur.lhq.re)),
+                         fma(A.hdt, lhp.im, fma(A.hdt, ctq.im, cur.lhq.im))};
+        const cd cq = cmul(kh.cre, -kh.cim, cur.lhq);                        // conj(c) lhq
+        const cd ldp = {-A.hdt_dr * fma(kh.b, lhp.re, cq.re), -A.hdt_dr * fma(kh.b, lhp.im, cq.im)};
+        const cd ldq = cscale(A.hdt_dr * kh.b, cur.lhq);
+        // ubar/delta -> integer points: own (1/2 ubar - delta) + left neighbour's (1/2 ubar + delta)
+        const cd cP = {fma(0.5, lubp.re, ldp.re), fma(0.5, lubp.im, ldp.im)};
+        const cd cQ = {fma(0.5, lubq.re, ldq.re), fma(0.5, lubq.im, ldq.im)};
+        const cd dP = {fma(0.5, lubp.re, -ldp.re), fma(0.5, lubp.im, -ldp.im)};
+        const cd dQ = {fma(0.5, lubq.re, -ldq.re), fma(0.5, lubq.im, -ldq.im)};
+        const cd outp = cadd3(cur.np, dP, from_left(cP));
+        const cd outq = cadd3(cur.nq, dQ, from_left(cQ));
+        if (own) {
+            const size_t o = (size_t)t * P + col;
+            st(lam_out, o, outp);
+            st(lam_out, o + A.plane, outq);
+        }
+
+        // spin gradient: coefficient derivatives against the cotangents of
+        // the stage outputs, at the owned half point and integer point
+        {
+            const Ang G = load_ang(ang, nth, t);
+            const int o = t & A.zero;
+            const Coef dkh = kerr_coef_da(rad_from_lds(rvh, o), rad_from_lds(rdh, o), G, sh, kh);
+            const Coef dki = kerr_coef_da(rad_from_lds(rvi, o), rad_from_lds(rdi, o), G, si, ki);
+            // half: dh_Phi = -dt/2dr db delta_Phi;  dh_Pi = -dt/2dr (dc dP - db dQ) + dt/2 dS(ubar)
+            const cd dhP = cscale(-A.hdt_dr * dkh.b, cur.dp);
+            const cd dd1 = d_pi(dkh, cur.dp, cur.dq);
+            const cd ds1 = s_pi(dkh, ubp_m, cur.ubp, ubp_p, cur.ubq);
+            const cd dhQ = {fma(A.hdt, ds1.re, -A.hdt_dr * dd1.re), fma(A.hdt, ds1.im, -A.hdt_dr * dd1.im)};
+            // integer: dPhi' = -dt/dr db dh_Phi;  dPi' = -dt/dr (dc dhP - db dhQ) + dt dS(hbar)
+            const cd dPp = cscale(-A.dt_dr * dki.b, cur.dhp);
+            const cd dd2 = d_pi(dki, cur.dhp, dhq);
+            const cd ds2 = s_pi(dki, hbp_m, cur.hbp, hbp_p, hbq);
+            const cd dQp = {fma(A.dt, ds2.re, -A.dt_dr * dd2.re), fma(A.dt, ds2.im, -A.dt_dr * dd2.im)};
+            double c = lhp.re * dhP.re + lhp.im * dhP.im;
+            c = fma(cur.lhq.re, dhQ.re, fma(cur.lhq.im, dhQ.im, c));
+            c = fma(cur.np.re, dPp.re, fma(cur.np.im, dPp.im, c));
+            c = fma(cur.nq.re, dQp.re, fma(cur.nq.im, dQp.im, c));
+            if (own) acc += c;
+        }
+
+        below = cur.up;
+        below_h = cur.uph;
+        ubp_m = cur.ubp;
+        hbp_m = cur.hbp;
+        if (t + 1 < nth) cur = nxt;
+    };
+
+    int t0 = j0;
+    for (; t0 + kAdjRowsInFlight <= j1; t0 += kAdjRowsInFlight) {
+#pragma unroll
+        for (int k = 0; k < kAdjRowsInFlight; ++k) finish_row(t0 + k, bu[k], bn[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kAdjRowsInFlight; ++k)
+        if (t0 + k < j1) finish_row(t0 + k, bu[k], bn[k]);
+
+    // fixed-order reduction over the wavefront, one slot per tile
+    for (int off = kWave / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+    if (lane == 0) dlda_slots[(size_t)chunk * A.n_strips + strip] += acc;
+}
+
+// lam_Phi += E^T g for every extraction point, in point order (one thread).
+__global__ void extract_adjoint_kernel(double2* __restrict__ lam, int pitch, const ExtPoint* __restrict__ pts, int n,
+                                       const double2* __restrict__ g) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int e = 0; e < n; ++e) {
+        const ExtPoint E = pts[e];
+        const double2 gv = g[e];
+        for (int r = 0; r < 2; ++r) {
+            const int row = r == 0 ? E.rowa : E.rowb;
+            if (row < 0) continue;
+            const double w = r == 0 ? E.wa : E.wb;
+            double2* a = &lam[(size_t)row * pitch + E.col];
+            double2* b = &lam[(size_t)row * pitch + E.col + 1];
+            const double wa = w * (1.0 - E.wr), wb = w * E.wr;
+            a->x = fma(wa, gv.x, a->x);
+            a->y = fma(wa, gv.y, a->y);
+            b->x = fma(wb, gv.x, b->x);
+            b->y = fma(wb, gv.y, b->y);
+        }
+    }
+}
+
+// Sum of the spin-gradient slots in a fixed order (one workgroup), added to *out.
+__global__ void reduce_slots_kernel(const double* __restrict__ slots, int n, double* __restrict__ out) {
+    __shared__ double part[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += slots[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out += part[0];
+}
+
+// Zero the radial boundary columns of a state.
+__global__ void zero_radial_boundary_kernel(double2* __restrict__ u, int nr, int nth, int pitch) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nth) return;
+    const double2 z = {0.0, 0.0};
+    const size_t plane = (size_t)nth * pitch;
+    const size_t a = (size_t)j * pitch, b = (size_t)j * pitch + nr - 1;
+    u[a] = z;
+    u[a + plane] = z;
+    u[b] = z;
+    u[b + plane] = z;
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const AdjArgs& a, int waves_per_block, hipStream_t s) {
+    const int groups = (a.k.n_chunks + waves_per_block - 1) / waves_per_block;
+    const dim3 block(kWave * waves_per_block), grid(a.k.n_strips * groups);
+    hipLaunchKernelGGL(lw_adjoint_kernel, grid, block, 0, s, a.nu_in, a.u_in, a.lam_out, a.rad, a.rad_da, a.ang,
+                       a.slots, a.k);
+    return hipGetLastError();
+}
+
+hipError_t launch_extract_adjoint(double2* lam, int pitch, const ExtPoint* pts, int n, const double2* g,
+                                  hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(extract_adjoint_kernel, dim3(1), dim3(64), 0, s, lam, pitch, pts, n, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_slots(const double* slots, int n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_slots_kernel, dim3(1), dim3(256), 0, s, slots, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_radial_boundary(double2* u, int nr, int nth, int pitch, hipStream_t s) {
+    hipLaunchKernelGGL(zero_radial_boundary_kernel, dim3((nth + 255) / 256), dim3(256), 0, s, u, nr, nth, pitch);
+    return hipGetLastError();
+}
+
+}  // namespace teuk

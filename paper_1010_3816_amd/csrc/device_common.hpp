@@ -1,0 +1,191 @@
+// Device-side building blocks shared by the forward step kernel
+// (lw_kernels.hip) and the adjoint step kernel (adjoint_kernels.hip):
+// complex helpers, cross-lane moves, the coefficient reconstruction of
+// Eq. (1) from the 1-D radial and angular tables, and the pieces of S and D.
+#pragma once
+
+#include "internal.hpp"
+
+namespace teuk {
+namespace {
+
+struct cd {
+    double re, im;
+};
+
+__device__ __forceinline__ cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cd csub(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cd cscale(double s, cd a) { return {s * a.re, s * a.im}; }
+__device__ __forceinline__ cd cavg(cd a, cd b) { return {0.5 * (a.re + b.re), 0.5 * (a.im + b.im)}; }
+
+// Cross-lane moves: lane L receives the value held by lane L+1 / lane L-1,
+// as two 32-bit DPP wavefront shifts (wave_shl:1 / wave_shr:1).  The edge
+// lanes (63 and 0) receive 0; their results are never stored.
+constexpr int kDppWaveShl1 = 0x130;
+// Rows of input loaded ahead of the row being finished, and the minimum
+// wavefronts per SIMD the register allocation must allow (build-time tuning).
+#ifndef TEUK_ROWS_IN_FLIGHT
+#define TEUK_ROWS_IN_FLIGHT 3
+#endif
+#ifndef TEUK_WAVES_PER_SIMD
+#define TEUK_WAVES_PER_SIMD 2
+#endif
+constexpr int kRowsInFlight = TEUK_ROWS_IN_FLIGHT;
+constexpr int kDppWaveShr1 = 0x138;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_right(double v) { return dpp_move<kDppWaveShl1>(v); }
+__device__ __forceinline__ double from_left(double v) { return dpp_move<kDppWaveShr1>(v); }
+__device__ __forceinline__ cd from_right(cd v) { return {from_right(v.re), from_right(v.im)}; }
+__device__ __forceinline__ cd from_left(cd v) { return {from_left(v.re), from_left(v.im)}; }
+
+// The coefficients of the first-order system at one (position, row), with
+// the difference-operator scalings folded in: a2s = A2/dth^2, a1s = A1/(2 dth).
+struct Coef {
+    double b, cre, cim, ctr, cti, a2s, a1s, v0r, v0i;
+};
+
+struct Rad {
+    double rho, rho2, a2d, rb1, rb2, rb3, ctr, cti0, cti1, b1n, dl2, v0r, v0i;
+};
+
+struct Ang {
+    double sn2, cs, cotp, pd;
+};
+
+__device__ __forceinline__ Rad load_rad(const double* __restrict__ rad, int pitch, int kind, int pos) {
+    auto f = [&](int field) { return rad[((size_t)field * 2 + kind) * pitch + pos]; };
+    Rad R;
+    R.rho = f(R_RHO);
+    R.rho2 = f(R_RHO2);
+    R.a2d = f(R_A2D);
+    R.rb1 = f(R_RB1);
+    R.rb2 = f(R_RB2);
+    R.rb3 = f(R_RB3);
+    R.ctr = f(R_CTR);
+    R.cti0 = f(R_CTI0);
+    R.cti1 = f(R_CTI1);
+    R.b1n = f(R_B1N);
+    R.dl2 = f(R_DL2);
+    R.v0r = f(R_V0R);
+    R.v0i = f(R_V0I);
+    return R;
+}
+
+__device__ __forceinline__ Ang load_ang(const double* ang, int nth, int j) {
+    Ang G;
+    G.sn2 = ang[A_SN2 * nth + j];
+    G.cs = ang[A_CS * nth + j];
+    G.cotp = ang[A_COTP * nth + j];
+    G.pd = ang[A_PD * nth + j];
+    return G;
+}
+
+// 1/Sigma and 1/Sigma^2 at one (position, row).
+struct Sig {
+    double isig, inv;
+};
+
+__device__ __forceinline__ Sig kerr_sigma(const Rad& R, const Ang& G) {
+    const double sig2 = fma(-R.a2d, G.sn2, R.rho2);
+    const double inv = 1.0 / sig2;
+    return {sqrt(inv), inv};
+}
+
+// Eq. (1) coefficients from the factored tables (see RadField / AngField).
+__device__ __forceinline__ Coef kerr_coef(const Rad& R, const Ang& G, Sig s) {
+    Coef c;
+    c.b = R.rho * s.isig;
+    const double bp = s.isig * fma(-fma(-R.rb3, G.sn2, R.rb2), s.inv, R.rb1);
+    c.ctr = R.ctr * s.inv;
+    c.cti = fma(R.cti1, G.cs, R.cti0) * s.inv;
+    const double b1 = R.b1n * s.inv;
+    c.cre = fma(c.b, bp - c.ctr, -b1);
+    c.cim = -c.b * c.cti;
+    c.a2s = R.dl2 * s.inv;
+    c.a1s = c.a2s * G.cotp;
+    c.v0r = fma(R.dl2, G.pd, R.v0r) * s.inv;
+    c.v0i = R.v0i * s.inv;
+    return c;
+}
+
+__device__ __forceinline__ Coef user_coef(const double* u, int nth, int pitch, int j, int pos, double inv_dth2,
+                                          double inv_2dth) {
+    auto f = [&](int k) { return u[((size_t)k * nth + j) * pitch + pos]; };
+    Coef c;
+    c.b = f(U_B);
+    c.cre = f(U_CRE);
+    c.cim = f(U_CIM);
+    c.ctr = f(U_CTRE);
+    c.cti = f(U_CTIM);
+    c.a2s = f(U_A2) * inv_dth2;
+    c.a1s = f(U_A1) * inv_2dth;
+    c.v0r = f(U_V0RE);
+    c.v0i = f(U_V0IM);
+    return c;
+}
+
+// Pi row of S:  -Ct q + A2 (f_{j+1} - 2 f_j + f_{j-1})/dth^2
+//               + A1 (f_{j+1} - f_{j-1})/(2 dth) - V0 f_j
+__device__ __forceinline__ cd s_pi(const Coef& k, cd fm, cd f0, cd fp, cd q) {
+    const double lr = (fp.re + fm.re) - 2.0 * f0.re;
+    const double li = (fp.im + fm.im) - 2.0 * f0.im;
+    const double gr = fp.re - fm.re;
+    const double gi = fp.im - fm.im;
+    double sr = fma(k.a2s, lr, k.a1s * gr);
+    double si = fma(k.a2s, li, k.a1s * gi);
+    sr -= fma(k.ctr, q.re, -k.cti * q.im);
+    si -= fma(k.ctr, q.im, k.cti * q.re);
+    sr -= fma(k.v0r, f0.re, -k.v0i * f0.im);
+    si -= fma(k.v0r, f0.im, k.v0i * f0.re);
+    return {sr, si};
+}
+
+// D applied to (dP, dQ), Pi row:  c dP - b dQ.
+__device__ __forceinline__ cd d_pi(const Coef& k, cd dP, cd dQ) {
+    return {fma(k.cre, dP.re, fma(-k.cim, dP.im, -k.b * dQ.re)),
+            fma(k.cre, dP.im, fma(k.cim, dP.re, -k.b * dQ.im))};
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; map them so that
+// each XCD (own L2) receives a contiguous range of tiles, i.e. neighbouring
+// strips whose halo columns overlap.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    constexpr int X = 8;
+    const int x = b % X, idx = b / X, per = nb / X, rem = nb % X;
+    return x * per + min(x, rem) + idx;
+}
+
+// Loads always read a valid (clamped) address; where the column lies
+// outside the grid the value is zeroed by a bit mask at its point of use, so
+// the load itself is unconditional and stays in flight until it is needed.
+__device__ __forceinline__ cd ld(const double2* __restrict__ p, size_t o) {
+    const double2 v = p[o];
+    return {v.x, v.y};
+}
+
+__device__ __forceinline__ cd masked(cd v, unsigned long long mask) {
+    return {__longlong_as_double(__double_as_longlong(v.re) & mask),
+            __longlong_as_double(__double_as_longlong(v.im) & mask)};
+}
+
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+// Streaming store of one complex value (16 B, one dwordx4 per lane): the
+// new state is not read again by this launch.
+__device__ __forceinline__ void st(double2* p, size_t o, cd v) {
+    v2d w;
+    w.x = v.re;
+    w.y = v.im;
+    __builtin_nontemporal_store(w, reinterpret_cast<v2d*>(p + o));
+}
+
+// All pointers are distinct allocations (restrict): the uniform reads of
+// the angular tables and extraction descriptors become scalar loads.
+}  // namespace
+}  // namespace teuk

@@ -58,33 +58,56 @@ struct ExtPoint {
 // Scalar launch parameters of the step kernel (passed by value).
 struct StepScalars {
     int32_t nr, nth, pitch, sigma;
-    int32_t rows, n_strips, n_tiles, n_ext;
+    int32_t rows, n_strips, n_chunks, n_ext;
+    int64_t plane;              // nth * pitch: offset of the Pi plane in a state
     double dt, hdt, dt_dr, hdt_dr;
     double inv_dth2, inv_2dth;  // USER mode scalings
 };
 
 struct StepArgs {
-    const double2* phi_in;   // [nth][pitch]
-    const double2* pi_in;
-    double2* phi_out;
-    double2* pi_out;
+    const double2* u_in;     // state: [Phi, Pi][nth][pitch]
+    double2* u_out;
     const double* rad;       // [kNumRad][2][pitch] (KERR)
     const double* ang;       // [kNumAng][nth]      (KERR)
     const double* uci;       // [kNumUser][nth][pitch] (USER, integer positions)
     const double* uch;       // [kNumUser][nth][pitch] (USER, half positions)
     const ExtPoint* ext;     // [n_ext]
     double2* series;         // n_ext samples of the input Phi, or nullptr
+    double2* win;            // copy of the input state (same layout), or nullptr
     StepScalars k;
 };
 
-// Launchers (lw_kernels.hip).  All return the hipError_t of the launch.
+// Scalar launch parameters of the adjoint kernel.
+struct AdjScalars {
+    int32_t nr, nth, pitch, sigma;
+    int32_t rows, n_strips, n_chunks, zero;  // zero: always 0 (an opaque row offset of LDS reads)
+    int64_t plane;                           // nth * pitch: offset of the Pi plane in a state
+    double dt, hdt, dt_dr, hdt_dr;
+};
+
+struct AdjArgs {
+    const double2* nu_in;    // lambda^{m+1}, [Phi, Pi][nth][pitch]
+    const double2* u_in;     // u^m
+    double2* lam_out;        // lambda^m
+    const double* rad;       // [kNumRad][2][pitch]
+    const double* rad_da;    // d/da of rad
+    const double* ang;       // [kNumAng][nth]
+    double* slots;           // [n_strips * n_chunks] spin-gradient partial sums (accumulated)
+    AdjScalars k;
+};
+
+// Launchers (lw_kernels.hip, adjoint_kernels.hip).  All return the
+// hipError_t of the launch.
 hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s);
-hipError_t launch_import(const double2* src, double2* dst, int nr, int nth, int pitch, hipStream_t s);
-hipError_t launch_export(const double2* src, double2* dst, int nr, int nth, int pitch, hipStream_t s);
-hipError_t launch_extract(const double2* phi, int pitch, int sigma, const ExtPoint* pts, int n, double2* out,
-                          hipStream_t s);
-hipError_t launch_nonfinite(const double2* phi, const double2* pi, int nr, int nth, int pitch, int* flag,
-                            hipStream_t s);
+hipError_t launch_import(const double2* src, double2* u, int f, int nr, int nth, int pitch, hipStream_t s);
+hipError_t launch_export(const double2* u, double2* dst, int f, int nr, int nth, int pitch, hipStream_t s);
+hipError_t launch_extract(const double2* u, int pitch, const ExtPoint* pts, int n, double2* out, hipStream_t s);
+hipError_t launch_nonfinite(const double2* u, int nr, int nth, int pitch, int* flag, hipStream_t s);
+hipError_t launch_adjoint(const AdjArgs& a, int waves_per_block, hipStream_t s);
+hipError_t launch_extract_adjoint(double2* lam, int pitch, const ExtPoint* pts, int n, const double2* g,
+                                  hipStream_t s);
+hipError_t launch_reduce_slots(const double* slots, int n, double* out, hipStream_t s);
+hipError_t launch_zero_radial_boundary(double2* u, int nr, int nth, int pitch, hipStream_t s);
 hipError_t launch_pitch_copy(const double* src, double* dst, int rows, int cols, int pitch, hipStream_t s);
 
 }  // namespace teuk

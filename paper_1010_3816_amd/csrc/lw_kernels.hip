@@ -24,192 +24,34 @@
 // Extraction is fused: the wavefront whose tile contains the bilinear
 // stencil of an extraction point accumulates Phi of the INPUT state while
 // it streams the rows, and writes the sample at the end of its sweep.
-#include "internal.hpp"
+#include "device_common.hpp"
 
 namespace teuk {
 namespace {
-
-struct cd {
-    double re, im;
+// Row-sweep of one tile.  Per row t the sweep keeps:
+//   p, q      Phi, Pi at (i, t)
+//   ubp       stage-1 average of Phi at the half point i+1/2
+//   hbp, dhp  mean and difference of the stage-1 Phi values at i-1/2, i+1/2
+//   x, wp     the stage-1 Pi value at (i+1/2, t) except for its row-(t+1)
+//             term: h_Pi(t) = x + wp * ubp(t+1); the theta stencil is the only
+//             part of Eq. (lw1) that needs the next row.
+struct Row {
+    cd p, q, ubp, hbp, dhp, x;
+    double wp;
 };
 
-__device__ __forceinline__ cd csub(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
-__device__ __forceinline__ cd cscale(double s, cd a) { return {s * a.re, s * a.im}; }
-__device__ __forceinline__ cd cavg(cd a, cd b) { return {0.5 * (a.re + b.re), 0.5 * (a.im + b.im)}; }
-
-// Cross-lane moves: lane L receives the value held by lane L+1 / lane L-1,
-// as two 32-bit DPP wavefront shifts (wave_shl:1 / wave_shr:1).  The edge
-// lanes (63 and 0) receive 0; their results are never stored.
-constexpr int kDppWaveShl1 = 0x130;
-constexpr int kRowsInFlight = 3;  // rows of input loaded ahead of the row being finished
-constexpr int kDppWaveShr1 = 0x138;
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double from_right(double v) { return dpp_move<kDppWaveShl1>(v); }
-__device__ __forceinline__ double from_left(double v) { return dpp_move<kDppWaveShr1>(v); }
-__device__ __forceinline__ cd from_right(cd v) { return {from_right(v.re), from_right(v.im)}; }
-__device__ __forceinline__ cd from_left(cd v) { return {from_left(v.re), from_left(v.im)}; }
-
-// The coefficients of the first-order system at one (position, row), with
-// the difference-operator scalings folded in: a2s = A2/dth^2, a1s = A1/(2 dth).
-struct Coef {
-    double b, cre, cim, ctr, cti, a2s, a1s, v0r, v0i;
-};
-
-struct Rad {
-    double rho, rho2, a2d, rb1, rb2, rb3, ctr, cti0, cti1, b1n, dl2, v0r, v0i;
-};
-
-struct Ang {
-    double sn2, cs, cotp, pd;
-};
-
-__device__ __forceinline__ Rad load_rad(const double* rad, int pitch, int kind, int pos) {
-    auto f = [&](int field) { return rad[((size_t)field * 2 + kind) * pitch + pos]; };
-    Rad R;
-    R.rho = f(R_RHO);
-    R.rho2 = f(R_RHO2);
-    R.a2d = f(R_A2D);
-    R.rb1 = f(R_RB1);
-    R.rb2 = f(R_RB2);
-    R.rb3 = f(R_RB3);
-    R.ctr = f(R_CTR);
-    R.cti0 = f(R_CTI0);
-    R.cti1 = f(R_CTI1);
-    R.b1n = f(R_B1N);
-    R.dl2 = f(R_DL2);
-    R.v0r = f(R_V0R);
-    R.v0i = f(R_V0I);
-    return R;
-}
-
-__device__ __forceinline__ Ang load_ang(const double* ang, int nth, int j) {
-    Ang G;
-    G.sn2 = ang[A_SN2 * nth + j];
-    G.cs = ang[A_CS * nth + j];
-    G.cotp = ang[A_COTP * nth + j];
-    G.pd = ang[A_PD * nth + j];
-    return G;
-}
-
-// 1/Sigma and 1/Sigma^2 at one (position, row).
-struct Sig {
-    double isig, inv;
-};
-
-__device__ __forceinline__ Sig kerr_sigma(const Rad& R, const Ang& G) {
-    const double sig2 = fma(-R.a2d, G.sn2, R.rho2);
-    const double inv = 1.0 / sig2;
-    return {sqrt(inv), inv};
-}
-
-// Eq. (1) coefficients from the factored tables (see RadField / AngField).
-__device__ __forceinline__ Coef kerr_coef(const Rad& R, const Ang& G, Sig s) {
-    Coef c;
-    c.b = R.rho * s.isig;
-    const double bp = s.isig * fma(-fma(-R.rb3, G.sn2, R.rb2), s.inv, R.rb1);
-    c.ctr = R.ctr * s.inv;
-    c.cti = fma(R.cti1, G.cs, R.cti0) * s.inv;
-    const double b1 = R.b1n * s.inv;
-    c.cre = fma(c.b, bp - c.ctr, -b1);
-    c.cim = -c.b * c.cti;
-    c.a2s = R.dl2 * s.inv;
-    c.a1s = c.a2s * G.cotp;
-    c.v0r = fma(R.dl2, G.pd, R.v0r) * s.inv;
-    c.v0i = R.v0i * s.inv;
-    return c;
-}
-
-__device__ __forceinline__ Coef user_coef(const double* u, int nth, int pitch, int j, int pos, double inv_dth2,
-                                          double inv_2dth) {
-    auto f = [&](int k) { return u[((size_t)k * nth + j) * pitch + pos]; };
-    Coef c;
-    c.b = f(U_B);
-    c.cre = f(U_CRE);
-    c.cim = f(U_CIM);
-    c.ctr = f(U_CTRE);
-    c.cti = f(U_CTIM);
-    c.a2s = f(U_A2) * inv_dth2;
-    c.a1s = f(U_A1) * inv_2dth;
-    c.v0r = f(U_V0RE);
-    c.v0i = f(U_V0IM);
-    return c;
-}
-
-// Pi row of S:  -Ct q + A2 (f_{j+1} - 2 f_j + f_{j-1})/dth^2
-//               + A1 (f_{j+1} - f_{j-1})/(2 dth) - V0 f_j
-__device__ __forceinline__ cd s_pi(const Coef& k, cd fm, cd f0, cd fp, cd q) {
-    const double lr = (fp.re + fm.re) - 2.0 * f0.re;
-    const double li = (fp.im + fm.im) - 2.0 * f0.im;
-    const double gr = fp.re - fm.re;
-    const double gi = fp.im - fm.im;
-    double sr = fma(k.a2s, lr, k.a1s * gr);
-    double si = fma(k.a2s, li, k.a1s * gi);
-    sr -= fma(k.ctr, q.re, -k.cti * q.im);
-    si -= fma(k.ctr, q.im, k.cti * q.re);
-    sr -= fma(k.v0r, f0.re, -k.v0i * f0.im);
-    si -= fma(k.v0r, f0.im, k.v0i * f0.re);
-    return {sr, si};
-}
-
-// D applied to (dP, dQ), Pi row:  c dP - b dQ.
-__device__ __forceinline__ cd d_pi(const Coef& k, cd dP, cd dQ) {
-    return {fma(k.cre, dP.re, fma(-k.cim, dP.im, -k.b * dQ.re)),
-            fma(k.cre, dP.im, fma(k.cim, dP.re, -k.b * dQ.im))};
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs; map them so that
-// each XCD (own L2) receives a contiguous range of tiles, i.e. neighbouring
-// strips whose halo columns overlap.
-__device__ __forceinline__ int xcd_block(int b, int nb) {
-    constexpr int X = 8;
-    const int x = b % X, idx = b / X, per = nb / X, rem = nb % X;
-    return x * per + min(x, rem) + idx;
-}
-
-// Loads always read a valid (clamped) address; where the column lies
-// outside the grid the value is zeroed by a bit mask at its point of use, so
-// the load itself is unconditional and stays in flight until it is needed.
-__device__ __forceinline__ cd ld(const double2* __restrict__ p, size_t o) {
-    const double2 v = p[o];
-    return {v.x, v.y};
-}
-
-__device__ __forceinline__ cd masked(cd v, unsigned long long mask) {
-    return {__longlong_as_double(__double_as_longlong(v.re) & mask),
-            __longlong_as_double(__double_as_longlong(v.im) & mask)};
-}
-
-typedef double v2d __attribute__((ext_vector_type(2)));
-
-// Streaming store of one complex value (16 B, one dwordx4 per lane): the
-// new state is not read again by this launch.
-__device__ __forceinline__ void st(double2* p, size_t o, cd v) {
-    v2d w;
-    w.x = v.re;
-    w.y = v.im;
-    __builtin_nontemporal_store(w, reinterpret_cast<v2d*>(p + o));
-}
-
-// All pointers are distinct allocations (restrict): the uniform reads of
-// the angular tables and extraction descriptors become scalar loads.
 template <bool KERR>
-__global__ void __launch_bounds__(512)
-    lw_step_kernel(const double2* __restrict__ phi_in, const double2* __restrict__ pi_in,
-                   double2* __restrict__ phi_out, double2* __restrict__ pi_out, const double* __restrict__ rad,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_WAVES_PER_SIMD, 8)))
+    lw_step_kernel(const double2* __restrict__ u_in, double2* __restrict__ u_out, const double* __restrict__ rad,
                    const double* __restrict__ ang, const double* __restrict__ uci, const double* __restrict__ uch,
-                   const ExtPoint* __restrict__ ext, double2* __restrict__ series, StepScalars A) {
+                   const ExtPoint* __restrict__ ext, double2* __restrict__ series, double2* __restrict__ win,
+                   StepScalars A) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
-    // wavefront-uniform tile index, made explicit so that everything derived
-    // from it (rows, table reads, loop control) is scalar
+    // Tiles are numbered strip-fastest, so the wavefronts of a workgroup take
+    // neighbouring strips of one theta chunk (their halo columns overlap);
+    // workgroups are remapped so that each XCD receives a contiguous range.
     const int tile = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * wpb + (threadIdx.x / kWave));
-    if (tile >= A.n_tiles) return;
     const int strip = tile % A.n_strips;
     const int chunk = tile / A.n_strips;
     const int nr = A.nr, nth = A.nth, P = A.pitch;
@@ -217,6 +59,15 @@ __global__ void __launch_bounds__(512)
     const unsigned long long in = ((col >= 0) && (col < nr)) ? ~0ull : 0ull;
     const int ci = min(max(col, 0), nr - 1);  // clamped integer column
     const int hi = min(max(col, 0), nr - 2);  // clamped half point col + 1/2
+
+    if (chunk >= A.n_chunks) return;  // wavefront-uniform (tiles beyond the last)
+    // radial factors of this lane's column and half point, held in registers
+    Rad Ri, Rh;
+    if constexpr (KERR) {
+        Ri = load_rad(rad, P, 0, ci);
+        Rh = load_rad(rad, P, 1, hi);
+    }
+
     const bool store_ok = (lane >= 1) && (lane <= kWave - 2) && (col < nr);
     const bool boundary = (col == 0) || (col == nr - 1);
     const int j0 = chunk * A.rows;
@@ -224,41 +75,48 @@ __global__ void __launch_bounds__(512)
     const double sg = (double)A.sigma;
     const int last = (j1 < nth) ? j1 : nth - 1;  // last row this tile reads
 
-    Rad Ri, Rh;
-    if constexpr (KERR) {
-        Ri = load_rad(rad, P, 0, ci);
-        Rh = load_rad(rad, P, 1, hi);
-    }
-
-    // extraction point owned by this lane, if any
-    int my_e = -1, my_ra = -1, my_rb = -1;
-    double my_wr = 0.0, my_wa = 0.0, my_wb = 0.0;
-    cd acc = {0.0, 0.0};
+    // the (at most one) extraction point of this tile, in scalar registers
+    int e_id = -1, e_lane = 0, e_ra = -1, e_rb = -1;
+    double e_wr = 0.0, e_wa = 0.0, e_wb = 0.0;
     for (int e = 0; e < A.n_ext; ++e) {
         const ExtPoint E = ext[e];
         const int es = E.col / kStripCols;
-        if (es == strip && E.rowa / A.rows == chunk && lane == E.col - es * kStripCols + 1) {
-            my_e = e;
-            my_ra = E.rowa;
-            my_rb = E.rowb;
-            my_wr = E.wr;
-            my_wa = E.wa;
-            my_wb = E.wb;
+        if (es == strip && E.rowa / A.rows == chunk) {
+            e_id = e;
+            e_lane = E.col - es * kStripCols + 1;
+            e_ra = E.rowa;
+            e_rb = E.rowb;
+            e_wr = E.wr;
+            e_wa = E.wa;
+            e_wb = E.wb;
         }
     }
+    cd acc = {0.0, 0.0};
 
-    // ---- per-row stage-1 pieces -------------------------------------------
-    // fresh(t): from u(t) of this lane and of lane L+1:
-    //   ubar (Phi, Pi), delta (Phi, Pi) at the half point to the right,
-    //   h_Phi there, and (via lane L-1) hbar_Phi, dh_Phi at this column.
-    struct Row {
-        cd p, q;          // u(t) at this column
-        cd ubp, ubq, dp, dq;
-        cd hbp, dhp;      // average / difference of h_Phi of the two neighbouring halves
-        Sig sh;           // 1/Sigma at (half, t)
+    auto half_coef = [&](int t, double& b) -> Coef {
+        Coef k;
+        if constexpr (KERR) {
+            const Ang G = load_ang(ang, nth, t);
+            k = kerr_coef(Rh, G, kerr_sigma(Rh, G));
+        } else {
+            k = user_coef(uch, nth, P, t, hi, A.inv_dth2, A.inv_2dth);
+        }
+        b = k.b;
+        return k;
+    };
+    auto half_b = [&](int t) -> double {
+        if constexpr (KERR) {
+            const Ang G = load_ang(ang, nth, t);
+            return Rh.rho * kerr_sigma(Rh, G).isig;
+        } else {
+            return uch[((size_t)U_B * nth + t) * P + hi];
+        }
     };
 
-    auto fresh = [&](int t, cd p, cd q) -> Row {
+    // Stage-1 pieces of row t from u(t) of this lane and of lane L+1.
+    // FULL: also the Pi part x, wp (needs ubp(t-1): `ubp_prev`, or the ghost
+    // row when t == 0).  Halo rows only need ubp and hbp.
+    auto fresh = [&](int t, cd p, cd q, cd ubp_prev, bool full) -> Row {
         p = masked(p, in);
         q = masked(q, in);
         Row R;
@@ -266,51 +124,55 @@ __global__ void __launch_bounds__(512)
         R.q = q;
         const cd pr = from_right(p), qr = from_right(q);
         R.ubp = cavg(p, pr);
-        R.ubq = cavg(q, qr);
-        R.dp = csub(pr, p);
-        R.dq = csub(qr, q);
+        const cd ubq = cavg(q, qr);
+        const cd dp = csub(pr, p);
         double bh;
-        if constexpr (KERR) {
-            const Ang G = load_ang(ang, nth, t);
-            R.sh = kerr_sigma(Rh, G);
-            bh = Rh.rho * R.sh.isig;
-        } else {
-            R.sh = {0.0, 0.0};
-            bh = uch[((size_t)U_B * nth + t) * P + hi];
-        }
+        Coef kh;
+        if (full)
+            kh = half_coef(t, bh);
+        else
+            bh = half_b(t);
         // h_Phi = ubar_Phi - dt/2 (b delta_Phi / dr - ubar_Pi)
         const double tb = A.hdt_dr * bh;
-        const cd hp = {fma(-tb, R.dp.re, fma(A.hdt, R.ubq.re, R.ubp.re)),
-                       fma(-tb, R.dp.im, fma(A.hdt, R.ubq.im, R.ubp.im))};
+        const cd hp = {fma(-tb, dp.re, fma(A.hdt, ubq.re, R.ubp.re)), fma(-tb, dp.im, fma(A.hdt, ubq.im, R.ubp.im))};
         const cd hpl = from_left(hp);
         R.hbp = cavg(hp, hpl);
         R.dhp = csub(hp, hpl);
-        if (my_e >= 0) {
-            const double w = (t == my_ra ? my_wa : 0.0) + (t == my_rb ? my_wb : 0.0);
-            const cd v = {fma(my_wr, pr.re - p.re, p.re), fma(my_wr, pr.im - p.im, p.im)};
-            acc.re = fma(w, v.re, acc.re);
-            acc.im = fma(w, v.im, acc.im);
+        if (full) {
+            // h_Pi = ubar_Pi - dt/2 [ (c delta_Phi - b delta_Pi)/dr - S_Pi(ubar) ], with
+            // S_Pi(ubar) = -Ct ubar_Pi + A2 lap + A1 grad - V0 ubar_Phi split as
+            // (everything but the row-(t+1) term) + (A2/dth^2 + A1/(2 dth)) ubar_Phi(t+1)
+            const cd dq = csub(qr, q);
+            const cd um = (t == 0) ? cscale(sg, R.ubp) : ubp_prev;
+            const cd dq1 = d_pi(kh, dp, dq);
+            const cd s1 = s_pi(kh, um, R.ubp, cd{0.0, 0.0}, ubq);
+            R.x = {fma(A.hdt, s1.re, fma(-A.hdt_dr, dq1.re, ubq.re)), fma(A.hdt, s1.im, fma(-A.hdt_dr, dq1.im, ubq.im))};
+            R.wp = A.hdt * (kh.a2s + kh.a1s);
+        }
+        if (t == e_ra || t == e_rb) {  // wavefront-uniform
+            const double w = (t == e_ra) ? e_wa : e_wb;
+            acc.re = fma(w, fma(e_wr, pr.re - p.re, p.re), acc.re);
+            acc.im = fma(w, fma(e_wr, pr.im - p.im, p.im), acc.im);
         }
         return R;
     };
 
-    // ---- prologue ----------------------------------------------------------
-    cd ubp_m, hbp_m;  // averaged Phi fields at row t-1
+    // ---- prologue: rows j0-1 (halo or ghost) and j0 ----------------------
+    cd hbp_m;  // hbar_Phi at row t-1
     Row cur;
     {
+        cd ubp_m = {0.0, 0.0};
         if (j0 > 0) {
             const size_t o = (size_t)(j0 - 1) * P + ci;
-            const Row rm = fresh(j0 - 1, ld(phi_in, o), ld(pi_in, o));
+            const Row rm = fresh(j0 - 1, ld(u_in, o), ld(u_in, o + A.plane), ubp_m, false);
             ubp_m = rm.ubp;
             hbp_m = rm.hbp;
         }
         const size_t o = (size_t)j0 * P + ci;
-        cur = fresh(j0, ld(phi_in, o), ld(pi_in, o));
-        if (j0 == 0) {
-            ubp_m = cscale(sg, cur.ubp);
-            hbp_m = cscale(sg, cur.hbp);
-        }
+        cur = fresh(j0, ld(u_in, o), ld(u_in, o + A.plane), ubp_m, true);
+        if (j0 == 0) hbp_m = cscale(sg, cur.hbp);
     }
+
     // Ring of D row buffers: buffer u holds row t+1 when row t (t - j0 = u
     // mod D) is finished, and is refilled with row t+1+D right after.  The
     // loop is unrolled by D so that loaded registers are never copied (a copy
@@ -319,8 +181,8 @@ __global__ void __launch_bounds__(512)
 #pragma unroll
     for (int u = 0; u < kRowsInFlight; ++u) {
         const size_t o = (size_t)min(j0 + 1 + u, last) * P + ci;
-        bp[u] = ld(phi_in, o);
-        bq[u] = ld(pi_in, o);
+        bp[u] = ld(u_in, o);
+        bq[u] = ld(u_in, o + A.plane);
     }
 
     auto finish_row = [&](int t, cd& rp, cd& rq) {
@@ -328,7 +190,7 @@ __global__ void __launch_bounds__(512)
         Row nxt;
         cd ubp_p, hbp_p;
         if (t + 1 < nth) {
-            nxt = fresh(t + 1, rp, rq);
+            nxt = fresh(t + 1, rp, rq, cur.ubp, true);
             ubp_p = nxt.ubp;
             hbp_p = nxt.hbp;
         } else {
@@ -337,25 +199,12 @@ __global__ void __launch_bounds__(512)
         }
         {
             const size_t o = (size_t)min(t + 1 + kRowsInFlight, last) * P + ci;
-            rp = ld(phi_in, o);
-            rq = ld(pi_in, o);
+            rp = ld(u_in, o);
+            rq = ld(u_in, o + A.plane);
         }
 
-        // stage 1, Pi component at (half, t)
-        Coef kh, ki;
-        if constexpr (KERR) {
-            const Ang G = load_ang(ang, nth, t);
-            kh = kerr_coef(Rh, G, cur.sh);
-            ki = kerr_coef(Ri, G, kerr_sigma(Ri, G));
-        } else {
-            kh = user_coef(uch, nth, P, t, hi, A.inv_dth2, A.inv_2dth);
-            ki = user_coef(uci, nth, P, t, ci, A.inv_dth2, A.inv_2dth);
-        }
-        // h_Pi = ubar_Pi - dt/2 [ (c delta_Phi - b delta_Pi)/dr - S_Pi(ubar) ]
-        const cd dq1 = d_pi(kh, cur.dp, cur.dq);
-        const cd s1 = s_pi(kh, ubp_m, cur.ubp, ubp_p, cur.ubq);
-        const cd hq = {fma(A.hdt, s1.re, fma(-A.hdt_dr, dq1.re, cur.ubq.re)),
-                       fma(A.hdt, s1.im, fma(-A.hdt_dr, dq1.im, cur.ubq.im))};
+        // stage 1, Pi component at (i+1/2, t), and its neighbour at i-1/2
+        const cd hq = {fma(cur.wp, ubp_p.re, cur.x.re), fma(cur.wp, ubp_p.im, cur.x.im)};
         const cd hql = from_left(hq);
         const cd hbq = cavg(hq, hql);
         const cd dhq = csub(hq, hql);
@@ -363,24 +212,32 @@ __global__ void __launch_bounds__(512)
         // stage 2 at (i, t)
         //   Phi' = Phi - dt [ b dh_Phi / dr - hbar_Pi ]
         //   Pi'  = Pi  - dt [ (c dh_Phi - b dh_Pi)/dr - S_Pi(hbar) ]
+        Coef ki;
+        if constexpr (KERR) {
+            const Ang G = load_ang(ang, nth, t);
+            ki = kerr_coef(Ri, G, kerr_sigma(Ri, G));
+        } else {
+            ki = user_coef(uci, nth, P, t, ci, A.inv_dth2, A.inv_2dth);
+        }
         const double tb = A.dt_dr * ki.b;
-        cd np = {fma(-tb, cur.dhp.re, fma(A.dt, hbq.re, cur.p.re)),
-                 fma(-tb, cur.dhp.im, fma(A.dt, hbq.im, cur.p.im))};
+        cd np = {fma(-tb, cur.dhp.re, fma(A.dt, hbq.re, cur.p.re)), fma(-tb, cur.dhp.im, fma(A.dt, hbq.im, cur.p.im))};
         const cd dq2 = d_pi(ki, cur.dhp, dhq);
         const cd s2 = s_pi(ki, hbp_m, cur.hbp, hbp_p, hbq);
-        cd nq = {fma(A.dt, s2.re, fma(-A.dt_dr, dq2.re, cur.q.re)),
-                 fma(A.dt, s2.im, fma(-A.dt_dr, dq2.im, cur.q.im))};
+        cd nq = {fma(A.dt, s2.re, fma(-A.dt_dr, dq2.re, cur.q.re)), fma(A.dt, s2.im, fma(-A.dt_dr, dq2.im, cur.q.im))};
         if (boundary) {
             np = {0.0, 0.0};
             nq = {0.0, 0.0};
         }
         if (store_ok) {
             const size_t o = (size_t)t * P + col;
-            st(phi_out, o, np);
-            st(pi_out, o, nq);
+            st(u_out, o, np);
+            st(u_out, o + A.plane, nq);
+            if (win != nullptr) {  // keep the input state (for the adjoint)
+                st(win, o, cur.p);
+                st(win, o + A.plane, cur.q);
+            }
         }
 
-        ubp_m = cur.ubp;
         hbp_m = cur.hbp;
         if (t + 1 < nth) cur = nxt;
     };
@@ -395,15 +252,18 @@ __global__ void __launch_bounds__(512)
     for (int u = 0; u < kRowsInFlight; ++u)
         if (t0 + u < j1) finish_row(t0 + u, bp[u], bq[u]);
 
-    if (my_e >= 0 && series != nullptr) {
+    if (e_id >= 0 && lane == e_lane && series != nullptr) {
         double2 w;
         w.x = acc.re;
         w.y = acc.im;
-        series[my_e] = w;
+        series[e_id] = w;
     }
 }
 
-__global__ void import_kernel(const double2* __restrict__ src, double2* __restrict__ dst, int nr, int nth,
+// The state is stored as two planes in one buffer: u[f * nth * pitch + j *
+// pitch + i], f = 0 for Phi and 1 for Pi.
+
+__global__ void import_kernel(const double2* __restrict__ src, double2* __restrict__ u, int f, int nr, int nth,
                               int pitch) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
@@ -412,25 +272,25 @@ __global__ void import_kernel(const double2* __restrict__ src, double2* __restri
     v.x = 0.0;
     v.y = 0.0;
     if (i > 0 && i < nr - 1) v = src[(size_t)j * nr + i];
-    dst[(size_t)j * pitch + i] = v;
+    u[(size_t)f * nth * pitch + (size_t)j * pitch + i] = v;
 }
 
-__global__ void export_kernel(const double2* __restrict__ src, double2* __restrict__ dst, int nr, int nth,
+__global__ void export_kernel(const double2* __restrict__ u, double2* __restrict__ dst, int f, int nr, int nth,
                               int pitch) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= nr || j >= nth) return;
-    dst[(size_t)j * nr + i] = src[(size_t)j * pitch + i];
+    dst[(size_t)j * nr + i] = u[(size_t)f * nth * pitch + (size_t)j * pitch + i];
 }
 
-__global__ void extract_kernel(const double2* __restrict__ phi, int pitch, const ExtPoint* __restrict__ pts,
-                               int n, double2* __restrict__ out) {
+__global__ void extract_kernel(const double2* __restrict__ u, int pitch, const ExtPoint* __restrict__ pts, int n,
+                               double2* __restrict__ out) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     const ExtPoint E = pts[e];
     auto row = [&](int j) {
-        const double2 a = phi[(size_t)j * pitch + E.col];
-        const double2 b = phi[(size_t)j * pitch + E.col + 1];
+        const double2 a = u[(size_t)j * pitch + E.col];
+        const double2 b = u[(size_t)j * pitch + E.col + 1];
         return cd{fma(E.wr, b.x - a.x, a.x), fma(E.wr, b.y - a.y, a.y)};
     };
     const cd va = row(E.rowa);
@@ -446,13 +306,12 @@ __global__ void extract_kernel(const double2* __restrict__ phi, int pitch, const
     out[e] = w;
 }
 
-__global__ void nonfinite_kernel(const double2* __restrict__ phi, const double2* __restrict__ pi, int nr, int nth,
-                                 int pitch, int* flag) {
+__global__ void nonfinite_kernel(const double2* __restrict__ u, int nr, int nth, int pitch, int* flag) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= nr || j >= nth) return;
     const size_t o = (size_t)j * pitch + i;
-    const double2 a = phi[o], b = pi[o];
+    const double2 a = u[o], b = u[o + (size_t)nth * pitch];
     if (!isfinite(a.x) || !isfinite(a.y) || !isfinite(b.x) || !isfinite(b.y)) *flag = 1;
 }
 
@@ -467,38 +326,36 @@ __global__ void pitch_copy_kernel(const double* __restrict__ src, double* __rest
 }  // namespace
 
 hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s) {
-    const int nb = (a.k.n_tiles + waves_per_block - 1) / waves_per_block;
+    const int nb = (a.k.n_strips * a.k.n_chunks + waves_per_block - 1) / waves_per_block;
     const dim3 block(kWave * waves_per_block), grid(nb);
     auto kern = kerr ? lw_step_kernel<true> : lw_step_kernel<false>;
-    hipLaunchKernelGGL(kern, grid, block, 0, s, a.phi_in, a.pi_in, a.phi_out, a.pi_out, a.rad, a.ang, a.uci, a.uch,
-                       a.ext, a.series, a.k);
+    hipLaunchKernelGGL(kern, grid, block, 0, s, a.u_in, a.u_out, a.rad, a.ang, a.uci, a.uch,
+                       a.ext, a.series, a.win, a.k);
     return hipGetLastError();
 }
 
-hipError_t launch_import(const double2* src, double2* dst, int nr, int nth, int pitch, hipStream_t s) {
+hipError_t launch_import(const double2* src, double2* u, int f, int nr, int nth, int pitch, hipStream_t s) {
     const dim3 block(256), grid((pitch + 255) / 256, nth);
-    hipLaunchKernelGGL(import_kernel, grid, block, 0, s, src, dst, nr, nth, pitch);
+    hipLaunchKernelGGL(import_kernel, grid, block, 0, s, src, u, f, nr, nth, pitch);
     return hipGetLastError();
 }
 
-hipError_t launch_export(const double2* src, double2* dst, int nr, int nth, int pitch, hipStream_t s) {
+hipError_t launch_export(const double2* u, double2* dst, int f, int nr, int nth, int pitch, hipStream_t s) {
     const dim3 block(256), grid((nr + 255) / 256, nth);
-    hipLaunchKernelGGL(export_kernel, grid, block, 0, s, src, dst, nr, nth, pitch);
+    hipLaunchKernelGGL(export_kernel, grid, block, 0, s, u, dst, f, nr, nth, pitch);
     return hipGetLastError();
 }
 
-hipError_t launch_extract(const double2* phi, int pitch, int /*sigma*/, const ExtPoint* pts, int n, double2* out,
-                          hipStream_t s) {
+hipError_t launch_extract(const double2* u, int pitch, const ExtPoint* pts, int n, double2* out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const dim3 block(64), grid((n + 63) / 64);
-    hipLaunchKernelGGL(extract_kernel, grid, block, 0, s, phi, pitch, pts, n, out);
+    hipLaunchKernelGGL(extract_kernel, grid, block, 0, s, u, pitch, pts, n, out);
     return hipGetLastError();
 }
 
-hipError_t launch_nonfinite(const double2* phi, const double2* pi, int nr, int nth, int pitch, int* flag,
-                            hipStream_t s) {
+hipError_t launch_nonfinite(const double2* u, int nr, int nth, int pitch, int* flag, hipStream_t s) {
     const dim3 block(256), grid((nr + 255) / 256, nth);
-    hipLaunchKernelGGL(nonfinite_kernel, grid, block, 0, s, phi, pi, nr, nth, pitch, flag);
+    hipLaunchKernelGGL(nonfinite_kernel, grid, block, 0, s, u, nr, nth, pitch, flag);
     return hipGetLastError();
 }
 

@@ -47,8 +47,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     int pitch = 0;
-    size_t state = 0;                 // bytes of one complex field [nth][pitch]
-    size_t off_phi[2]{}, off_pi[2]{}; // ping-pong state
+    size_t state = 0;                 // bytes of one state [Phi, Pi][nth][pitch]
+    size_t off_u[2]{};                // ping-pong state
     size_t off_rad = 0, off_ang = 0;  // KERR tables
     size_t off_uci = 0, off_uch = 0;  // USER tables
     size_t off_ext = 0, off_ext2 = 0, off_flag = 0;
@@ -87,12 +87,10 @@ Layout make_layout(const teuk_params* p) {
     Layout L;
     const int nr = (int)p->nr, nth = (int)p->ntheta;
     L.pitch = (nr + 7) / 8 * 8;  // 128-byte rows of complex128
-    L.state = align_up((size_t)nth * L.pitch * sizeof(double2));
+    L.state = align_up((size_t)nth * L.pitch * 2 * sizeof(double2));
     size_t o = 0;
     for (int k = 0; k < 2; ++k) {
-        L.off_phi[k] = o;
-        o += L.state;
-        L.off_pi[k] = o;
+        L.off_u[k] = o;
         o += L.state;
     }
     L.off_rad = o;
@@ -167,21 +165,26 @@ struct teuk_grid {
     int wpb = 4;          // wavefronts per workgroup
     bool fused_ext = true;
     bool coef_set = false;
+    // adjoint (teuk_enable_adjoint)
+    char* aws = nullptr;      // adjoint workspace
+    size_t aoff_lam[2]{}, aoff_da = 0, aoff_slots = 0, aoff_sum = 0;
+    int adj_rows = 32, adj_wpb = 4, adj_chunks = 0, adj_strips = 0;
 
-    double2* phi(int k) const { return reinterpret_cast<double2*>(ws + L.off_phi[k]); }
-    double2* pi(int k) const { return reinterpret_cast<double2*>(ws + L.off_pi[k]); }
+    double2* u(int k) const { return reinterpret_cast<double2*>(ws + L.off_u[k]); }
     template <class T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
 
 namespace {
 
-// Fused extraction needs at most one point per lane of a tile.
+// Fused extraction handles at most one point per tile (its state is held
+// in scalar registers of the tile's wavefront).
 bool fused_extraction_ok(const teuk_grid* g) {
     const auto& E = g->ext;
     for (size_t i = 0; i < E.size(); ++i)
         for (size_t k = i + 1; k < E.size(); ++k)
-            if (E[i].col == E[k].col && E[i].rowa / g->rows == E[k].rowa / g->rows) return false;
+            if (E[i].col / kStripCols == E[k].col / kStripCols && E[i].rowa / g->rows == E[k].rowa / g->rows)
+                return false;
     return true;
 }
 
@@ -194,13 +197,14 @@ StepArgs step_args(const teuk_grid* g) {
     k.sigma = g->sigma;
     k.rows = g->rows;
     k.n_strips = (k.nr + kStripCols - 1) / kStripCols;
-    k.n_tiles = k.n_strips * ((k.nth + g->rows - 1) / g->rows);
+    k.n_chunks = (k.nth + g->rows - 1) / g->rows;
     k.dt = g->p.dt;
     k.hdt = 0.5 * g->p.dt;
     k.dt_dr = g->p.dt / g->dr;
     k.hdt_dr = 0.5 * g->p.dt / g->dr;
     k.inv_dth2 = 1.0 / (g->dth * g->dth);
     k.inv_2dth = 1.0 / (2.0 * g->dth);
+    k.plane = (int64_t)k.nth * k.pitch;
     a.rad = g->at<double>(g->L.off_rad);
     a.ang = g->at<double>(g->L.off_ang);
     if (g->p.coef_mode == TEUK_COEF_USER) {
@@ -340,7 +344,7 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
     hipError_t e = hipGetDevice(&g->device);
     if (e != hipSuccess) return bail(fail(TEUK_E_HIP, "hipGetDevice: %s", hipGetErrorString(e)));
     hipStream_t s = g->stream;
-    e = hipMemsetAsync(g->ws, 0, L.off_rad, s);
+    e = hipMemsetAsync(g->ws, 0, L.off_rad, s);  // both state buffers
     if (e == hipSuccess && !rad.empty())
         e = hipMemcpyAsync(g->ws + L.off_rad, rad.data(), rad.size() * sizeof(double), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -371,14 +375,18 @@ int teuk_set_initial_data(teuk_grid* g, const void* d_phi, const void* d_pi) {
     if (!d_phi || !d_pi) return fail(TEUK_E_INVALID_ARG, "initial data pointers are NULL");
     if (int rc = set_device(g)) return rc;
     const int nr = (int)g->p.nr, nth = (int)g->p.ntheta;
-    HIP_TRY(launch_import(static_cast<const double2*>(d_phi), g->phi(0), nr, nth, g->L.pitch, g->stream));
-    HIP_TRY(launch_import(static_cast<const double2*>(d_pi), g->pi(0), nr, nth, g->L.pitch, g->stream));
+    HIP_TRY(launch_import(static_cast<const double2*>(d_phi), g->u(0), 0, nr, nth, g->L.pitch, g->stream));
+    HIP_TRY(launch_import(static_cast<const double2*>(d_pi), g->u(0), 1, nr, nth, g->L.pitch, g->stream));
     g->cur = 0;
     g->steps = 0;
     return TEUK_OK;
 }
 
-int teuk_step_n(teuk_grid* g, int64_t n, void* d_series) {
+namespace {
+
+// n steps; optional extraction series and optional window of input states
+// (slot k = the state before step k, stride L.state bytes).
+int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window) {
     if (int rc = check_grid(g)) return rc;
     if (n < 0) return fail(TEUK_E_INVALID_ARG, "n=%lld < 0", (long long)n);
     if (!g->coef_set) return fail(TEUK_E_STATE, "USER-mode coefficients not set");
@@ -389,22 +397,41 @@ int teuk_step_n(teuk_grid* g, int64_t n, void* d_series) {
     StepArgs a = step_args(g);
     const bool kerr = g->p.coef_mode == TEUK_COEF_KERR;
     const ExtPoint* ext = g->at<ExtPoint>(g->L.off_ext);
+    char* win = static_cast<char*>(d_window);
     for (int64_t k = 0; k < n; ++k) {
-        a.phi_in = g->phi(g->cur);
-        a.pi_in = g->pi(g->cur);
-        a.phi_out = g->phi(1 - g->cur);
-        a.pi_out = g->pi(1 - g->cur);
+        a.u_in = g->u(g->cur);
+        a.u_out = g->u(1 - g->cur);
         // fused: step k samples its input, i.e. the state after step k-1
         a.series = (series && g->fused_ext && k > 0) ? series + (k - 1) * ne : nullptr;
+        a.win = win ? reinterpret_cast<double2*>(win + (size_t)k * g->L.state) : nullptr;
         HIP_TRY(launch_step(a, kerr, g->wpb, g->stream));
         g->cur = 1 - g->cur;
         g->steps += 1;
         if (series && !g->fused_ext)
-            HIP_TRY(launch_extract(g->phi(g->cur), g->L.pitch, g->sigma, ext, ne, series + k * ne, g->stream));
+            HIP_TRY(launch_extract(g->u(g->cur), g->L.pitch, ext, ne, series + k * ne, g->stream));
     }
     if (series && g->fused_ext)
-        HIP_TRY(launch_extract(g->phi(g->cur), g->L.pitch, g->sigma, ext, ne, series + (n - 1) * ne, g->stream));
+        HIP_TRY(launch_extract(g->u(g->cur), g->L.pitch, ext, ne, series + (n - 1) * ne, g->stream));
     return TEUK_OK;
+}
+
+}  // namespace
+
+int teuk_step_n(teuk_grid* g, int64_t n, void* d_series) { return step_n_impl(g, n, d_series, nullptr); }
+
+size_t teuk_window_bytes(const teuk_grid* g, int64_t n) {
+    if (!g || n < 0) {
+        fail(TEUK_E_INVALID_ARG, "need a grid and n >= 0");
+        return 0;
+    }
+    return g->L.state * (size_t)n;
+}
+
+int teuk_step_n_store(teuk_grid* g, int64_t n, void* d_series, void* d_window) {
+    if (n > 0 && !d_window) return fail(TEUK_E_INVALID_ARG, "window is NULL");
+    if (d_window && reinterpret_cast<uintptr_t>(d_window) % kAlign)
+        return fail(TEUK_E_WORKSPACE, "window not %zu-byte aligned", kAlign);
+    return step_n_impl(g, n, d_series, d_window);
 }
 
 int teuk_extract(teuk_grid* g, int32_t n, const double* h_rstar, const double* h_theta, void* d_out) {
@@ -424,7 +451,7 @@ int teuk_extract(teuk_grid* g, int32_t n, const double* h_rstar, const double* h
     if (int rc = set_device(g)) return rc;
     ExtPoint* dp = g->at<ExtPoint>(g->L.off_ext2);
     HIP_TRY(hipMemcpyAsync(dp, pts.data(), n * sizeof(ExtPoint), hipMemcpyHostToDevice, g->stream));
-    HIP_TRY(launch_extract(g->phi(g->cur), g->L.pitch, g->sigma, dp, n, static_cast<double2*>(d_out), g->stream));
+    HIP_TRY(launch_extract(g->u(g->cur), g->L.pitch, dp, n, static_cast<double2*>(d_out), g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));  // `pts` is released on return
     return TEUK_OK;
 }
@@ -434,8 +461,8 @@ int teuk_get_state(teuk_grid* g, void* d_phi, void* d_pi) {
     if (!d_phi || !d_pi) return fail(TEUK_E_INVALID_ARG, "output pointers are NULL");
     if (int rc = set_device(g)) return rc;
     const int nr = (int)g->p.nr, nth = (int)g->p.ntheta;
-    HIP_TRY(launch_export(g->phi(g->cur), static_cast<double2*>(d_phi), nr, nth, g->L.pitch, g->stream));
-    HIP_TRY(launch_export(g->pi(g->cur), static_cast<double2*>(d_pi), nr, nth, g->L.pitch, g->stream));
+    HIP_TRY(launch_export(g->u(g->cur), static_cast<double2*>(d_phi), 0, nr, nth, g->L.pitch, g->stream));
+    HIP_TRY(launch_export(g->u(g->cur), static_cast<double2*>(d_pi), 1, nr, nth, g->L.pitch, g->stream));
     return TEUK_OK;
 }
 
@@ -444,8 +471,7 @@ int teuk_check_finite(teuk_grid* g) {
     if (int rc = set_device(g)) return rc;
     int* flag = g->at<int>(g->L.off_flag);
     HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), g->stream));
-    HIP_TRY(launch_nonfinite(g->phi(g->cur), g->pi(g->cur), (int)g->p.nr, (int)g->p.ntheta, g->L.pitch, flag,
-                             g->stream));
+    HIP_TRY(launch_nonfinite(g->u(g->cur), (int)g->p.nr, (int)g->p.ntheta, g->L.pitch, flag, g->stream));
     int h = 0;
     HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
@@ -473,6 +499,137 @@ int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per
     if (int rc = check_grid(g)) return rc;
     if (rows_per_tile) *rows_per_tile = g->rows;
     if (waves_per_block) *waves_per_block = g->wpb;
+    return TEUK_OK;
+}
+
+namespace {
+
+void adjoint_layout(teuk_grid* g, size_t* total) {
+    const int nth = (int)g->p.ntheta;
+    g->adj_rows = std::min(nth, 32);
+    g->adj_chunks = (nth + g->adj_rows - 1) / g->adj_rows;
+    g->adj_strips = ((int)g->p.nr + kStripCols - 1) / kStripCols;
+    size_t o = 0;
+    for (int k = 0; k < 2; ++k) {
+        g->aoff_lam[k] = o;
+        o += g->L.state;
+    }
+    g->aoff_da = o;
+    o += align_up((size_t)kNumRad * 2 * g->L.pitch * sizeof(double));
+    g->aoff_slots = o;
+    o += align_up((size_t)g->adj_strips * g->adj_chunks * sizeof(double));
+    g->aoff_sum = o;
+    o += kAlign;
+    *total = o;
+}
+
+}  // namespace
+
+size_t teuk_adjoint_workspace_bytes(teuk_grid* g) {
+    if (!g) {
+        fail(TEUK_E_INVALID_ARG, "grid handle is NULL");
+        return 0;
+    }
+    size_t total;
+    adjoint_layout(g, &total);
+    return total;
+}
+
+int teuk_enable_adjoint(teuk_grid* g, void* d_adj_workspace, size_t bytes) {
+    if (int rc = check_grid(g)) return rc;
+    if (g->p.coef_mode != TEUK_COEF_KERR) return fail(TEUK_E_STATE, "the adjoint needs TEUK_COEF_KERR coefficients");
+    if (!d_adj_workspace) return fail(TEUK_E_INVALID_ARG, "adjoint workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(d_adj_workspace) % kAlign)
+        return fail(TEUK_E_WORKSPACE, "adjoint workspace not %zu-byte aligned", kAlign);
+    size_t total;
+    adjoint_layout(g, &total);
+    if (bytes < total) return fail(TEUK_E_WORKSPACE, "adjoint workspace has %zu bytes, needs %zu", bytes, total);
+    // a-derivatives of the radial tables at fixed r* (dual numbers through
+    // the tortoise inversion and every radial factor)
+    const int nr = (int)g->p.nr;
+    std::vector<double> da((size_t)kNumRad * 2 * g->L.pitch, 0.0);
+    for (int kind = 0; kind < 2; ++kind) {
+        const int npos = kind == 0 ? nr : nr - 1;
+        for (int i = 0; i < npos; ++i) {
+            const double rs = g->p.rstar_min + (i + 0.5 * kind) * g->dr;
+            Dual x;
+            if (!tortoise_inverse_dual(g->p.a, rs, &x))
+                return fail(TEUK_E_INVALID_ARG, "tortoise inversion failed at r*=%g", rs);
+            Dual R[kNumRad];
+            radial_fields<Dual>(Dual(g->p.a, 1.0), g->p.s, g->p.m, x, g->dth, R);
+            for (int f = 0; f < kNumRad; ++f) da[((size_t)f * 2 + kind) * g->L.pitch + i] = R[f].d;
+        }
+    }
+    if (int rc = set_device(g)) return rc;
+    g->aws = static_cast<char*>(d_adj_workspace);
+    HIP_TRY(hipMemsetAsync(g->aws, 0, total, g->stream));
+    HIP_TRY(hipMemcpyAsync(g->aws + g->aoff_da, da.data(), da.size() * sizeof(double), hipMemcpyHostToDevice,
+                           g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return TEUK_OK;
+}
+
+int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi, const void* d_dL_dseries,
+                        const void* d_window, int32_t flags, double* h_dL_da_accum) {
+    if (int rc = check_grid(g)) return rc;
+    if (!g->aws) return fail(TEUK_E_STATE, "teuk_enable_adjoint has not been called");
+    if (n < 0) return fail(TEUK_E_INVALID_ARG, "n=%lld < 0", (long long)n);
+    if (!d_lam_phi || !d_lam_pi) return fail(TEUK_E_INVALID_ARG, "cotangent pointers are NULL");
+    if (n > 0 && !d_window) return fail(TEUK_E_INVALID_ARG, "window is NULL");
+    if (flags & ~TEUK_ADJ_PROJECT_INITIAL) return fail(TEUK_E_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (int rc = set_device(g)) return rc;
+    const int nr = (int)g->p.nr, nth = (int)g->p.ntheta, P = g->L.pitch;
+    const int ne = g->p.n_extract;
+    const double2* gs = (ne > 0) ? static_cast<const double2*>(d_dL_dseries) : nullptr;
+    const ExtPoint* ext = g->at<ExtPoint>(g->L.off_ext);
+    hipStream_t s = g->stream;
+    auto lam = [&](int k) { return reinterpret_cast<double2*>(g->aws + g->aoff_lam[k]); };
+    double* slots = reinterpret_cast<double*>(g->aws + g->aoff_slots);
+    double* sum = reinterpret_cast<double*>(g->aws + g->aoff_sum);
+    const int nslots = g->adj_strips * g->adj_chunks;
+
+    int c = 0;
+    HIP_TRY(launch_import(static_cast<const double2*>(d_lam_phi), lam(c), 0, nr, nth, P, s));
+    HIP_TRY(launch_import(static_cast<const double2*>(d_lam_pi), lam(c), 1, nr, nth, P, s));
+    HIP_TRY(hipMemsetAsync(slots, 0, (size_t)nslots * sizeof(double), s));
+    HIP_TRY(hipMemsetAsync(sum, 0, sizeof(double), s));
+    // the sample of the segment's last state
+    if (gs && n > 0) HIP_TRY(launch_extract_adjoint(lam(c), P, ext, ne, gs + (n - 1) * ne, s));
+    AdjArgs a{};
+    a.k.nr = nr;
+    a.k.nth = nth;
+    a.k.pitch = P;
+    a.k.sigma = g->sigma;
+    a.k.rows = g->adj_rows;
+    a.k.n_strips = g->adj_strips;
+    a.k.n_chunks = g->adj_chunks;
+    a.k.zero = 0;
+    a.k.plane = (int64_t)nth * P;
+    a.k.dt = g->p.dt;
+    a.k.hdt = 0.5 * g->p.dt;
+    a.k.dt_dr = g->p.dt / g->dr;
+    a.k.hdt_dr = 0.5 * g->p.dt / g->dr;
+    a.rad = g->at<double>(g->L.off_rad);
+    a.rad_da = reinterpret_cast<const double*>(g->aws + g->aoff_da);
+    a.ang = g->at<double>(g->L.off_ang);
+    a.slots = slots;
+    const char* win = static_cast<const char*>(d_window);
+    for (int64_t k = n - 1; k >= 0; --k) {
+        a.nu_in = lam(c);
+        a.u_in = reinterpret_cast<const double2*>(win + (size_t)k * g->L.state);
+        a.lam_out = lam(1 - c);
+        HIP_TRY(launch_adjoint(a, g->adj_wpb, s));
+        c = 1 - c;
+        if (gs && k >= 1) HIP_TRY(launch_extract_adjoint(lam(c), P, ext, ne, gs + (k - 1) * ne, s));
+    }
+    if (flags & TEUK_ADJ_PROJECT_INITIAL) HIP_TRY(launch_zero_radial_boundary(lam(c), nr, nth, P, s));
+    HIP_TRY(launch_export(lam(c), static_cast<double2*>(d_lam_phi), 0, nr, nth, P, s));
+    HIP_TRY(launch_export(lam(c), static_cast<double2*>(d_lam_pi), 1, nr, nth, P, s));
+    HIP_TRY(launch_reduce_slots(slots, nslots, sum, s));
+    double h = 0.0;
+    HIP_TRY(hipMemcpyAsync(&h, sum, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h_dL_da_accum) *h_dL_da_accum += h;
     return TEUK_OK;
 }
 

@@ -50,3 +50,22 @@ def small_case(a, s, m, nr, nth, rmin=-30.0, rmax=60.0, dt=None, ext=((20.0, mat
              extract_rstar=[e[0] for e in ext], extract_theta=[e[1] for e in ext])
     w["dt"] = dt if dt is not None else inputs.stable_dt(dr, nth, m, s, 200)
     return w
+
+
+def oracle_segment_adjoint(o, states, lam_phi, lam_pi, gser, ext_r, ext_t):
+    """Reverse of one segment with oracle primitives: `states` are the inputs
+    of the segment's steps; gser[k] is dL/d(sample after step k+1)."""
+    n = len(states)
+    lp, lq = np.array(lam_phi, dtype=np.complex128), np.array(lam_pi, dtype=np.complex128)
+    if gser is not None:
+        for e in range(len(ext_r)):
+            lp = o.extract_adjoint(lp, ext_r[e], ext_t[e], gser[n - 1, e])
+    dlda = 0.0
+    for k in range(n - 1, -1, -1):
+        tp, tq = o.tangent_a(*states[k])
+        dlda += float(np.real(np.vdot(lp, tp) + np.vdot(lq, tq)))
+        lp, lq = o.adjoint_step(lp, lq)
+        if gser is not None and k >= 1:
+            for e in range(len(ext_r)):
+                lp = o.extract_adjoint(lp, ext_r[e], ext_t[e], gser[k - 1, e])
+    return lp, lq, dlda
