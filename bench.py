@@ -10,7 +10,10 @@ in the 256 MB Infinity Cache, so it is the grid on which HBM bandwidth bounds
 the step.  The state is resident in HBM before the timed region starts.
 
 Prints one JSON line.  `value` is grid-point updates per second (one update
-= one (r*, theta) point advanced one full step).  `roofline` prices the step
+= one (r*, theta) point advanced one full step).  `batched` reports the
+64-member uneven batch in one persistent launch per step and its ratio to
+`value`; `adjoint` the backward (recompute + adjoint) over forward time of a
+checkpointed waveform-loss gradient on the 6400 x 256 grid.  `roofline` prices the step
 kernel at its algorithmic traffic, 64 bytes per update (read Phi, Pi and
 write Phi, Pi once, complex128), against the 8 TB/s HBM peak.  `cpu_baseline`
 times the CPU oracle (test infrastructure, plain C + OpenMP) on a bounded
@@ -57,9 +60,9 @@ def measured_traffic(workload):
         return None
 
 
-def cpu_baseline(w, target_seconds=12.0):
-    """The oracle as it stands, on the same grid, for as many whole steps as
-    fit in about `target_seconds` (at least one)."""
+def cpu_baseline(w, target_seconds=10.0):
+    """The oracle as it stands, on the same grid, timed over whole steps
+    until at least `target_seconds` have passed."""
     import numpy as np
 
     import oracle
@@ -71,15 +74,82 @@ def cpu_baseline(w, target_seconds=12.0):
     t0 = time.perf_counter()
     phi, pi = o.step(phi, pi, 1)
     one = time.perf_counter() - t0
-    n = max(1, int(target_seconds / max(one, 1e-6)))
+    chunk = max(1, int(1.0 / max(one, 1e-6)))
+    n, el = 0, 0.0
     t0 = time.perf_counter()
-    phi, pi = o.step(phi, pi, n)
-    el = time.perf_counter() - t0
+    while el < target_seconds:
+        phi, pi = o.step(phi, pi, chunk)
+        n += chunk
+        el = time.perf_counter() - t0
     assert np.isfinite(phi).all()
     pts = w["nr"] * w["ntheta"]
     return {"value": pts * n / el, "unit": "grid-point updates/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"{n} steps of the full {w['nr']}x{w['ntheta']} grid ({el:.1f} s), after 1 untimed step"}
+
+
+def batched_leg(steps=200):
+    """64 uneven evolutions in one persistent launch per step (autotuned)."""
+    import torch
+
+    from paper_1010_3816_amd import autotune, binding, inputs
+
+    mbs = inputs.batch_members()
+    b = binding.TeukBatch(mbs)
+    tune = autotune.tune_batch(b, use_cache=False)
+    for k, mb in enumerate(mbs):
+        p, q = inputs.initial_data(mb)
+        b.set_initial_data(k, torch.from_numpy(p).cuda(), torch.from_numpy(q).cuda())
+    b.step(10)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    b.step(steps)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    pts = b.total_points()
+    out = {"value": pts / (ms * 1e-3), "unit": "member grid-point updates/s", "members": len(mbs),
+           "points_per_step": pts, "steps": steps, "ms_per_step": ms,
+           "launch": {"rows": tune["rows"], "waves_per_block": tune["waves"], "blocks": tune["blocks"]}}
+    b.close()
+    return out
+
+
+def adjoint_leg(n_steps=800, checkpoint_every=100):
+    """Forward (with checkpoints) and backward (recompute + adjoint) of a
+    waveform loss on the adjoint workload's grid; ratio = backward / forward."""
+    import torch
+
+    from paper_1010_3816_amd import inputs
+    from paper_1010_3816_amd.autograd import evolve
+
+    w = inputs.workload("adjoint_a0.7_6400x256")
+    cfg = {k: w[k] for k in ("s", "m", "nr", "ntheta", "rstar_min", "rstar_max", "dt")}
+    cfg["extract_rstar"] = [30.0]  # inside the light cone of the pulse for this run length
+    cfg["extract_theta"] = [math.pi / 2]
+    p0, q0 = inputs.initial_data(w)
+    P = torch.from_numpy(p0).cuda().requires_grad_(True)
+    Q = torch.from_numpy(q0).cuda().requires_grad_(True)
+    A = torch.tensor(w["a"], dtype=torch.float64, device="cuda", requires_grad=True)
+    target = torch.zeros((n_steps, 1), dtype=torch.complex128, device="cuda")
+    times = []
+    for _ in range(2):  # the first pass warms up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ser = evolve(P, Q, A, cfg, n_steps, checkpoint_every)
+        L = ((ser - target).abs() ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append((t1 - t0, t2 - t1))
+        P.grad = Q.grad = A.grad = None
+    fwd, bwd = times[-1]
+    return {"workload": "adjoint_a0.7_6400x256", "steps": n_steps, "checkpoint_every": checkpoint_every,
+            "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3, "ratio": bwd / fwd}
 
 
 def main():
@@ -89,6 +159,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="kerr_a0.99_25600x512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint legs")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB streaming kernel (for counter calibration)")
     args = ap.parse_args()
@@ -164,6 +235,11 @@ def main():
         "wall_s_timed_region": wall,
     }
     g.close()
+    if not args.no_extras:
+        bl = batched_leg()
+        bl["ratio_to_single"] = bl["value"] / ups
+        out["batched"] = bl
+        out["adjoint"] = adjoint_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -178,6 +178,41 @@ int teuk_enable_adjoint(teuk_grid* g, void* d_adj_workspace, size_t bytes);
 int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi, const void* d_dL_dseries,
                         const void* d_window, int32_t flags, double* h_dL_da_accum);
 
+/* ---- Batched evolutions ------------------------------------------------
+ * Many independent grids (each its own a, s, m, nr, ntheta, r* range and dt;
+ * TEUK_COEF_KERR, no extraction points) advanced together: one persistent
+ * launch per step walks a single work list of all members' tiles, and runs
+ * of two steps are replayed from a captured HIP graph.  Every member's
+ * arithmetic is identical to that of a single grid with the same tile rows. */
+typedef struct teuk_batch teuk_batch;
+
+/* Device bytes for a batch of `count` members (0 if a member is invalid). */
+size_t teuk_batch_workspace_bytes(const teuk_params* members, int32_t count);
+
+/* Create a batch: builds every member's tables (synchronous).  The state of
+ * every member is zero until teuk_batch_set_initial_data. */
+int teuk_batch_init(const teuk_params* members, int32_t count, void* hip_stream, void* d_workspace, size_t bytes,
+                    teuk_batch** out);
+
+/* As teuk_set_initial_data / teuk_get_state for one member. */
+int teuk_batch_set_initial_data(teuk_batch* b, int32_t member, const void* d_phi, const void* d_pi);
+int teuk_batch_get_state(teuk_batch* b, int32_t member, void* d_phi, void* d_pi);
+
+/* Advance every member by n >= 0 steps. */
+int teuk_batch_step_n(teuk_batch* b, int64_t n);
+
+/* Launch shape: theta rows per tile, wavefronts per workgroup (1, 2, 4, 8)
+ * and workgroups of the persistent launch.  Waits for queued work. */
+int teuk_batch_set_launch(teuk_batch* b, int32_t rows_per_tile, int32_t waves_per_block, int32_t n_blocks);
+int teuk_batch_get_launch(const teuk_batch* b, int32_t* rows_per_tile, int32_t* waves_per_block,
+                          int32_t* n_blocks);
+
+/* Grid points over all members (updates per batched step). */
+int64_t teuk_batch_total_points(const teuk_batch* b);
+
+/* Release the batch and its members (host memory only). */
+int teuk_batch_free(teuk_batch* b);
+
 /* Release the handle (host memory only; the workspace stays the caller's).
  * Waits for work queued on the grid's stream. */
 int teuk_free(teuk_grid* g);

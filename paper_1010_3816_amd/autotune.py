@@ -1,0 +1,122 @@
+"""Launch-shape autotuner for the step kernels.
+
+The paper's only per-device tuning knob was OpenCL's local_work_size
+(Sec. 4); here the knobs are the theta rows per wavefront tile, the
+wavefronts per workgroup and, for batched launches, the number of workgroups
+of the persistent launch.  Candidates are timed with HIP events on the
+grid's own stream, the fastest is applied, and the choice is cached in a JSON
+file keyed by device and problem shape ($TEUK_TUNE_CACHE, default
+~/.cache/paper_1010_3816_amd/launch.json).  Results of the kernels do not
+depend on the launch shape, only their speed does.
+
+Timing advances the state of the grid or batch: tune before setting the
+initial data, or set it again afterwards.
+"""
+import json
+import os
+
+from . import binding
+
+GRID_ROWS = (8, 12, 16, 24, 32, 48, 64)
+GRID_WAVES = (1, 2, 4, 8)
+BATCH_ROWS = (8, 16, 24, 32)
+BATCH_WAVES = (2, 4, 8)
+
+
+def _cache_path():
+    return os.environ.get("TEUK_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_1010_3816_amd", "launch.json"))
+
+
+def _load_cache():
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(key, value):
+    path = _cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        cache = _load_cache()
+        cache[key] = value
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass  # a read-only home only loses the cache
+
+
+def _device_key(torch, device):
+    p = torch.cuda.get_device_properties(device)
+    return f"{getattr(p, 'gcnArchName', p.name)}/{p.multi_processor_count}cu"
+
+
+def _time(torch, stream, fn, steps, reps=3):
+    fn(2)
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn(steps)
+        e1.record(stream)
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / steps)
+    return best
+
+
+def tune_grid(grid, rows=GRID_ROWS, waves=GRID_WAVES, steps=20, use_cache=True):
+    """Pick (rows_per_tile, waves_per_block) for a TeukGrid; returns
+    {"rows": r, "waves": w, "ms": t, "table": [...]}."""
+    torch = grid.torch
+    key = f"grid|{_device_key(torch, grid.device)}|{grid.nr}x{grid.ntheta}"
+    if use_cache:
+        hit = _load_cache().get(key)
+        if hit:
+            grid.set_tile(min(hit["rows"], grid.ntheta), hit["waves"])
+            return dict(hit, cached=True)
+    table = []
+    for r in sorted({min(r, grid.ntheta) for r in rows}):
+        for w in waves:
+            grid.set_tile(r, w)
+            ms = _time(torch, grid.stream, lambda n: binding.teuk_step_n(grid.handle, n, None), steps)
+            table.append({"rows": r, "waves": w, "ms": ms})
+    best = min(table, key=lambda e: e["ms"])
+    grid.set_tile(best["rows"], best["waves"])
+    out = {"rows": best["rows"], "waves": best["waves"], "ms": best["ms"], "table": table}
+    if use_cache:
+        _store_cache(key, {"rows": best["rows"], "waves": best["waves"], "ms": best["ms"]})
+    return out
+
+
+def tune_batch(batch, rows=BATCH_ROWS, waves=BATCH_WAVES, blocks_per_cu=(1, 2, 4), steps=10, use_cache=True):
+    """Pick (rows_per_tile, waves_per_block, n_blocks) for a TeukBatch."""
+    torch = batch.torch
+    shapes = ",".join(f"{m['nr']}x{m['ntheta']}" for m in batch.members)
+    import hashlib
+
+    key = f"batch|{_device_key(torch, batch.device)}|{hashlib.sha256(shapes.encode()).hexdigest()[:16]}"
+    if use_cache:
+        hit = _load_cache().get(key)
+        if hit:
+            batch.set_launch(hit["rows"], hit["waves"], hit["blocks"])
+            return dict(hit, cached=True)
+    cus = torch.cuda.get_device_properties(batch.device).multi_processor_count
+    table = []
+    for r in rows:
+        for w in waves:
+            for k in blocks_per_cu:
+                nb = max(1, cus * 4 * k // w)  # k wavefronts per SIMD
+                batch.set_launch(r, w, nb)
+                ms = _time(torch, batch.stream, batch.step, steps)
+                table.append({"rows": r, "waves": w, "blocks": nb, "ms": ms})
+    best = min(table, key=lambda e: e["ms"])
+    batch.set_launch(best["rows"], best["waves"], best["blocks"])
+    out = {"rows": best["rows"], "waves": best["waves"], "blocks": best["blocks"], "ms": best["ms"], "table": table}
+    if use_cache:
+        _store_cache(key, {"rows": best["rows"], "waves": best["waves"], "blocks": best["blocks"], "ms": best["ms"]})
+    return out

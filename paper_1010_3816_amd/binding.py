@@ -73,6 +73,15 @@ def _load():
         "teuk_adjoint_workspace_bytes": (ctypes.c_size_t, [V]),
         "teuk_enable_adjoint": (ctypes.c_int, [V, V, ctypes.c_size_t]),
         "teuk_adjoint_step_n": (ctypes.c_int, [V, I64, V, V, V, V, I32, ctypes.POINTER(D)]),
+        "teuk_batch_workspace_bytes": (ctypes.c_size_t, [P, I32]),
+        "teuk_batch_init": (ctypes.c_int, [P, I32, V, V, ctypes.c_size_t, ctypes.POINTER(V)]),
+        "teuk_batch_set_initial_data": (ctypes.c_int, [V, I32, V, V]),
+        "teuk_batch_get_state": (ctypes.c_int, [V, I32, V, V]),
+        "teuk_batch_step_n": (ctypes.c_int, [V, I64]),
+        "teuk_batch_set_launch": (ctypes.c_int, [V, I32, I32, I32]),
+        "teuk_batch_get_launch": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "teuk_batch_total_points": (I64, [V]),
+        "teuk_batch_free": (ctypes.c_int, [V]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -86,7 +95,9 @@ EXPORTED = ("teuk_workspace_bytes", "teuk_init_grid", "teuk_set_coefficients", "
             "teuk_step_n", "teuk_extract", "teuk_get_state", "teuk_check_finite", "teuk_steps_taken",
             "teuk_get_dt", "teuk_set_tile", "teuk_get_tile", "teuk_suggest_dt", "teuk_free",
             "teuk_last_error", "teuk_window_bytes", "teuk_step_n_store", "teuk_adjoint_workspace_bytes",
-            "teuk_enable_adjoint", "teuk_adjoint_step_n")
+            "teuk_enable_adjoint", "teuk_adjoint_step_n", "teuk_batch_workspace_bytes", "teuk_batch_init",
+            "teuk_batch_set_initial_data", "teuk_batch_get_state", "teuk_batch_step_n", "teuk_batch_set_launch",
+            "teuk_batch_get_launch", "teuk_batch_total_points", "teuk_batch_free")
 
 
 def _check(rc):
@@ -351,10 +362,84 @@ class TeukGrid:
             pass
 
 
+class TeukBatch:
+    """Many grids advanced by one persistent launch per step (C ABI teuk_batch_*).
+
+    members: list of dicts with a, s, m, nr, ntheta, rstar_min, rstar_max, dt."""
+
+    def __init__(self, members, device=None, stream=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.members = [dict(m) for m in members]
+        arr = (teuk_params * len(members))()
+        for k, m in enumerate(members):
+            arr[k] = make_params(m["a"], m["s"], m["m"], m["nr"], m["ntheta"], m["rstar_min"], m["rstar_max"],
+                                 m["dt"])
+        self._arr = arr
+        nb = _lib.teuk_batch_workspace_bytes(arr, len(members))
+        if nb == 0:
+            raise TeukError(TEUK_E_INVALID_ARG, teuk_last_error())
+        self.workspace = _aligned_bytes(torch, nb, self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.teuk_batch_init(arr, len(members), ctypes.c_void_p(self.stream.cuda_stream),
+                                        _dptr(self.workspace), nb, ctypes.byref(h)))
+        self.handle = h
+
+    def __len__(self):
+        return len(self.members)
+
+    def shape(self, k):
+        return (int(self.members[k]["ntheta"]), int(self.members[k]["nr"]))
+
+    def set_initial_data(self, k, phi, pi):
+        phi = self.torch.as_tensor(phi, dtype=self.torch.complex128, device=self.device).contiguous()
+        pi = self.torch.as_tensor(pi, dtype=self.torch.complex128, device=self.device).contiguous()
+        if tuple(phi.shape) != self.shape(k) or tuple(pi.shape) != self.shape(k):
+            raise ValueError(f"member {k}: expected shape {self.shape(k)}")
+        self._keep = getattr(self, "_keep", {})
+        self._keep[k] = (phi, pi)
+        _check(_lib.teuk_batch_set_initial_data(self.handle, int(k), _dptr(phi), _dptr(pi)))
+
+    def state(self, k):
+        phi = self.torch.empty(self.shape(k), dtype=self.torch.complex128, device=self.device)
+        pi = self.torch.empty_like(phi)
+        _check(_lib.teuk_batch_get_state(self.handle, int(k), _dptr(phi), _dptr(pi)))
+        return phi, pi
+
+    def step(self, n):
+        _check(_lib.teuk_batch_step_n(self.handle, int(n)))
+
+    def set_launch(self, rows_per_tile, waves_per_block, n_blocks):
+        _check(_lib.teuk_batch_set_launch(self.handle, int(rows_per_tile), int(waves_per_block), int(n_blocks)))
+
+    def launch(self):
+        r, w, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.teuk_batch_get_launch(self.handle, ctypes.byref(r), ctypes.byref(w), ctypes.byref(b)))
+        return r.value, w.value, b.value
+
+    def total_points(self):
+        return int(_lib.teuk_batch_total_points(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            _check(_lib.teuk_batch_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def suggest_dt(a, s, m, nr, ntheta, rstar_min, rstar_max, n_steps, growth=10.0, courant=0.5):
     p = make_params(a, s, m, nr, ntheta, rstar_min, rstar_max, 1.0)
     return teuk_suggest_dt(p, n_steps, growth, courant)
 
 
-__all__ = [n for n in EXPORTED] + ["TeukGrid", "TeukError", "make_params", "suggest_dt", "teuk_params"]
+__all__ = [n for n in EXPORTED] + ["TeukGrid", "TeukBatch", "TeukError", "make_params", "suggest_dt", "teuk_params"]
 

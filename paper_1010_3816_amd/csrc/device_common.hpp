@@ -58,6 +58,44 @@ struct Ang {
     double sn2, cs, cotp, pd;
 };
 
+// Typed pointers for the tile sweep: state in global memory (address space
+// 1) and the coefficient tables, read-only for a launch, in the constant
+// address space (4), so that wavefront-uniform table reads become scalar
+// loads even where the pointers come from a descriptor in memory.
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) v2d* gin_t;
+typedef __attribute__((address_space(1))) v2d* gout_t;
+typedef const __attribute__((address_space(4))) double* ctab_t;
+typedef const __attribute__((address_space(4))) ExtPoint* cext_t;
+
+__device__ __forceinline__ Rad load_rad(ctab_t rad, int pitch, int kind, int pos) {
+    auto f = [&](int field) { return rad[((size_t)field * 2 + kind) * pitch + pos]; };
+    Rad R;
+    R.rho = f(R_RHO);
+    R.rho2 = f(R_RHO2);
+    R.a2d = f(R_A2D);
+    R.rb1 = f(R_RB1);
+    R.rb2 = f(R_RB2);
+    R.rb3 = f(R_RB3);
+    R.ctr = f(R_CTR);
+    R.cti0 = f(R_CTI0);
+    R.cti1 = f(R_CTI1);
+    R.b1n = f(R_B1N);
+    R.dl2 = f(R_DL2);
+    R.v0r = f(R_V0R);
+    R.v0i = f(R_V0I);
+    return R;
+}
+
+__device__ __forceinline__ Ang load_ang(ctab_t ang, int nth, int j) {
+    Ang G;
+    G.sn2 = ang[A_SN2 * nth + j];
+    G.cs = ang[A_CS * nth + j];
+    G.cotp = ang[A_COTP * nth + j];
+    G.pd = ang[A_PD * nth + j];
+    return G;
+}
+
 __device__ __forceinline__ Rad load_rad(const double* __restrict__ rad, int pitch, int kind, int pos) {
     auto f = [&](int field) { return rad[((size_t)field * 2 + kind) * pitch + pos]; };
     Rad R;
@@ -114,7 +152,7 @@ __device__ __forceinline__ Coef kerr_coef(const Rad& R, const Ang& G, Sig s) {
     return c;
 }
 
-__device__ __forceinline__ Coef user_coef(const double* u, int nth, int pitch, int j, int pos, double inv_dth2,
+__device__ __forceinline__ Coef user_coef(ctab_t u, int nth, int pitch, int j, int pos, double inv_dth2,
                                           double inv_2dth) {
     auto f = [&](int k) { return u[((size_t)k * nth + j) * pitch + pos]; };
     Coef c;
@@ -174,7 +212,10 @@ __device__ __forceinline__ cd masked(cd v, unsigned long long mask) {
             __longlong_as_double(__double_as_longlong(v.im) & mask)};
 }
 
-typedef double v2d __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cd ld(gin_t p, size_t o) {
+    const v2d v = p[o];
+    return {v.x, v.y};
+}
 
 // Streaming store of one complex value (16 B, one dwordx4 per lane): the
 // new state is not read again by this launch.
@@ -183,6 +224,13 @@ __device__ __forceinline__ void st(double2* p, size_t o, cd v) {
     w.x = v.re;
     w.y = v.im;
     __builtin_nontemporal_store(w, reinterpret_cast<v2d*>(p + o));
+}
+
+__device__ __forceinline__ void st(gout_t p, size_t o, cd v) {
+    v2d w;
+    w.x = v.re;
+    w.y = v.im;
+    __builtin_nontemporal_store(w, p + o);
 }
 
 // All pointers are distinct allocations (restrict): the uniform reads of

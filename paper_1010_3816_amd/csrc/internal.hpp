@@ -77,6 +77,16 @@ struct StepArgs {
     StepScalars k;
 };
 
+// One member of a batched launch (device-resident descriptor).
+struct BatchMember {
+    double2* u[2];           // the member's two state buffers
+    const double* rad;       // its radial and angular tables (KERR)
+    const double* ang;
+    StepScalars k;           // its launch scalars (rows shared by all members)
+    int32_t tile_begin;      // first tile of this member in the work list
+    int32_t pad[3];
+};
+
 // Scalar launch parameters of the adjoint kernel.
 struct AdjScalars {
     int32_t nr, nth, pitch, sigma;
@@ -99,6 +109,8 @@ struct AdjArgs {
 // Launchers (lw_kernels.hip, adjoint_kernels.hip).  All return the
 // hipError_t of the launch.
 hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s);
+hipError_t launch_batch(const BatchMember* members, int n_members, int total_tiles, int parity, int n_blocks,
+                        int waves_per_block, hipStream_t s);
 hipError_t launch_import(const double2* src, double2* u, int f, int nr, int nth, int pitch, hipStream_t s);
 hipError_t launch_export(const double2* u, double2* dst, int f, int nr, int nth, int pitch, hipStream_t s);
 hipError_t launch_extract(const double2* u, int pitch, const ExtPoint* pts, int n, double2* out, hipStream_t s);

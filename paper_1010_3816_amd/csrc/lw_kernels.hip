@@ -40,27 +40,19 @@ struct Row {
     double wp;
 };
 
+// One tile (strip of 64 columns x theta chunk) of one grid.  Inlined into
+// the single-grid kernel and into the batched kernel.
 template <bool KERR>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_WAVES_PER_SIMD, 8)))
-    lw_step_kernel(const double2* __restrict__ u_in, double2* __restrict__ u_out, const double* __restrict__ rad,
-                   const double* __restrict__ ang, const double* __restrict__ uci, const double* __restrict__ uch,
-                   const ExtPoint* __restrict__ ext, double2* __restrict__ series, double2* __restrict__ win,
-                   StepScalars A) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wpb = blockDim.x / kWave;
-    // Tiles are numbered strip-fastest, so the wavefronts of a workgroup take
-    // neighbouring strips of one theta chunk (their halo columns overlap);
-    // workgroups are remapped so that each XCD receives a contiguous range.
-    const int tile = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * wpb + (threadIdx.x / kWave));
-    const int strip = tile % A.n_strips;
-    const int chunk = tile / A.n_strips;
+__device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __restrict__ u_out, ctab_t rad, ctab_t ang,
+                                           ctab_t uci, ctab_t uch, cext_t ext, double2* __restrict__ series,
+                                           gout_t __restrict__ win, const StepScalars& A, int strip, int chunk,
+                                           int lane) {
     const int nr = A.nr, nth = A.nth, P = A.pitch;
     const int col = strip * kStripCols - 1 + lane;
     const unsigned long long in = ((col >= 0) && (col < nr)) ? ~0ull : 0ull;
     const int ci = min(max(col, 0), nr - 1);  // clamped integer column
     const int hi = min(max(col, 0), nr - 2);  // clamped half point col + 1/2
 
-    if (chunk >= A.n_chunks) return;  // wavefront-uniform (tiles beyond the last)
     // radial factors of this lane's column and half point, held in registers
     Rad Ri, Rh;
     if constexpr (KERR) {
@@ -79,7 +71,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_W
     int e_id = -1, e_lane = 0, e_ra = -1, e_rb = -1;
     double e_wr = 0.0, e_wa = 0.0, e_wb = 0.0;
     for (int e = 0; e < A.n_ext; ++e) {
-        const ExtPoint E = ext[e];
+        const ExtPoint E = {ext[e].col, ext[e].rowa, ext[e].rowb, 0, ext[e].wr, ext[e].wa, ext[e].wb, 0.0};
         const int es = E.col / kStripCols;
         if (es == strip && E.rowa / A.rows == chunk) {
             e_id = e;
@@ -260,6 +252,57 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_W
     }
 }
 
+template <bool KERR>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_WAVES_PER_SIMD, 8)))
+    lw_step_kernel(const double2* __restrict__ u_in, double2* __restrict__ u_out, const double* __restrict__ rad,
+                   const double* __restrict__ ang, const double* __restrict__ uci, const double* __restrict__ uch,
+                   const ExtPoint* __restrict__ ext, double2* __restrict__ series, double2* __restrict__ win,
+                   StepScalars A) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wpb = blockDim.x / kWave;
+    // Tiles are numbered strip-fastest, so the wavefronts of a workgroup take
+    // neighbouring strips of one theta chunk (their halo columns overlap);
+    // workgroups are remapped so that each XCD receives a contiguous range.
+    // The tile index is made explicitly wavefront-uniform so that everything
+    // derived from it (rows, table reads, loop control) is scalar.
+    const int tile = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * wpb + (threadIdx.x / kWave));
+    const int strip = tile % A.n_strips;
+    const int chunk = tile / A.n_strips;
+    if (chunk >= A.n_chunks) return;  // tiles beyond the last
+    sweep_tile<KERR>((gin_t)u_in, (gout_t)u_out, (ctab_t)rad, (ctab_t)ang, (ctab_t)uci, (ctab_t)uch, (cext_t)ext,
+                     series, (gout_t)win, A, strip, chunk, lane);
+}
+
+// Many grids in one persistent launch: the tiles of all members form one
+// work list (member k owns tiles [tile_begin_k, tile_begin_{k+1})); each
+// wavefront walks the list with a grid-wide stride.  All tiles have the
+// same shape (62 columns x `rows` rows, ragged only at a member's edges),
+// so the static stride balances uneven members.  `parity` selects which of
+// each member's two state buffers is the input.
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_WAVES_PER_SIMD, 8)))
+    lw_batch_kernel(const BatchMember* __restrict__ members, int n_members, int total_tiles, int parity) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wpb = blockDim.x / kWave;
+    const int nwaves = gridDim.x * wpb;
+    const int w0 = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * wpb + (threadIdx.x / kWave));
+    for (int tile = w0; tile < total_tiles; tile += nwaves) {
+        int lo = 0, hi = n_members - 1;  // last member with tile_begin <= tile
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (members[mid].tile_begin <= tile)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const BatchMember& M = members[lo];
+        const int local = tile - M.tile_begin;
+        const int strip = local % M.k.n_strips;
+        const int chunk = local / M.k.n_strips;
+        sweep_tile<true>((gin_t)M.u[parity], (gout_t)M.u[1 - parity], (ctab_t)M.rad, (ctab_t)M.ang, nullptr,
+                         nullptr, nullptr, nullptr, nullptr, M.k, strip, chunk, lane);
+    }
+}
+
 // The state is stored as two planes in one buffer: u[f * nth * pitch + j *
 // pitch + i], f = 0 for Phi and 1 for Pi.
 
@@ -331,6 +374,13 @@ hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStr
     auto kern = kerr ? lw_step_kernel<true> : lw_step_kernel<false>;
     hipLaunchKernelGGL(kern, grid, block, 0, s, a.u_in, a.u_out, a.rad, a.ang, a.uci, a.uch,
                        a.ext, a.series, a.win, a.k);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchMember* members, int n_members, int total_tiles, int parity, int n_blocks,
+                        int waves_per_block, hipStream_t s) {
+    hipLaunchKernelGGL(lw_batch_kernel, dim3(n_blocks), dim3(kWave * waves_per_block), 0, s, members, n_members,
+                       total_tiles, parity);
     return hipGetLastError();
 }
 

@@ -327,7 +327,7 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
     g->dr = dr;
     g->dth = dth;
     g->sigma = (std::abs(p->m) % 2 == 0) ? 1 : -1;
-    g->rows = std::min(nth, 64);
+    g->rows = std::min(nth, 16);
     g->ext_r.assign(p->extract_rstar, p->extract_rstar + p->n_extract);
     g->ext_t.assign(p->extract_theta, p->extract_theta + p->n_extract);
     g->p.extract_rstar = g->ext_r.data();
@@ -630,6 +630,246 @@ int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi
     HIP_TRY(hipMemcpyAsync(&h, sum, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (h_dL_da_accum) *h_dL_da_accum += h;
+    return TEUK_OK;
+}
+
+/* ---- batched evolutions ------------------------------------------------ */
+
+struct teuk_batch {
+    std::vector<teuk_grid*> members;
+    std::vector<size_t> ws_off;     // member workspace offsets in the batch workspace
+    size_t desc_off = 0;            // descriptor table offset
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int rows = 16, wpb = 4, n_blocks = 0;
+    int total_tiles = 0;
+    int parity = 0;                 // which state buffer of every member is the input
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;  // two steps (parity 0 then 1)
+    hipStream_t cap = nullptr;      // private stream the graph is captured on
+    int64_t steps = 0;
+};
+
+namespace {
+
+size_t batch_layout(const teuk_params* members, int count, std::vector<size_t>* offs, size_t* desc_off) {
+    size_t o = 0;
+    for (int k = 0; k < count; ++k) {
+        if (offs) offs->push_back(o);
+        o += align_up(make_layout(&members[k]).total);
+    }
+    if (desc_off) *desc_off = o;
+    o += align_up((size_t)count * sizeof(BatchMember));
+    return o;
+}
+
+void batch_drop_graph(teuk_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Descriptor table for the current tile rows; uploaded synchronously.
+int batch_upload(teuk_batch* b) {
+    std::vector<BatchMember> d(b->members.size());
+    int tiles = 0;
+    for (size_t k = 0; k < b->members.size(); ++k) {
+        teuk_grid* g = b->members[k];
+        g->rows = std::min<int>(b->rows, (int)g->p.ntheta);
+        StepArgs a = step_args(g);
+        BatchMember& M = d[k];
+        M.u[0] = g->u(0);
+        M.u[1] = g->u(1);
+        M.rad = a.rad;
+        M.ang = a.ang;
+        M.k = a.k;
+        M.k.n_ext = 0;
+        M.tile_begin = tiles;
+        tiles += a.k.n_strips * a.k.n_chunks;
+    }
+    b->total_tiles = tiles;
+    HIP_TRY(hipMemcpyAsync(b->ws + b->desc_off, d.data(), d.size() * sizeof(BatchMember), hipMemcpyHostToDevice,
+                           b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return TEUK_OK;
+}
+
+int batch_launch(teuk_batch* b, int parity, hipStream_t s) {
+    const hipError_t e = launch_batch(reinterpret_cast<const BatchMember*>(b->ws + b->desc_off),
+                                      (int)b->members.size(), b->total_tiles, parity, b->n_blocks, b->wpb, s);
+    return e == hipSuccess ? TEUK_OK : fail(TEUK_E_HIP, "batched step launch failed: %s", hipGetErrorString(e));
+}
+
+// Capture two steps (parity 0, then 1) into a graph.  The capture runs on a
+// private stream (capturing the caller's stream may not be allowed, e.g. the
+// legacy default stream); the graph is launched on the caller's stream.
+int batch_capture(teuk_batch* b) {
+    if (!b->cap) HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    const int rc0 = batch_launch(b, 0, b->cap);
+    const int rc1 = batch_launch(b, 1, b->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &graph);
+    if (rc0 || rc1 || e != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(TEUK_E_HIP, "capturing the batched step graph failed: %s", hipGetErrorString(e));
+    }
+    b->graph = graph;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return TEUK_OK;
+}
+
+int batch_check(const teuk_batch* b, int member) {
+    if (!b) return fail(TEUK_E_INVALID_ARG, "batch handle is NULL");
+    if (member < 0 || member >= (int)b->members.size())
+        return fail(TEUK_E_INVALID_ARG, "member %d outside [0, %zu)", member, b->members.size());
+    return TEUK_OK;
+}
+
+}  // namespace
+
+size_t teuk_batch_workspace_bytes(const teuk_params* members, int32_t count) {
+    if (!members || count < 1) {
+        fail(TEUK_E_INVALID_ARG, "need count >= 1 members");
+        return 0;
+    }
+    for (int k = 0; k < count; ++k)
+        if (validate(&members[k]) != TEUK_OK) return 0;
+    return batch_layout(members, count, nullptr, nullptr);
+}
+
+int teuk_batch_init(const teuk_params* members, int32_t count, void* hip_stream, void* d_workspace, size_t bytes,
+                    teuk_batch** out) {
+    if (!members || count < 1 || !out) return fail(TEUK_E_INVALID_ARG, "need members, count >= 1 and out");
+    for (int k = 0; k < count; ++k) {
+        if (int rc = validate(&members[k])) return rc;
+        if (members[k].coef_mode != TEUK_COEF_KERR)
+            return fail(TEUK_E_INVALID_ARG, "member %d: batched members use TEUK_COEF_KERR", k);
+        if (members[k].n_extract != 0)
+            return fail(TEUK_E_INVALID_ARG, "member %d: batched members take no extraction points", k);
+    }
+    if (!d_workspace || reinterpret_cast<uintptr_t>(d_workspace) % kAlign)
+        return fail(TEUK_E_WORKSPACE, "batch workspace NULL or not %zu-byte aligned", kAlign);
+    teuk_batch* b = new teuk_batch();
+    const size_t need = batch_layout(members, count, &b->ws_off, &b->desc_off);
+    if (bytes < need) {
+        delete b;
+        return fail(TEUK_E_WORKSPACE, "batch workspace has %zu bytes, needs %zu", bytes, need);
+    }
+    b->ws = static_cast<char*>(d_workspace);
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    for (int k = 0; k < count; ++k) {
+        teuk_grid* g = nullptr;
+        const size_t mbytes = make_layout(&members[k]).total;
+        if (int rc = teuk_init_grid(&members[k], hip_stream, b->ws + b->ws_off[k], mbytes, &g)) {
+            for (teuk_grid* m : b->members) teuk_free(m);
+            delete b;
+            return rc;
+        }
+        b->members.push_back(g);
+    }
+    b->device = b->members[0]->device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || cus < 1)
+        cus = 256;
+    b->n_blocks = cus * 8 / b->wpb;  // two wavefronts per SIMD, four SIMDs per CU
+    if (int rc = batch_upload(b)) {
+        for (teuk_grid* m : b->members) teuk_free(m);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return TEUK_OK;
+}
+
+int teuk_batch_set_initial_data(teuk_batch* b, int32_t member, const void* d_phi, const void* d_pi) {
+    if (int rc = batch_check(b, member)) return rc;
+    if (!d_phi || !d_pi) return fail(TEUK_E_INVALID_ARG, "initial data pointers are NULL");
+    teuk_grid* g = b->members[member];
+    if (int rc = set_device(g)) return rc;
+    const int nr = (int)g->p.nr, nth = (int)g->p.ntheta;
+    HIP_TRY(launch_import(static_cast<const double2*>(d_phi), g->u(b->parity), 0, nr, nth, g->L.pitch, g->stream));
+    HIP_TRY(launch_import(static_cast<const double2*>(d_pi), g->u(b->parity), 1, nr, nth, g->L.pitch, g->stream));
+    g->cur = b->parity;
+    g->steps = 0;
+    return TEUK_OK;
+}
+
+int teuk_batch_get_state(teuk_batch* b, int32_t member, void* d_phi, void* d_pi) {
+    if (int rc = batch_check(b, member)) return rc;
+    return teuk_get_state(b->members[member], d_phi, d_pi);
+}
+
+int teuk_batch_step_n(teuk_batch* b, int64_t n) {
+    if (int rc = batch_check(b, 0)) return rc;
+    if (n < 0) return fail(TEUK_E_INVALID_ARG, "n=%lld < 0", (long long)n);
+    if (n == 0) return TEUK_OK;
+    if (int rc = set_device(b->members[0])) return rc;
+    int64_t left = n;
+    if (b->parity == 1) {  // single step back to parity 0
+        if (int rc = batch_launch(b, 1, b->stream)) return rc;
+        b->parity = 0;
+        --left;
+    }
+    if (left >= 2) {
+        if (!b->exec)  // captured once per launch configuration
+            if (int rc = batch_capture(b)) return rc;
+        for (int64_t k = 0; k + 1 < left; k += 2) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    }
+    if (left % 2) {
+        if (int rc = batch_launch(b, 0, b->stream)) return rc;
+        b->parity = 1;
+    }
+    b->steps += n;
+    for (teuk_grid* g : b->members) {
+        g->cur = b->parity;
+        g->steps += n;
+    }
+    return TEUK_OK;
+}
+
+int teuk_batch_set_launch(teuk_batch* b, int32_t rows_per_tile, int32_t waves_per_block, int32_t n_blocks) {
+    if (int rc = batch_check(b, 0)) return rc;
+    if (rows_per_tile < 1 || rows_per_tile > 4096)
+        return fail(TEUK_E_INVALID_ARG, "rows_per_tile=%d outside [1, 4096]", rows_per_tile);
+    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4 && waves_per_block != 8)
+        return fail(TEUK_E_INVALID_ARG, "waves_per_block=%d not in {1, 2, 4, 8}", waves_per_block);
+    if (n_blocks < 1 || n_blocks > (1 << 20)) return fail(TEUK_E_INVALID_ARG, "n_blocks=%d out of range", n_blocks);
+    if (int rc = set_device(b->members[0])) return rc;
+    HIP_TRY(hipStreamSynchronize(b->stream));  // in-flight launches read the old descriptors
+    batch_drop_graph(b);
+    b->rows = rows_per_tile;
+    b->wpb = waves_per_block;
+    b->n_blocks = n_blocks;
+    return batch_upload(b);
+}
+
+int teuk_batch_get_launch(const teuk_batch* b, int32_t* rows_per_tile, int32_t* waves_per_block,
+                          int32_t* n_blocks) {
+    if (int rc = batch_check(b, 0)) return rc;
+    if (rows_per_tile) *rows_per_tile = b->rows;
+    if (waves_per_block) *waves_per_block = b->wpb;
+    if (n_blocks) *n_blocks = b->n_blocks;
+    return TEUK_OK;
+}
+
+int64_t teuk_batch_total_points(const teuk_batch* b) {
+    if (!b) return -1;
+    int64_t n = 0;
+    for (const teuk_grid* g : b->members) n += g->p.nr * g->p.ntheta;
+    return n;
+}
+
+int teuk_batch_free(teuk_batch* b) {
+    if (!b) return TEUK_OK;
+    hipError_t e = hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (teuk_grid* g : b->members) teuk_free(g);
+    delete b;
+    if (e != hipSuccess) return fail(TEUK_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
     return TEUK_OK;
 }
 
