@@ -33,13 +33,18 @@ sys.path.insert(0, ROOT)
 METRIC = "FP64 grid-point updates/s + % HBM roofline; adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = 64
-KERNEL_SRC = os.path.join(ROOT, "paper_1010_3816_amd", "csrc", "lw_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1010_3816_amd", "csrc", f)
+               for f in ("lw_kernels.hip", "device_common.hpp", "internal.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lw_step_kerr_a0.99_25600x512_traffic.txt")
 
 
 def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sources the step kernel is compiled from."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload):
@@ -88,15 +93,20 @@ def cpu_baseline(w, target_seconds=10.0):
             "sample": f"{n} steps of the full {w['nr']}x{w['ntheta']} grid ({el:.1f} s), after 1 untimed step"}
 
 
-def batched_leg(steps=200):
-    """64 uneven evolutions in one persistent launch per step (autotuned)."""
+def batched_leg(steps=200, launch=None):
+    """64 uneven evolutions in one persistent launch per step (autotuned
+    unless `launch` = (rows, waves_per_block, blocks) is given)."""
     import torch
 
     from paper_1010_3816_amd import autotune, binding, inputs
 
     mbs = inputs.batch_members()
     b = binding.TeukBatch(mbs)
-    tune = autotune.tune_batch(b, use_cache=False)
+    if launch is None:
+        tune = autotune.tune_batch(b, use_cache=False)
+    else:
+        b.set_launch(*launch)
+        tune = {"rows": launch[0], "waves": launch[1], "blocks": launch[2]}
     for k, mb in enumerate(mbs):
         p, q = inputs.initial_data(mb)
         b.set_initial_data(k, torch.from_numpy(p).cuda(), torch.from_numpy(q).cuda())
@@ -160,6 +170,10 @@ def main():
     ap.add_argument("--workload", default="kerr_a0.99_25600x512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint legs")
+    ap.add_argument("--only", choices=["batched", "adjoint"],
+                    help="run only this leg and print its JSON object (for profiling)")
+    ap.add_argument("--batch-launch", default=None,
+                    help="rows,waves_per_block,blocks for the batched leg (default: autotune)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB streaming kernel (for counter calibration)")
     args = ap.parse_args()
@@ -173,6 +187,13 @@ def main():
     from paper_1010_3816_amd import binding, inputs
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    launch = tuple(int(x) for x in args.batch_launch.split(",")) if args.batch_launch else None
+    if args.only == "batched":
+        print(json.dumps(batched_leg(launch=launch)), flush=True)
+        return
+    if args.only == "adjoint":
+        print(json.dumps(adjoint_leg()), flush=True)
+        return
     w = inputs.workload(args.workload)
     g = binding.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"],
                          extract_rstar=w["extract_rstar"], extract_theta=w["extract_theta"])
@@ -236,7 +257,7 @@ def main():
     }
     g.close()
     if not args.no_extras:
-        bl = batched_leg()
+        bl = batched_leg(launch=launch)
         bl["ratio_to_single"] = bl["value"] / ups
         out["batched"] = bl
         out["adjoint"] = adjoint_leg()
