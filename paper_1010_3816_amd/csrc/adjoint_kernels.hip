@@ -105,7 +105,8 @@ __global__ void __launch_bounds__(256)
     lw_adjoint_kernel(const double2* __restrict__ nu_in, const double2* __restrict__ u_in,
                       double2* __restrict__ lam_out, const double* __restrict__ rad,
                       const double* __restrict__ rad_da, const double* __restrict__ ang,
-                      double* __restrict__ dlda_slots, AdjScalars A) {
+                      double* __restrict__ dlda_slots, const ExtPoint* __restrict__ ext,
+                      const double* __restrict__ gsample, AdjScalars A) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
     // a workgroup owns one strip and wpb consecutive theta chunks, so that it
@@ -287,8 +288,21 @@ __global__ void __launch_bounds__(256)
         const cd cQ = {fma(0.5, lubq.re, ldq.re), fma(0.5, lubq.im, ldq.im)};
         const cd dP = {fma(0.5, lubp.re, -ldp.re), fma(0.5, lubp.im, -ldp.im)};
         const cd dQ = {fma(0.5, lubq.re, -ldq.re), fma(0.5, lubq.im, -ldq.im)};
-        const cd outp = cadd3(cur.np, dP, from_left(cP));
+        cd outp = cadd3(cur.np, dP, from_left(cP));
         const cd outq = cadd3(cur.nq, dQ, from_left(cQ));
+        // transposed extraction of the sample of the output state: each
+        // stencil point of an extraction point receives its bilinear weight
+        // times the sample's gradient (gsample[e], re/im interleaved)
+        if (gsample != nullptr) {
+            for (int e = 0; e < A.n_ext; ++e) {
+                const ExtPoint E = ext[e];
+                if (t != E.rowa && t != E.rowb) continue;  // wavefront-uniform
+                const double wrow = (t == E.rowa) ? E.wa : E.wb;
+                const double w = (col == E.col) ? wrow * (1.0 - E.wr) : (col == E.col + 1) ? wrow * E.wr : 0.0;
+                outp.re = fma(w, gsample[2 * e], outp.re);
+                outp.im = fma(w, gsample[2 * e + 1], outp.im);
+            }
+        }
         if (own) {
             const size_t o = (size_t)t * P + col;
             st(lam_out, o, outp);
@@ -395,7 +409,7 @@ hipError_t launch_adjoint(const AdjArgs& a, int waves_per_block, hipStream_t s) 
     const int groups = (a.k.n_chunks + waves_per_block - 1) / waves_per_block;
     const dim3 block(kWave * waves_per_block), grid(a.k.n_strips * groups);
     hipLaunchKernelGGL(lw_adjoint_kernel, grid, block, 0, s, a.nu_in, a.u_in, a.lam_out, a.rad, a.rad_da, a.ang,
-                       a.slots, a.k);
+                       a.slots, a.ext, a.gsample, a.k);
     return hipGetLastError();
 }
 

@@ -27,6 +27,12 @@ constexpr int kDppWaveShl1 = 0x130;
 #ifndef TEUK_ROWS_IN_FLIGHT
 #define TEUK_ROWS_IN_FLIGHT 3
 #endif
+// Tile order of the single-grid launch: 0 = strip-fastest (the wavefronts
+// of a workgroup take neighbouring strips), 1 = chunk-fastest (they take
+// consecutive theta chunks of one strip).
+#ifndef TEUK_CHUNK_FASTEST
+#define TEUK_CHUNK_FASTEST 0
+#endif
 #ifndef TEUK_WAVES_PER_SIMD
 #define TEUK_WAVES_PER_SIMD 2
 #endif

@@ -92,6 +92,7 @@ struct AdjScalars {
     int32_t nr, nth, pitch, sigma;
     int32_t rows, n_strips, n_chunks, zero;  // zero: always 0 (an opaque row offset of LDS reads)
     int64_t plane;                           // nth * pitch: offset of the Pi plane in a state
+    int32_t n_ext, pad;                      // extraction points (fused transposed extraction)
     double dt, hdt, dt_dr, hdt_dr;
 };
 
@@ -103,6 +104,8 @@ struct AdjArgs {
     const double* rad_da;    // d/da of rad
     const double* ang;       // [kNumAng][nth]
     double* slots;           // [n_strips * n_chunks] spin-gradient partial sums (accumulated)
+    const ExtPoint* ext;     // [n_ext] extraction points
+    const double* gsample;   // gradient of the output state's sample, 2 doubles per point, or nullptr
     AdjScalars k;
 };
 

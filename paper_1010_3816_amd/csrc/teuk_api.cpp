@@ -40,6 +40,7 @@ int fail(int code, const char* fmt, ...) {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxExtract = 4096;
+constexpr int kMaxFusedAdjointExtract = 16;  // extraction points handled inside the adjoint kernel
 constexpr int64_t kMaxNr = int64_t(1) << 24;
 constexpr int64_t kMaxNth = int64_t(1) << 20;
 
@@ -613,14 +614,20 @@ int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi
     a.rad_da = reinterpret_cast<const double*>(g->aws + g->aoff_da);
     a.ang = g->at<double>(g->L.off_ang);
     a.slots = slots;
+    a.ext = ext;
+    // the sample of the state an adjoint step produces is added by the
+    // adjoint kernel itself for a few points, by a separate pass otherwise
+    const bool fused = ne <= kMaxFusedAdjointExtract;
+    a.k.n_ext = fused ? ne : 0;
     const char* win = static_cast<const char*>(d_window);
     for (int64_t k = n - 1; k >= 0; --k) {
         a.nu_in = lam(c);
         a.u_in = reinterpret_cast<const double2*>(win + (size_t)k * g->L.state);
         a.lam_out = lam(1 - c);
+        a.gsample = (gs && k >= 1 && fused) ? reinterpret_cast<const double*>(gs + (k - 1) * ne) : nullptr;
         HIP_TRY(launch_adjoint(a, g->adj_wpb, s));
         c = 1 - c;
-        if (gs && k >= 1) HIP_TRY(launch_extract_adjoint(lam(c), P, ext, ne, gs + (k - 1) * ne, s));
+        if (gs && k >= 1 && !fused) HIP_TRY(launch_extract_adjoint(lam(c), P, ext, ne, gs + (k - 1) * ne, s));
     }
     if (flags & TEUK_ADJ_PROJECT_INITIAL) HIP_TRY(launch_zero_radial_boundary(lam(c), nr, nth, P, s));
     HIP_TRY(launch_export(lam(c), static_cast<double2*>(d_lam_phi), 0, nr, nth, P, s));
