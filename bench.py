@@ -127,23 +127,30 @@ def batched_leg(steps=200, launch=None):
     return out
 
 
-def adjoint_leg(n_steps=800, checkpoint_every=100):
-    """Forward (with checkpoints) and backward (recompute + adjoint) of a
-    waveform loss on the adjoint workload's grid; ratio = backward / forward."""
+def adjoint_leg(n_steps=None, checkpoint_every=None):
+    """Forward (with checkpoints) and backward (recompute + adjoint) of the
+    waveform misfit on the adjoint workload: 6400 x 256, a = 0.7, 8000 steps,
+    a checkpoint every 100 steps, target = series of the perturbed run
+    (a + 0.01, centre + 0.5).  ratio = backward / forward wall time."""
     import torch
 
     from paper_1010_3816_amd import inputs
     from paper_1010_3816_amd.autograd import evolve
 
     w = inputs.workload("adjoint_a0.7_6400x256")
-    cfg = {k: w[k] for k in ("s", "m", "nr", "ntheta", "rstar_min", "rstar_max", "dt")}
-    cfg["extract_rstar"] = [30.0]  # inside the light cone of the pulse for this run length
-    cfg["extract_theta"] = [math.pi / 2]
+    n_steps = n_steps or w["steps"]
+    checkpoint_every = checkpoint_every or w["checkpoint_every"]
+    cfg = {k: w[k] for k in ("s", "m", "nr", "ntheta", "rstar_min", "rstar_max", "dt", "extract_rstar",
+                             "extract_theta")}
+    wt = inputs.adjoint_target(w)
+    with torch.no_grad():
+        pt, qt = (torch.from_numpy(x).cuda() for x in inputs.initial_data(wt))
+        target = evolve(pt, qt, wt["a"], cfg, n_steps, n_steps).clone()
+        del pt, qt
     p0, q0 = inputs.initial_data(w)
     P = torch.from_numpy(p0).cuda().requires_grad_(True)
     Q = torch.from_numpy(q0).cuda().requires_grad_(True)
     A = torch.tensor(w["a"], dtype=torch.float64, device="cuda", requires_grad=True)
-    target = torch.zeros((n_steps, 1), dtype=torch.complex128, device="cuda")
     times = []
     for _ in range(2):  # the first pass warms up
         torch.cuda.synchronize()
@@ -156,16 +163,18 @@ def adjoint_leg(n_steps=800, checkpoint_every=100):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         times.append((t1 - t0, t2 - t1))
+        dlda = float(A.grad)
         P.grad = Q.grad = A.grad = None
     fwd, bwd = times[-1]
     return {"workload": "adjoint_a0.7_6400x256", "steps": n_steps, "checkpoint_every": checkpoint_every,
+            "extract": [w["extract_rstar"][0], w["extract_theta"][0]], "loss": float(L), "dL_da": dlda,
             "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3, "ratio": bwd / fwd}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="kerr_a0.99_25600x512")
     ap.add_argument("--no-cpu-baseline", action="store_true")

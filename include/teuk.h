@@ -141,9 +141,12 @@ int teuk_suggest_dt(const teuk_params* p, int64_t n_steps, double growth, double
  * to the library; 256-byte aligned, caller-allocated). */
 size_t teuk_window_bytes(const teuk_grid* g, int64_t n);
 
-/* As teuk_step_n, and also copy the state before step k (k = 0..n-1) into
- * window slot k.  d_window may be reused by later calls once the stream has
- * passed the adjoint call that reads it. */
+/* As teuk_step_n, and also leave the state before step k (k = 0..n-1) in
+ * window slot k: the steps write their outputs straight into the next slot,
+ * so keeping the states costs no extra pass.  The grid's own state ends at
+ * step n as with teuk_step_n.  d_window must not overlap the workspace; it
+ * may be reused by later calls once the stream has passed the adjoint call
+ * that reads it. */
 int teuk_step_n_store(teuk_grid* g, int64_t n, void* d_series, void* d_window);
 
 /* ---- Adjoint (gradients of a loss of the extraction series) ------------
@@ -163,6 +166,13 @@ size_t teuk_adjoint_workspace_bytes(teuk_grid* g);
 /* Build the a-derivative tables (dual numbers on the host) and attach the
  * adjoint workspace.  KERR mode only.  Synchronous. */
 int teuk_enable_adjoint(teuk_grid* g, void* d_adj_workspace, size_t bytes);
+
+/* Launch shape of the adjoint kernel: theta rows per wavefront tile (1 ..
+ * ntheta, default min(ntheta, 16)) and wavefronts per workgroup (1, 2 or 4,
+ * default 4).  The cotangents do not depend on it; dL/da is summed per tile,
+ * so its last bits may.  TEUK_E_INVALID_ARG outside these ranges. */
+int teuk_set_adjoint_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per_block);
+int teuk_get_adjoint_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per_block);
 
 /* Reverse of one segment of n forward steps whose input states are in
  * d_window (as written by teuk_step_n_store; slot k = state s0+k).

@@ -65,6 +65,8 @@ def _load():
         "teuk_get_dt": (D, [V]),
         "teuk_set_tile": (ctypes.c_int, [V, I32, I32]),
         "teuk_get_tile": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "teuk_set_adjoint_tile": (ctypes.c_int, [V, I32, I32]),
+        "teuk_get_adjoint_tile": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "teuk_suggest_dt": (ctypes.c_int, [P, I64, D, D, ctypes.POINTER(D)]),
         "teuk_free": (ctypes.c_int, [V]),
         "teuk_last_error": (ctypes.c_char_p, []),
@@ -95,7 +97,7 @@ EXPORTED = ("teuk_workspace_bytes", "teuk_init_grid", "teuk_set_coefficients", "
             "teuk_step_n", "teuk_extract", "teuk_get_state", "teuk_check_finite", "teuk_steps_taken",
             "teuk_get_dt", "teuk_set_tile", "teuk_get_tile", "teuk_suggest_dt", "teuk_free",
             "teuk_last_error", "teuk_window_bytes", "teuk_step_n_store", "teuk_adjoint_workspace_bytes",
-            "teuk_enable_adjoint", "teuk_adjoint_step_n", "teuk_batch_workspace_bytes", "teuk_batch_init",
+            "teuk_enable_adjoint", "teuk_adjoint_step_n", "teuk_set_adjoint_tile", "teuk_get_adjoint_tile", "teuk_batch_workspace_bytes", "teuk_batch_init",
             "teuk_batch_set_initial_data", "teuk_batch_get_state", "teuk_batch_step_n", "teuk_batch_set_launch",
             "teuk_batch_get_launch", "teuk_batch_total_points", "teuk_batch_free")
 
@@ -197,6 +199,16 @@ def teuk_set_tile(h, rows_per_tile, waves_per_block):
 def teuk_get_tile(h):
     r, w = ctypes.c_int32(), ctypes.c_int32()
     _check(_lib.teuk_get_tile(h, ctypes.byref(r), ctypes.byref(w)))
+    return r.value, w.value
+
+
+def teuk_set_adjoint_tile(h, rows_per_tile, waves_per_block):
+    return _check(_lib.teuk_set_adjoint_tile(h, int(rows_per_tile), int(waves_per_block)))
+
+
+def teuk_get_adjoint_tile(h):
+    r, w = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.teuk_get_adjoint_tile(h, ctypes.byref(r), ctypes.byref(w)))
     return r.value, w.value
 
 
@@ -349,6 +361,12 @@ class TeukGrid:
 
     def tile(self):
         return teuk_get_tile(self.handle)
+
+    def set_adjoint_tile(self, rows_per_tile, waves_per_block):
+        teuk_set_adjoint_tile(self.handle, rows_per_tile, waves_per_block)
+
+    def adjoint_tile(self):
+        return teuk_get_adjoint_tile(self.handle)
 
     def close(self):
         if getattr(self, "handle", None) is not None:

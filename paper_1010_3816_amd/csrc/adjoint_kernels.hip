@@ -84,7 +84,12 @@ __device__ __forceinline__ cd cmul(double x, double y, cd v) {
     return {fma(x, v.re, -y * v.im), fma(x, v.im, y * v.re)};
 }
 
-constexpr int kAdjRowsInFlight = 2;
+// Rows of input loaded ahead of the row being finished.  One keeps the
+// kernel within the registers of two wavefronts per SIMD.
+#ifndef TEUK_ADJ_ROWS_IN_FLIGHT
+#define TEUK_ADJ_ROWS_IN_FLIGHT 1
+#endif
+constexpr int kAdjRowsInFlight = TEUK_ADJ_ROWS_IN_FLIGHT;
 
 // Per-row state carried from the row's arrival to its completion.
 struct AdjRow {
@@ -99,6 +104,8 @@ struct AdjRow {
     cd mid, up, dn;       // stage-2 theta-stencil pieces (to rows t, t+1, t-1)
     cd ldhp;              // cotangent of dh_Phi at i
     cd midh, uph, dnh;    // stage-1 theta-stencil pieces
+    Sig si, sh;           // 1/Sigma, 1/Sigma^2 at the integer and half point
+    Ang g;                // angular factors of the row (wavefront-uniform)
 };
 
 __global__ void __launch_bounds__(256)
@@ -142,8 +149,10 @@ __global__ void __launch_bounds__(256)
     const int last = (j1 < nth) ? j1 : nth - 1;
     double acc = 0.0;  // spin-gradient partial sum of this lane
 
-    auto coefs = [&](int t, Coef& ki, Coef& kh, Sig& si, Sig& sh) {
-        const Ang G = load_ang(ang, nth, t);
+    // angular factors of row t (clamped: rows past the last are loaded
+    // ahead but never used)
+    auto ang_row = [&](int t) -> Ang { return load_ang(ang, nth, min(t, nth - 1)); };
+    auto coefs = [&](int t, const Ang& G, Coef& ki, Coef& kh, Sig& si, Sig& sh) {
         const int o = t & A.zero;
         const Rad Ri = rad_from_lds(rvi, o), Rh = rad_from_lds(rvh, o);
         si = kerr_sigma(Ri, G);
@@ -154,11 +163,14 @@ __global__ void __launch_bounds__(256)
 
     // Arrival of row t: forward stage-1 pieces of u^m and the same-row part
     // of the transposed step applied to nu.
-    auto fresh = [&](int t, cd p, cd q, cd np, cd nq, cd ubp_prev) -> AdjRow {
+    auto fresh = [&](int t, cd p, cd q, cd np, cd nq, cd ubp_prev, const Ang& G) -> AdjRow {
         AdjRow R;
         Coef ki, kh;
         Sig si, sh;
-        coefs(t, ki, kh, si, sh);
+        coefs(t, G, ki, kh, si, sh);
+        R.si = si;
+        R.sh = sh;
+        R.g = G;
         // forward (as in the step kernel)
         p = masked(p, in);
         q = masked(q, in);
@@ -212,7 +224,7 @@ __global__ void __launch_bounds__(256)
         if (j0 > 0) {
             const size_t o = (size_t)(j0 - 1) * P + ci;
             const AdjRow rm = fresh(j0 - 1, ld(u_in, o), ld(u_in, o + A.plane), ld(nu_in, o), ld(nu_in, o + A.plane),
-                                    ubp_prev);
+                                    ubp_prev, ang_row(j0 - 1));
             ubp_prev = rm.ubp;
             ubp_m = rm.ubp;
             hbp_m = rm.hbp;
@@ -220,7 +232,8 @@ __global__ void __launch_bounds__(256)
             below_h = rm.uph;
         }
         const size_t o = (size_t)j0 * P + ci;
-        cur = fresh(j0, ld(u_in, o), ld(u_in, o + A.plane), ld(nu_in, o), ld(nu_in, o + A.plane), ubp_prev);
+        cur = fresh(j0, ld(u_in, o), ld(u_in, o + A.plane), ld(nu_in, o), ld(nu_in, o + A.plane), ubp_prev,
+                    ang_row(j0));
         if (j0 == 0) {
             ubp_m = cscale(sg, cur.ubp);
             hbp_m = cscale(sg, cur.hbp);
@@ -228,6 +241,7 @@ __global__ void __launch_bounds__(256)
             below_h = cscale(sg, cur.dnh);
         }
     }
+    Ang g_next = ang_row(j0 + 1);  // angular factors one row ahead
     cd bu[kAdjRowsInFlight][2], bn[kAdjRowsInFlight][2];
 #pragma unroll
     for (int k = 0; k < kAdjRowsInFlight; ++k) {
@@ -241,8 +255,10 @@ __global__ void __launch_bounds__(256)
     auto finish_row = [&](int t, cd* ru, cd* rn) {
         AdjRow nxt;
         cd ubp_p, hbp_p, above, above_h;
+        const Ang g1 = g_next;
+        g_next = ang_row(t + 2);
         if (t + 1 < nth) {
-            nxt = fresh(t + 1, ru[0], ru[1], rn[0], rn[1], cur.ubp);
+            nxt = fresh(t + 1, ru[0], ru[1], rn[0], rn[1], cur.ubp, g1);
             ubp_p = nxt.ubp;
             hbp_p = nxt.hbp;
             above = nxt.dn;
@@ -252,6 +268,7 @@ __global__ void __launch_bounds__(256)
             hbp_p = cscale(sg, cur.hbp);
             above = cscale(sg, cur.up);
             above_h = cscale(sg, cur.uph);
+            nxt = cur;  // unused: the sweep ends with this row
         }
         {
             const size_t o = (size_t)min(t + 1 + kAdjRowsInFlight, last) * P + ci;
@@ -260,9 +277,16 @@ __global__ void __launch_bounds__(256)
             rn[0] = ld(nu_in, o);
             rn[1] = ld(nu_in, o + A.plane);
         }
+        // coefficients of row t again (rebuilding them from the tables is
+        // cheaper than keeping them in registers since the row arrived)
+        const Ang& G = cur.g;
+        const Sig si = cur.si, sh = cur.sh;
         Coef ki, kh;
-        Sig si, sh;
-        coefs(t, ki, kh, si, sh);
+        {
+            const int o = t & A.zero;
+            ki = kerr_coef(rad_from_lds(rvi, o), G, si);
+            kh = kerr_coef(rad_from_lds(rvh, o), G, sh);
+        }
 
         // forward stage-1 Pi value at the halves i+1/2, i-1/2 of row t
         const cd hq = {fma(cur.wp, ubp_p.re, cur.x.re), fma(cur.wp, ubp_p.im, cur.x.im)};
@@ -312,7 +336,6 @@ __global__ void __launch_bounds__(256)
         // spin gradient: coefficient derivatives against the cotangents of
         // the stage outputs, at the owned half point and integer point
         {
-            const Ang G = load_ang(ang, nth, t);
             const int o = t & A.zero;
             const Coef dkh = kerr_coef_da(rad_from_lds(rvh, o), rad_from_lds(rdh, o), G, sh, kh);
             const Coef dki = kerr_coef_da(rad_from_lds(rvi, o), rad_from_lds(rdi, o), G, si, ki);
@@ -337,7 +360,7 @@ __global__ void __launch_bounds__(256)
         below_h = cur.uph;
         ubp_m = cur.ubp;
         hbp_m = cur.hbp;
-        if (t + 1 < nth) cur = nxt;
+        cur = nxt;
     };
 
     int t0 = j0;

@@ -36,7 +36,8 @@ enum RadField : int {
     kNumRad
 };
 
-// Angular table fields, each a row of ntheta doubles.
+// Angular table fields, stored row by row: [ntheta][kNumAng] doubles, so
+// that one scalar load fetches all fields of a row.
 enum AngField : int {
     A_SN2 = 0,  // sin^2 th
     A_CS,       // cos th
@@ -68,7 +69,7 @@ struct StepArgs {
     const double2* u_in;     // state: [Phi, Pi][nth][pitch]
     double2* u_out;
     const double* rad;       // [kNumRad][2][pitch] (KERR)
-    const double* ang;       // [kNumAng][nth]      (KERR)
+    const double* ang;       // [nth][kNumAng]      (KERR)
     const double* uci;       // [kNumUser][nth][pitch] (USER, integer positions)
     const double* uch;       // [kNumUser][nth][pitch] (USER, half positions)
     const ExtPoint* ext;     // [n_ext]
@@ -102,7 +103,7 @@ struct AdjArgs {
     double2* lam_out;        // lambda^m
     const double* rad;       // [kNumRad][2][pitch]
     const double* rad_da;    // d/da of rad
-    const double* ang;       // [kNumAng][nth]
+    const double* ang;       // [nth][kNumAng]
     double* slots;           // [n_strips * n_chunks] spin-gradient partial sums (accumulated)
     const ExtPoint* ext;     // [n_ext] extraction points
     const double* gsample;   // gradient of the output state's sample, 2 doubles per point, or nullptr

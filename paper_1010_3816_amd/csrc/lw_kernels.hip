@@ -38,6 +38,7 @@ namespace {
 struct Row {
     cd p, q, ubp, hbp, dhp, x;
     double wp;
+    Ang g;  // angular factors of row t (wavefront-uniform, KERR)
 };
 
 // One tile (strip of 64 columns x theta chunk) of one grid.  Inlined into
@@ -85,10 +86,16 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
     }
     cd acc = {0.0, 0.0};
 
-    auto half_coef = [&](int t, double& b) -> Coef {
+    // angular factors of row t (clamped to the grid: rows past the last
+    // are loaded ahead but never used)
+    auto ang_row = [&](int t) -> Ang {
+        Ang G{};
+        if constexpr (KERR) G = load_ang(ang, nth, min(t, nth - 1));
+        return G;
+    };
+    auto half_coef = [&](int t, const Ang& G, double& b) -> Coef {
         Coef k;
         if constexpr (KERR) {
-            const Ang G = load_ang(ang, nth, t);
             k = kerr_coef(Rh, G, kerr_sigma(Rh, G));
         } else {
             k = user_coef(uch, nth, P, t, hi, A.inv_dth2, A.inv_2dth);
@@ -96,9 +103,8 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
         b = k.b;
         return k;
     };
-    auto half_b = [&](int t) -> double {
+    auto half_b = [&](int t, const Ang& G) -> double {
         if constexpr (KERR) {
-            const Ang G = load_ang(ang, nth, t);
             return Rh.rho * kerr_sigma(Rh, G).isig;
         } else {
             return uch[((size_t)U_B * nth + t) * P + hi];
@@ -108,12 +114,13 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
     // Stage-1 pieces of row t from u(t) of this lane and of lane L+1.
     // FULL: also the Pi part x, wp (needs ubp(t-1): `ubp_prev`, or the ghost
     // row when t == 0).  Halo rows only need ubp and hbp.
-    auto fresh = [&](int t, cd p, cd q, cd ubp_prev, bool full) -> Row {
+    auto fresh = [&](int t, cd p, cd q, cd ubp_prev, bool full, const Ang& G) -> Row {
         p = masked(p, in);
         q = masked(q, in);
         Row R;
         R.p = p;
         R.q = q;
+        R.g = G;
         const cd pr = from_right(p), qr = from_right(q);
         R.ubp = cavg(p, pr);
         const cd ubq = cavg(q, qr);
@@ -121,9 +128,9 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
         double bh;
         Coef kh;
         if (full)
-            kh = half_coef(t, bh);
+            kh = half_coef(t, G, bh);
         else
-            bh = half_b(t);
+            bh = half_b(t, G);
         // h_Phi = ubar_Phi - dt/2 (b delta_Phi / dr - ubar_Pi)
         const double tb = A.hdt_dr * bh;
         const cd hp = {fma(-tb, dp.re, fma(A.hdt, ubq.re, R.ubp.re)), fma(-tb, dp.im, fma(A.hdt, ubq.im, R.ubp.im))};
@@ -156,14 +163,17 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
         cd ubp_m = {0.0, 0.0};
         if (j0 > 0) {
             const size_t o = (size_t)(j0 - 1) * P + ci;
-            const Row rm = fresh(j0 - 1, ld(u_in, o), ld(u_in, o + A.plane), ubp_m, false);
+            const Row rm = fresh(j0 - 1, ld(u_in, o), ld(u_in, o + A.plane), ubp_m, false, ang_row(j0 - 1));
             ubp_m = rm.ubp;
             hbp_m = rm.hbp;
         }
         const size_t o = (size_t)j0 * P + ci;
-        cur = fresh(j0, ld(u_in, o), ld(u_in, o + A.plane), ubp_m, true);
+        cur = fresh(j0, ld(u_in, o), ld(u_in, o + A.plane), ubp_m, true, ang_row(j0));
         if (j0 == 0) hbp_m = cscale(sg, cur.hbp);
     }
+    // angular factors of the row after the next one to be finished, loaded
+    // one row ahead so that their scalar loads are complete when needed
+    Ang g_next = ang_row(j0 + 1);
 
     // Ring of D row buffers: buffer u holds row t+1 when row t (t - j0 = u
     // mod D) is finished, and is refilled with row t+1+D right after.  The
@@ -181,13 +191,16 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
         // row t+1: streamed, or the pole ghost row
         Row nxt;
         cd ubp_p, hbp_p;
+        const Ang g1 = g_next;
+        g_next = ang_row(t + 2);
         if (t + 1 < nth) {
-            nxt = fresh(t + 1, rp, rq, cur.ubp, true);
+            nxt = fresh(t + 1, rp, rq, cur.ubp, true, g1);
             ubp_p = nxt.ubp;
             hbp_p = nxt.hbp;
         } else {
             ubp_p = cscale(sg, cur.ubp);
             hbp_p = cscale(sg, cur.hbp);
+            nxt = cur;  // unused: the sweep ends with this row
         }
         {
             const size_t o = (size_t)min(t + 1 + kRowsInFlight, last) * P + ci;
@@ -206,8 +219,7 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
         //   Pi'  = Pi  - dt [ (c dh_Phi - b dh_Pi)/dr - S_Pi(hbar) ]
         Coef ki;
         if constexpr (KERR) {
-            const Ang G = load_ang(ang, nth, t);
-            ki = kerr_coef(Ri, G, kerr_sigma(Ri, G));
+            ki = kerr_coef(Ri, cur.g, kerr_sigma(Ri, cur.g));
         } else {
             ki = user_coef(uci, nth, P, t, ci, A.inv_dth2, A.inv_2dth);
         }
@@ -231,7 +243,7 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
         }
 
         hbp_m = cur.hbp;
-        if (t + 1 < nth) cur = nxt;
+        cur = nxt;
     };
 
     // whole groups of kRowsInFlight rows, then the ragged tail

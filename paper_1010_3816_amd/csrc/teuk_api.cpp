@@ -317,7 +317,7 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
     for (int j = 0; j < nth; ++j) {
         double G[kNumAng];
         angular_fields(p->s, p->m, j, dth, G);
-        for (int f = 0; f < kNumAng; ++f) ang[(size_t)f * nth + j] = G[f];
+        for (int f = 0; f < kNumAng; ++f) ang[(size_t)j * kNumAng + f] = G[f];
     }
 
     teuk_grid* g = new teuk_grid();
@@ -329,6 +329,9 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
     g->dth = dth;
     g->sigma = (std::abs(p->m) % 2 == 0) ? 1 : -1;
     g->rows = std::min(nth, 16);
+    g->adj_rows = std::min(nth, 16);
+    g->adj_chunks = (nth + g->adj_rows - 1) / g->adj_rows;
+    g->adj_strips = ((int)p->nr + kStripCols - 1) / kStripCols;
     g->ext_r.assign(p->extract_rstar, p->extract_rstar + p->n_extract);
     g->ext_t.assign(p->extract_theta, p->extract_theta + p->n_extract);
     g->p.extract_rstar = g->ext_r.data();
@@ -399,18 +402,31 @@ int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window) {
     const bool kerr = g->p.coef_mode == TEUK_COEF_KERR;
     const ExtPoint* ext = g->at<ExtPoint>(g->L.off_ext);
     char* win = static_cast<char*>(d_window);
+    auto window_state = [&](int64_t k) { return reinterpret_cast<double2*>(win + (size_t)k * g->L.state); };
+    // Without a window the state ping-pongs between the grid's two buffers.
+    // With one, step k reads window[k] and writes window[k+1] directly (the
+    // window is the sequence of input states), the first step copies the
+    // grid's state into window[0] on the way, and the last step writes the
+    // grid's other buffer: no state is written twice.
+    const int cur0 = g->cur;
     for (int64_t k = 0; k < n; ++k) {
-        a.u_in = g->u(g->cur);
-        a.u_out = g->u(1 - g->cur);
+        if (win) {
+            a.u_in = (k == 0) ? g->u(cur0) : window_state(k);
+            a.u_out = (k + 1 < n) ? window_state(k + 1) : g->u(1 - cur0);
+            a.win = (k == 0) ? window_state(0) : nullptr;
+        } else {
+            a.u_in = g->u(g->cur);
+            a.u_out = g->u(1 - g->cur);
+            a.win = nullptr;
+            g->cur = 1 - g->cur;
+        }
         // fused: step k samples its input, i.e. the state after step k-1
         a.series = (series && g->fused_ext && k > 0) ? series + (k - 1) * ne : nullptr;
-        a.win = win ? reinterpret_cast<double2*>(win + (size_t)k * g->L.state) : nullptr;
         HIP_TRY(launch_step(a, kerr, g->wpb, g->stream));
-        g->cur = 1 - g->cur;
         g->steps += 1;
-        if (series && !g->fused_ext)
-            HIP_TRY(launch_extract(g->u(g->cur), g->L.pitch, ext, ne, series + k * ne, g->stream));
+        if (series && !g->fused_ext) HIP_TRY(launch_extract(a.u_out, g->L.pitch, ext, ne, series + k * ne, g->stream));
     }
+    if (win) g->cur = 1 - cur0;
     if (series && g->fused_ext)
         HIP_TRY(launch_extract(g->u(g->cur), g->L.pitch, ext, ne, series + (n - 1) * ne, g->stream));
     return TEUK_OK;
@@ -503,13 +519,29 @@ int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per
     return TEUK_OK;
 }
 
+int teuk_set_adjoint_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per_block) {
+    if (int rc = check_grid(g)) return rc;
+    if (rows_per_tile < 1 || rows_per_tile > g->p.ntheta)
+        return fail(TEUK_E_INVALID_ARG, "rows_per_tile=%d outside [1, ntheta]", rows_per_tile);
+    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+        return fail(TEUK_E_INVALID_ARG, "waves_per_block=%d not in {1, 2, 4}", waves_per_block);
+    g->adj_rows = rows_per_tile;
+    g->adj_chunks = (int)((g->p.ntheta + rows_per_tile - 1) / rows_per_tile);
+    g->adj_wpb = waves_per_block;
+    return TEUK_OK;
+}
+
+int teuk_get_adjoint_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per_block) {
+    if (int rc = check_grid(g)) return rc;
+    if (rows_per_tile) *rows_per_tile = g->adj_rows;
+    if (waves_per_block) *waves_per_block = g->adj_wpb;
+    return TEUK_OK;
+}
+
 namespace {
 
 void adjoint_layout(teuk_grid* g, size_t* total) {
     const int nth = (int)g->p.ntheta;
-    g->adj_rows = std::min(nth, 32);
-    g->adj_chunks = (nth + g->adj_rows - 1) / g->adj_rows;
-    g->adj_strips = ((int)g->p.nr + kStripCols - 1) / kStripCols;
     size_t o = 0;
     for (int k = 0; k < 2; ++k) {
         g->aoff_lam[k] = o;
@@ -518,7 +550,7 @@ void adjoint_layout(teuk_grid* g, size_t* total) {
     g->aoff_da = o;
     o += align_up((size_t)kNumRad * 2 * g->L.pitch * sizeof(double));
     g->aoff_slots = o;
-    o += align_up((size_t)g->adj_strips * g->adj_chunks * sizeof(double));
+    o += align_up((size_t)g->adj_strips * nth * sizeof(double));  // room for any tile rows
     g->aoff_sum = o;
     o += kAlign;
     *total = o;

@@ -22,6 +22,11 @@ grid sizes, Sec. 4; these are synthetic stand-ins):
   5000 steps each.
 * ``adjoint_a0.7_6400x256``: a=0.7, s=-2, m=2, 6400 x 256, r* in
   [-100, 600], rng(1013) pulse, 8000 steps, checkpoint every 100 steps.
+  At the stable time step the run covers t ~ 11.7 M, so a signal from the
+  pulse (centre ~ 17 M) cannot reach r* = 500 M: the extraction point is
+  moved inside the light cone, to r* = 25 M (about centre + t/2), theta =
+  pi/2.  The loss target is the series of a perturbed run (a + 0.01, centre
+  + 0.5), see ``adjoint_target``.
 """
 import math
 
@@ -141,7 +146,7 @@ def workload(name):
         c, wd = _pulse_draw(1013)
         w = dict(a=0.7, s=-2, m=2, nr=6400, ntheta=256, rstar_min=-100.0, rstar_max=600.0,
                  center=c, width=wd, profile="regular", steps=8000, checkpoint_every=100,
-                 extract_rstar=[500.0], extract_theta=[math.pi / 2])
+                 extract_rstar=[25.0], extract_theta=[math.pi / 2])
     else:
         raise KeyError(name)
     w["name"] = name
@@ -149,6 +154,16 @@ def workload(name):
     w["dt_literal"] = 0.5 * w["dr"]
     w["dt"] = stable_dt(w["dr"], w["ntheta"], w["m"], w["s"], w["steps"])
     return w
+
+
+def adjoint_target(w):
+    """Parameters of the perturbed run whose extraction series is the loss
+    target of the adjoint workload: spin + 0.01 and pulse centre + 0.5 M,
+    everything else (grid, time step, width, extraction point) unchanged."""
+    t = dict(w)
+    t["a"] = w["a"] + 0.01
+    t["center"] = w["center"] + 0.5
+    return t
 
 
 def batch_members(seed=1012, count=64, rstar_min=-100.0, rstar_max=600.0, steps=5000):

@@ -150,3 +150,30 @@ def test_state_round_trip_and_finite_check(gpu):
     g.set_initial_data(torch.from_numpy(bad).cuda(), torch.from_numpy(pi0).cuda())
     assert not g.check_finite()
     g.close()
+
+
+def test_step_split_invariance_and_zero_steps(gpu):
+    """n steps in one call equal the same steps split over several calls, bit
+    for bit, series included (the sample of each call's first input state is
+    fused into the next kernel, the last one taken after the loop); a call
+    with n = 0 changes nothing."""
+    import torch
+
+    w = small_case(0.9, -2, 3, 211, 37, ext=((20.0, math.pi / 2), (-12.0, 0.3)))
+    phi0, pi0 = inputs.random_state(211, 37, seed=17)
+    ref = run_gpu(gpu, w, phi0, pi0, 12)
+    g = gpu.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"],
+                     extract_rstar=w["extract_rstar"], extract_theta=w["extract_theta"])
+    g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
+    parts = []
+    for n in (1, 0, 5, 6):
+        s = g.step(n)
+        if n == 0:
+            assert s is None and g.steps == 1
+        else:
+            parts.append(s.cpu().numpy())
+    phi, pi = (t.cpu().numpy() for t in g.state())
+    assert g.steps == 12
+    assert np.array_equal(phi, ref[0]) and np.array_equal(pi, ref[1])
+    assert np.array_equal(np.concatenate(parts), ref[2])
+    g.close()
