@@ -167,7 +167,7 @@ def adjoint_leg(n_steps=None, checkpoint_every=None):
         P.grad = Q.grad = A.grad = None
     fwd, bwd = times[-1]
     return {"workload": "adjoint_a0.7_6400x256", "steps": n_steps, "checkpoint_every": checkpoint_every,
-            "extract": [w["extract_rstar"][0], w["extract_theta"][0]], "loss": float(L), "dL_da": dlda,
+            "extract": [w["extract_rstar"][0], w["extract_theta"][0]], "loss": float(L.detach()), "dL_da": dlda,
             "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3, "ratio": bwd / fwd}
 
 
