@@ -6,18 +6,23 @@ One "step" is one Lax-Wendroff time step (Eqs. (lw1)-(lw2) of
 arXiv:1010.3816 with the boundary updates) of the whole grid, launched
 through the C ABI (teuk_step_n).  The default workload is the 25600 x 512
 Kerr a = 0.99 grid (13.1 M points, 419 MB per state copy): it does not fit
-in the 256 MB Infinity Cache, so it is the grid on which HBM bandwidth bounds
-the step.  The state is resident in HBM before the timed region starts.
+in the 256 MB Infinity Cache, so HBM traffic is real.  The state is resident
+in HBM before the timed region starts.  The library advances pairs of steps
+in one pass (temporal blocking); the launch shape is autotuned first.
 
 Prints one JSON line.  `value` is grid-point updates per second (one update
-= one (r*, theta) point advanced one full step).  `batched` reports the
-64-member uneven batch in one persistent launch per step and its ratio to
-`value`; `adjoint` the backward (recompute + adjoint) over forward time of a
-checkpointed waveform-loss gradient on the 6400 x 256 grid.  `roofline` prices the step
-kernel at its algorithmic traffic, 64 bytes per update (read Phi, Pi and
-write Phi, Pi once, complex128), against the 8 TB/s HBM peak.  `cpu_baseline`
-times the CPU oracle (test infrastructure, plain C + OpenMP) on a bounded
-number of steps of the same grid.
+= one (r*, theta) point advanced one full step).  `roofline` describes the
+dominant kernel, the two-step pass: it moves 64 algorithmic bytes per point
+per pass (Phi, Pi read and written once, complex128), i.e. 32 B per update,
+and executes about 222 FP64 flops per update (FMA = 2; counted from its
+instruction stream, coefficient rebuild included), so with the state traffic
+halved its ceiling is FP64 arithmetic: `bound` "alu", peak 78.6 TFLOP/s;
+the HBM view is given beside it.  `batched` reports the 64-member uneven
+batch in one persistent launch per pass and its ratio to `value`; `adjoint`
+the backward (recompute + adjoint) over forward time of a checkpointed
+waveform-loss gradient on the 6400 x 256 grid.  `cpu_baseline` times the
+CPU oracle (test infrastructure, plain C + OpenMP) on a bounded number of
+steps of the same grid.
 """
 import argparse
 import hashlib
@@ -32,7 +37,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FP64 grid-point updates/s + % HBM roofline; adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_UPDATE = 64
+FP64_PEAK_TFLOPS = 78.6
+BYTES_PER_POINT_PASS = 64   # Phi, Pi read and written once per pass (complex128)
+FLOPS_PER_UPDATE = {1: 233, 2: 222}  # FP64 flops per point and step, single-step and two-step kernels
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1010_3816_amd", "csrc", f)
                for f in ("lw_kernels.hip", "device_common.hpp", "internal.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lw_step_kerr_a0.99_25600x512_traffic.txt")
@@ -47,9 +54,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
-    """HBM bytes per step launch from the committed rocprofv3 counter summary,
-    if it was taken on this workload with the current kernel source."""
+def measured_traffic(workload, spp):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, if it was taken on this workload and kernel
+    with the current kernel source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -57,7 +65,8 @@ def measured_traffic(workload):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("workload") != workload:
+    if (kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("workload") != workload
+            or kv.get("steps_per_launch") != str(spp)):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -183,6 +192,10 @@ def main():
                     help="run only this leg and print its JSON object (for profiling)")
     ap.add_argument("--batch-launch", default=None,
                     help="rows,waves_per_block,blocks for the batched leg (default: autotune)")
+    ap.add_argument("--tile", default=None,
+                    help="rows,waves_per_block of the step kernel (default: autotune)")
+    ap.add_argument("--steps-per-pass", type=int, choices=[1, 2], default=None,
+                    help="force one or two steps per kernel pass (default: the library's, two)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB streaming kernel (for counter calibration)")
     args = ap.parse_args()
@@ -193,7 +206,7 @@ def main():
 
     import torch
 
-    from paper_1010_3816_amd import binding, inputs
+    from paper_1010_3816_amd import autotune, binding, inputs
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
     launch = tuple(int(x) for x in args.batch_launch.split(",")) if args.batch_launch else None
@@ -206,6 +219,13 @@ def main():
     w = inputs.workload(args.workload)
     g = binding.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"],
                          extract_rstar=w["extract_rstar"], extract_theta=w["extract_theta"])
+    if args.steps_per_pass:
+        g.set_steps_per_pass(args.steps_per_pass)
+    spp = g.steps_per_pass()
+    if args.tile:
+        g.set_tile(*(int(x) for x in args.tile.split(",")))
+    else:
+        autotune.tune_grid(g, rows=(16, 32, 64), waves=(1, 2, 4), steps=20, use_cache=False)
     phi0, pi0 = inputs.initial_data(w)
     g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
     series = torch.empty((max(args.steps, args.warmup, 1), max(g.n_extract, 1)), dtype=torch.complex128,
@@ -231,9 +251,22 @@ def main():
     pts = w["nr"] * w["ntheta"]
     ms_step = ms / args.steps
     ups = pts / (ms_step * 1e-3)
-    achieved = BYTES_PER_UPDATE * pts / (ms_step * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload)
+    # per launch of the dominant kernel (spp steps per launch)
+    launch_s = spp * ms_step * 1e-3
+    hbm_gbs = BYTES_PER_POINT_PASS * pts / launch_s / 1e9
+    tflops = FLOPS_PER_UPDATE[spp] * spp * pts / launch_s / 1e12
+    traffic = measured_traffic(args.workload, spp)
     rows, wpb = g.tile()
+    if spp == 2:
+        roof = {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tflops / FP64_PEAK_TFLOPS, "traffic": traffic, "kernel": "lw_step2_kernel",
+                "flops_per_update": FLOPS_PER_UPDATE[2], "steps_per_launch": 2,
+                "hbm": {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_gbs / HBM_PEAK_GBS,
+                        "bytes_per_update": BYTES_PER_POINT_PASS / 2}}
+    else:
+        roof = {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": traffic, "kernel": "lw_step_kernel",
+                "flops_per_update": FLOPS_PER_UPDATE[1], "steps_per_launch": 1}
 
     if args.calibrate:
         n = 1 << 27  # 1 GiB of float64
@@ -259,9 +292,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "nr": w["nr"], "ntheta": w["ntheta"], "a": w["a"], "s": w["s"],
                    "m": w["m"], "rstar": [w["rstar_min"], w["rstar_max"]], "dt": w["dt"],
-                   "n_extract": g.n_extract, "tile_rows": rows, "waves_per_block": wpb},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+                   "n_extract": g.n_extract, "steps_per_pass": spp, "tile_rows": rows, "waves_per_block": wpb},
+        "roofline": roof,
         "wall_s_timed_region": wall,
     }
     g.close()

@@ -120,11 +120,25 @@ int teuk_check_finite(teuk_grid* g);
 int64_t teuk_steps_taken(const teuk_grid* g);
 double teuk_get_dt(const teuk_grid* g);
 
-/* Launch shape of the step kernel: rows of theta per wavefront tile
- * (1..ntheta) and wavefronts per workgroup (1, 2, 4 or 8).  Results do not
- * depend on it (every point's arithmetic is the same). */
+/* Launch shape of the step kernels: rows of theta per wavefront tile
+ * (1..ntheta, default min(ntheta, 32)) and wavefronts per workgroup (1, 2,
+ * 4 or 8, default 4).  Results do not depend on it (every point's
+ * arithmetic is the same). */
 int teuk_set_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per_block);
 int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per_block);
+
+/* Steps per pass over the state: 1 or 2 (default).  With 2, teuk_step_n
+ * advances pairs of steps in one kernel pass (temporal blocking: the
+ * intermediate state stays in registers, halving the state traffic per
+ * step) and an odd last step alone; the per-point arithmetic is that of
+ * single steps, so results are identical.  teuk_step_n_store keeps the
+ * intermediate state of a pass in its window slot; its first step runs
+ * alone (it also copies its input).  Runs whose extraction points share a
+ * tile of the two-step kernel run one step per pass.  The tile rows of
+ * teuk_set_tile apply; at most 4 wavefronts per workgroup are used.
+ * TEUK_E_INVALID_ARG for other values. */
+int teuk_set_steps_per_pass(teuk_grid* g, int32_t steps_per_pass);
+int teuk_get_steps_per_pass(const teuk_grid* g, int32_t* steps_per_pass);
 
 /* Host-only: a time step for n_steps steps of this problem.  Returns
  * min(courant * dr, dt_g), where dt_g bounds the growth of the fastest
@@ -214,6 +228,9 @@ int teuk_batch_step_n(teuk_batch* b, int64_t n);
 /* Launch shape: theta rows per tile, wavefronts per workgroup (1, 2, 4, 8)
  * and workgroups of the persistent launch.  Waits for queued work. */
 int teuk_batch_set_launch(teuk_batch* b, int32_t rows_per_tile, int32_t waves_per_block, int32_t n_blocks);
+/* Steps per launch of the batch: 1 or 2 (default; see teuk_set_steps_per_pass).
+ * Member results do not depend on it.  Synchronises the batch's stream. */
+int teuk_batch_set_steps_per_pass(teuk_batch* b, int32_t steps_per_pass);
 int teuk_batch_get_launch(const teuk_batch* b, int32_t* rows_per_tile, int32_t* waves_per_block,
                           int32_t* n_blocks);
 

@@ -65,6 +65,8 @@ def _load():
         "teuk_get_dt": (D, [V]),
         "teuk_set_tile": (ctypes.c_int, [V, I32, I32]),
         "teuk_get_tile": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "teuk_set_steps_per_pass": (ctypes.c_int, [V, I32]),
+        "teuk_get_steps_per_pass": (ctypes.c_int, [V, ctypes.POINTER(I32)]),
         "teuk_set_adjoint_tile": (ctypes.c_int, [V, I32, I32]),
         "teuk_get_adjoint_tile": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "teuk_suggest_dt": (ctypes.c_int, [P, I64, D, D, ctypes.POINTER(D)]),
@@ -81,6 +83,7 @@ def _load():
         "teuk_batch_get_state": (ctypes.c_int, [V, I32, V, V]),
         "teuk_batch_step_n": (ctypes.c_int, [V, I64]),
         "teuk_batch_set_launch": (ctypes.c_int, [V, I32, I32, I32]),
+        "teuk_batch_set_steps_per_pass": (ctypes.c_int, [V, I32]),
         "teuk_batch_get_launch": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "teuk_batch_total_points": (I64, [V]),
         "teuk_batch_free": (ctypes.c_int, [V]),
@@ -97,9 +100,11 @@ EXPORTED = ("teuk_workspace_bytes", "teuk_init_grid", "teuk_set_coefficients", "
             "teuk_step_n", "teuk_extract", "teuk_get_state", "teuk_check_finite", "teuk_steps_taken",
             "teuk_get_dt", "teuk_set_tile", "teuk_get_tile", "teuk_suggest_dt", "teuk_free",
             "teuk_last_error", "teuk_window_bytes", "teuk_step_n_store", "teuk_adjoint_workspace_bytes",
-            "teuk_enable_adjoint", "teuk_adjoint_step_n", "teuk_set_adjoint_tile", "teuk_get_adjoint_tile", "teuk_batch_workspace_bytes", "teuk_batch_init",
+            "teuk_enable_adjoint", "teuk_adjoint_step_n", "teuk_set_adjoint_tile", "teuk_get_adjoint_tile",
+            "teuk_set_steps_per_pass", "teuk_get_steps_per_pass", "teuk_batch_workspace_bytes", "teuk_batch_init",
             "teuk_batch_set_initial_data", "teuk_batch_get_state", "teuk_batch_step_n", "teuk_batch_set_launch",
-            "teuk_batch_get_launch", "teuk_batch_total_points", "teuk_batch_free")
+            "teuk_batch_get_launch", "teuk_batch_total_points", "teuk_batch_free",
+            "teuk_batch_set_steps_per_pass")
 
 
 def _check(rc):
@@ -200,6 +205,16 @@ def teuk_get_tile(h):
     r, w = ctypes.c_int32(), ctypes.c_int32()
     _check(_lib.teuk_get_tile(h, ctypes.byref(r), ctypes.byref(w)))
     return r.value, w.value
+
+
+def teuk_set_steps_per_pass(h, steps_per_pass):
+    return _check(_lib.teuk_set_steps_per_pass(h, int(steps_per_pass)))
+
+
+def teuk_get_steps_per_pass(h):
+    v = ctypes.c_int32()
+    _check(_lib.teuk_get_steps_per_pass(h, ctypes.byref(v)))
+    return v.value
 
 
 def teuk_set_adjoint_tile(h, rows_per_tile, waves_per_block):
@@ -362,6 +377,12 @@ class TeukGrid:
     def tile(self):
         return teuk_get_tile(self.handle)
 
+    def set_steps_per_pass(self, steps_per_pass):
+        teuk_set_steps_per_pass(self.handle, steps_per_pass)
+
+    def steps_per_pass(self):
+        return teuk_get_steps_per_pass(self.handle)
+
     def set_adjoint_tile(self, rows_per_tile, waves_per_block):
         teuk_set_adjoint_tile(self.handle, rows_per_tile, waves_per_block)
 
@@ -433,6 +454,9 @@ class TeukBatch:
 
     def set_launch(self, rows_per_tile, waves_per_block, n_blocks):
         _check(_lib.teuk_batch_set_launch(self.handle, int(rows_per_tile), int(waves_per_block), int(n_blocks)))
+
+    def set_steps_per_pass(self, steps_per_pass):
+        _check(_lib.teuk_batch_set_steps_per_pass(self.handle, int(steps_per_pass)))
 
     def launch(self):
         r, w, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

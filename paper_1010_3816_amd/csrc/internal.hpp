@@ -15,6 +15,10 @@ namespace teuk {
 // columns c0 .. c0+61 (lanes 1..62) have both neighbouring half points.
 constexpr int kWave = 64;
 constexpr int kStripCols = kWave - 2;
+// Output columns per strip of the two-step kernel: its second step needs the
+// first step's results one column further out on each side, so lanes 2..61
+// hold the output columns c0 .. c0+59 of a strip whose lanes hold c0-2 .. c0+61.
+constexpr int kStripCols2 = kWave - 4;
 
 // Radial table fields, each a row of `pitch` doubles, first for the integer
 // positions r*_i then for the half positions r*_{i+1/2}.  With r, Delta,
@@ -74,7 +78,8 @@ struct StepArgs {
     const double* uch;       // [kNumUser][nth][pitch] (USER, half positions)
     const ExtPoint* ext;     // [n_ext]
     double2* series;         // n_ext samples of the input Phi, or nullptr
-    double2* win;            // copy of the input state (same layout), or nullptr
+    double2* win;            // copy of the input state (two-step kernel: the intermediate state), or nullptr
+    double2* series_mid;     // two-step kernel: samples of Phi after the first step, or nullptr
     StepScalars k;
 };
 
@@ -85,7 +90,9 @@ struct BatchMember {
     const double* ang;
     StepScalars k;           // its launch scalars (rows shared by all members)
     int32_t tile_begin;      // first tile of this member in the work list
-    int32_t pad[3];
+    int32_t tile_begin2;     // the same in the two-step work list
+    int32_t n_strips2;       // its strips of the two-step kernel
+    int32_t pad;
 };
 
 // Scalar launch parameters of the adjoint kernel.
@@ -113,8 +120,11 @@ struct AdjArgs {
 // Launchers (lw_kernels.hip, adjoint_kernels.hip).  All return the
 // hipError_t of the launch.
 hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s);
+// Two steps in one pass (k.n_strips counted in kStripCols2-column strips).
+hipError_t launch_step2(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s);
+// two = true: two steps per launch (work list of tile_begin2 / n_strips2).
 hipError_t launch_batch(const BatchMember* members, int n_members, int total_tiles, int parity, int n_blocks,
-                        int waves_per_block, hipStream_t s);
+                        int waves_per_block, bool two, hipStream_t s);
 hipError_t launch_import(const double2* src, double2* u, int f, int nr, int nth, int pitch, hipStream_t s);
 hipError_t launch_export(const double2* u, double2* dst, int f, int nr, int nth, int pitch, hipStream_t s);
 hipError_t launch_extract(const double2* u, int pitch, const ExtPoint* pts, int n, double2* out, hipStream_t s);

@@ -264,6 +264,296 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
     }
 }
 
+// Two Lax-Wendroff steps in one pass over a tile (temporal blocking): the
+// first step's result never leaves registers.  Step A sweeps the input rows
+// exactly as sweep_tile does; each row it completes, u^{n+1}(r), is fed as
+// the next input row of a second sweep, step B, which completes row r-1 of
+// u^{n+2}.  Per tile, A covers the rows j0-1 .. j1 that B needs (reading
+// j0-2 .. j1+1) and B writes j0 .. j1-1.  Across lanes, A's results are
+// valid on lanes 1..62 and B's on lanes 2..61, hence 60-column strips.
+// Boundary rules are those of one step: A's radial boundary columns are
+// zero before B reads them, and both sweeps use the pole ghost rows.
+// Extraction is fused for both states a pass samples: the input (sample of
+// step n-1) and the intermediate state (sample of step n).
+template <bool KERR>
+__device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __restrict__ u_out, ctab_t rad,
+                                            ctab_t ang, ctab_t uci, ctab_t uch, cext_t ext,
+                                            double2* __restrict__ series_in, double2* __restrict__ series_mid,
+                                            gout_t __restrict__ u_mid, const StepScalars& A, int strip, int chunk,
+                                            int lane) {
+    const int nr = A.nr, nth = A.nth, P = A.pitch;
+    const int col = strip * kStripCols2 - 2 + lane;
+    const unsigned long long in = ((col >= 0) && (col < nr)) ? ~0ull : 0ull;
+    const int ci = min(max(col, 0), nr - 1);
+    const int hi = min(max(col, 0), nr - 2);
+
+    Rad Ri, Rh;
+    if constexpr (KERR) {
+        Ri = load_rad(rad, P, 0, ci);
+        Rh = load_rad(rad, P, 1, hi);
+    }
+
+    const bool store_ok = (lane >= 2) && (lane <= kWave - 3) && (col < nr);
+    const bool boundary = (col == 0) || (col == nr - 1);
+    const int j0 = chunk * A.rows;
+    const int j1 = min(j0 + A.rows, nth);
+    const int aE = min(j1, nth - 1);         // last row step A completes
+    const int lastA = min(aE + 1, nth - 1);  // last input row read
+    const double sg = (double)A.sigma;
+
+    // the (at most one) extraction point of this tile
+    int e_id = -1, e_lane = 0, e_ra = -1, e_rb = -1;
+    double e_wr = 0.0, e_wa = 0.0, e_wb = 0.0;
+    for (int e = 0; e < A.n_ext; ++e) {
+        const int ecol = ext[e].col, era = ext[e].rowa;
+        const int es = ecol / kStripCols2;
+        if (es == strip && era / A.rows == chunk) {
+            e_id = e;
+            e_lane = ecol - es * kStripCols2 + 2;
+            e_ra = era;
+            e_rb = ext[e].rowb;
+            e_wr = ext[e].wr;
+            e_wa = ext[e].wa;
+            e_wb = ext[e].wb;
+        }
+    }
+    cd acc_in = {0.0, 0.0}, acc_mid = {0.0, 0.0};
+    // bilinear sample of a (masked) Phi row into acc
+    auto sample = [&](int t, cd p, cd& acc) {
+        if (t == e_ra || t == e_rb) {  // wavefront-uniform
+            const double w = (t == e_ra) ? e_wa : e_wb;
+            const cd pr = from_right(p);
+            acc.re = fma(w, fma(e_wr, pr.re - p.re, p.re), acc.re);
+            acc.im = fma(w, fma(e_wr, pr.im - p.im, p.im), acc.im);
+        }
+    };
+
+    auto ang_row = [&](int t) -> Ang {
+        Ang G{};
+        if constexpr (KERR) G = load_ang(ang, nth, min(t, nth - 1));
+        return G;
+    };
+
+    // Stage-1 pieces of row t (as in sweep_tile).  FULL = false: only the
+    // averages needed from a halo row.
+    auto fresh = [&](int t, cd p, cd q, cd ubp_prev, bool full, const Ang& G) -> Row {
+        p = masked(p, in);
+        q = masked(q, in);
+        Row R;
+        R.p = p;
+        R.q = q;
+        R.g = G;
+        const cd pr = from_right(p), qr = from_right(q);
+        R.ubp = cavg(p, pr);
+        const cd ubq = cavg(q, qr);
+        const cd dp = csub(pr, p);
+        Coef kh;
+        double bh;
+        if constexpr (KERR) {
+            if (full) {
+                kh = kerr_coef(Rh, G, kerr_sigma(Rh, G));
+                bh = kh.b;
+            } else {
+                bh = Rh.rho * kerr_sigma(Rh, G).isig;
+            }
+        } else {
+            kh = user_coef(uch, nth, P, t, hi, A.inv_dth2, A.inv_2dth);
+            bh = kh.b;
+        }
+        const double tb = A.hdt_dr * bh;
+        const cd hp = {fma(-tb, dp.re, fma(A.hdt, ubq.re, R.ubp.re)), fma(-tb, dp.im, fma(A.hdt, ubq.im, R.ubp.im))};
+        const cd hpl = from_left(hp);
+        R.hbp = cavg(hp, hpl);
+        R.dhp = csub(hp, hpl);
+        if (full) {
+            const cd dq = csub(qr, q);
+            const cd um = (t == 0) ? cscale(sg, R.ubp) : ubp_prev;
+            const cd dq1 = d_pi(kh, dp, dq);
+            const cd s1 = s_pi(kh, um, R.ubp, cd{0.0, 0.0}, ubq);
+            R.x = {fma(A.hdt, s1.re, fma(-A.hdt_dr, dq1.re, ubq.re)), fma(A.hdt, s1.im, fma(-A.hdt_dr, dq1.im, ubq.im))};
+            R.wp = A.hdt * (kh.a2s + kh.a1s);
+        }
+        return R;
+    };
+
+    // Stage 2 at (i, t): the new (Phi, Pi) of row t from its stage-1 state
+    // c, hbar_Phi of row t-1 and (ubar_Phi, hbar_Phi) of row t+1.
+    auto out_row = [&](int t, const Row& c, cd hbp_m, cd ubp_p, cd hbp_p, cd& np, cd& nq) {
+        const cd hq = {fma(c.wp, ubp_p.re, c.x.re), fma(c.wp, ubp_p.im, c.x.im)};
+        const cd hql = from_left(hq);
+        const cd hbq = cavg(hq, hql);
+        const cd dhq = csub(hq, hql);
+        Coef ki;
+        if constexpr (KERR) {
+            ki = kerr_coef(Ri, c.g, kerr_sigma(Ri, c.g));
+        } else {
+            ki = user_coef(uci, nth, P, t, ci, A.inv_dth2, A.inv_2dth);
+        }
+        const double tb = A.dt_dr * ki.b;
+        np = {fma(-tb, c.dhp.re, fma(A.dt, hbq.re, c.p.re)), fma(-tb, c.dhp.im, fma(A.dt, hbq.im, c.p.im))};
+        const cd dq2 = d_pi(ki, c.dhp, dhq);
+        const cd s2 = s_pi(ki, hbp_m, c.hbp, hbp_p, hbq);
+        nq = {fma(A.dt, s2.re, fma(-A.dt_dr, dq2.re, c.q.re)), fma(A.dt, s2.im, fma(-A.dt_dr, dq2.im, c.q.im))};
+        if (boundary) {
+            np = {0.0, 0.0};
+            nq = {0.0, 0.0};
+        }
+    };
+
+    // the intermediate state, kept for the adjoint (owned rows and columns)
+    auto store_mid = [&](int t, cd vp, cd vq) {
+        if (u_mid != nullptr && t >= j0 && t < j1 && store_ok) {
+            const size_t o = (size_t)t * P + col;
+            st(u_mid, o, vp);
+            st(u_mid, o + A.plane, vq);
+        }
+    };
+
+    auto load_row = [&](int t, cd& p, cd& q) {
+        const size_t o = (size_t)min(max(t, 0), lastA) * P + ci;
+        p = ld(u_in, o);
+        q = ld(u_in, o + A.plane);
+    };
+
+    // ---- prologue: step A completes rows j0-1 (if j0 > 0) and j0; step B
+    // takes them as its halo row and its first row ------------------------
+    Row a_cur, b_cur;
+    cd a_hbp_m, b_hbp_m;
+    {
+        cd p, q;
+        // step A's rows j0-2 (halo) .. j0+1
+        cd ubp_m = {0.0, 0.0};
+        const int aS = max(j0 - 1, 0);
+        if (aS > 0) {
+            load_row(aS - 1, p, q);
+            const Row h = fresh(aS - 1, p, q, ubp_m, false, ang_row(aS - 1));
+            sample(aS - 1, h.p, acc_in);
+            ubp_m = h.ubp;
+            a_hbp_m = h.hbp;
+        }
+        load_row(aS, p, q);
+        a_cur = fresh(aS, p, q, ubp_m, true, ang_row(aS));
+        sample(aS, a_cur.p, acc_in);
+        if (aS == 0) a_hbp_m = cscale(sg, a_cur.hbp);
+        cd b_ubp_m = {0.0, 0.0};
+        for (int r = aS; r <= j0; ++r) {  // one or two rows, wavefront-uniform
+            Row a_nxt;
+            cd ubp_p, hbp_p;
+            if (r + 1 < nth) {
+                load_row(r + 1, p, q);
+                a_nxt = fresh(r + 1, p, q, a_cur.ubp, true, ang_row(r + 1));
+                sample(r + 1, a_nxt.p, acc_in);
+                ubp_p = a_nxt.ubp;
+                hbp_p = a_nxt.hbp;
+            } else {
+                ubp_p = cscale(sg, a_cur.ubp);
+                hbp_p = cscale(sg, a_cur.hbp);
+                a_nxt = a_cur;
+            }
+            cd vp, vq;
+            out_row(r, a_cur, a_hbp_m, ubp_p, hbp_p, vp, vq);
+            store_mid(r, vp, vq);
+            const Ang gr = a_cur.g;
+            a_hbp_m = a_cur.hbp;
+            a_cur = a_nxt;
+            if (r < j0) {  // step B's halo row j0-1
+                const Row h = fresh(r, vp, vq, b_ubp_m, false, gr);
+                sample(r, h.p, acc_mid);
+                b_ubp_m = h.ubp;
+                b_hbp_m = h.hbp;
+            } else {
+                b_cur = fresh(r, vp, vq, b_ubp_m, true, gr);
+                sample(r, b_cur.p, acc_mid);
+                if (r == 0) b_hbp_m = cscale(sg, b_cur.hbp);
+            }
+        }
+    }
+
+    // ---- main sweep: A completes row r (reading row r+1 from the ring), B
+    // completes row r-1 --------------------------------------------------
+    cd bp[kRowsInFlight], bq[kRowsInFlight];
+#pragma unroll
+    for (int u = 0; u < kRowsInFlight; ++u) load_row(j0 + 2 + u, bp[u], bq[u]);
+    Ang g_next = ang_row(j0 + 2);
+
+    auto step_row = [&](int r, cd& rp, cd& rq) {
+        Row a_nxt;
+        cd ubp_p, hbp_p;
+        const Ang g1 = g_next;
+        g_next = ang_row(r + 2);
+        if (r + 1 < nth) {
+            a_nxt = fresh(r + 1, rp, rq, a_cur.ubp, true, g1);
+            sample(r + 1, a_nxt.p, acc_in);
+            ubp_p = a_nxt.ubp;
+            hbp_p = a_nxt.hbp;
+        } else {
+            ubp_p = cscale(sg, a_cur.ubp);
+            hbp_p = cscale(sg, a_cur.hbp);
+            a_nxt = a_cur;  // unused: the sweep ends with this row
+        }
+        load_row(r + 1 + kRowsInFlight, rp, rq);
+        cd vp, vq;
+        out_row(r, a_cur, a_hbp_m, ubp_p, hbp_p, vp, vq);
+        store_mid(r, vp, vq);
+        const Ang gr = a_cur.g;
+        a_hbp_m = a_cur.hbp;
+        a_cur = a_nxt;
+
+        const Row b_nxt = fresh(r, vp, vq, b_cur.ubp, true, gr);
+        sample(r, b_nxt.p, acc_mid);
+        cd wp, wq;
+        out_row(r - 1, b_cur, b_hbp_m, b_nxt.ubp, b_nxt.hbp, wp, wq);
+        if (store_ok) {
+            const size_t o = (size_t)(r - 1) * P + col;
+            st(u_out, o, wp);
+            st(u_out, o + A.plane, wq);
+        }
+        b_hbp_m = b_cur.hbp;
+        b_cur = b_nxt;
+    };
+
+    int r0 = j0 + 1;
+    for (; r0 + kRowsInFlight - 1 <= aE; r0 += kRowsInFlight) {
+#pragma unroll
+        for (int u = 0; u < kRowsInFlight; ++u) step_row(r0 + u, bp[u], bq[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kRowsInFlight; ++u)
+        if (r0 + u <= aE) step_row(r0 + u, bp[u], bq[u]);
+
+    // the grid's last row: step B with the pole ghost row
+    if (j1 == nth) {
+        cd wp, wq;
+        out_row(nth - 1, b_cur, b_hbp_m, cscale(sg, b_cur.ubp), cscale(sg, b_cur.hbp), wp, wq);
+        if (store_ok) {
+            const size_t o = (size_t)(nth - 1) * P + col;
+            st(u_out, o, wp);
+            st(u_out, o + A.plane, wq);
+        }
+    }
+
+    if (e_id >= 0 && lane == e_lane) {
+        if (series_in != nullptr) series_in[e_id] = double2{acc_in.re, acc_in.im};
+        if (series_mid != nullptr) series_mid[e_id] = double2{acc_mid.re, acc_mid.im};
+    }
+}
+
+template <bool KERR>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4)))
+    lw_step2_kernel(const double2* __restrict__ u_in, double2* __restrict__ u_out, const double* __restrict__ rad,
+                    const double* __restrict__ ang, const double* __restrict__ uci, const double* __restrict__ uch,
+                    const ExtPoint* __restrict__ ext, double2* __restrict__ series_in,
+                    double2* __restrict__ series_mid, double2* __restrict__ u_mid, StepScalars A) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wpb = blockDim.x / kWave;
+    const int tile = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * wpb + (threadIdx.x / kWave));
+    const int strip = tile % A.n_strips;
+    const int chunk = tile / A.n_strips;
+    if (chunk >= A.n_chunks) return;  // tiles beyond the last
+    sweep_tile2<KERR>((gin_t)u_in, (gout_t)u_out, (ctab_t)rad, (ctab_t)ang, (ctab_t)uci, (ctab_t)uch, (cext_t)ext,
+                      series_in, series_mid, (gout_t)u_mid, A, strip, chunk, lane);
+}
+
 template <bool KERR>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_WAVES_PER_SIMD, 8)))
     lw_step_kernel(const double2* __restrict__ u_in, double2* __restrict__ u_out, const double* __restrict__ rad,
@@ -318,6 +608,34 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_W
         const int chunk = local / M.k.n_strips;
         sweep_tile<true>((gin_t)M.u[parity], (gout_t)M.u[1 - parity], (ctab_t)M.rad, (ctab_t)M.ang, nullptr,
                          nullptr, nullptr, nullptr, nullptr, M.k, strip, chunk, lane);
+    }
+}
+
+// The batched launch of the two-step pass: as lw_batch_kernel, over the
+// members' two-step tiles.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4)))
+    lw_batch2_kernel(const BatchMember* __restrict__ members, int n_members, int total_tiles, int parity) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wpb = blockDim.x / kWave;
+    const int nwaves = gridDim.x * wpb;
+    const int w0 = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * wpb + (threadIdx.x / kWave));
+    for (int tile = w0; tile < total_tiles; tile += nwaves) {
+        int lo = 0, hi = n_members - 1;  // last member with tile_begin2 <= tile
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (members[mid].tile_begin2 <= tile)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const BatchMember& M = members[lo];
+        const int local = tile - M.tile_begin2;
+        StepScalars k = M.k;
+        k.n_strips = M.n_strips2;
+        const int strip = local % k.n_strips;
+        const int chunk = local / k.n_strips;
+        sweep_tile2<true>((gin_t)M.u[parity], (gout_t)M.u[1 - parity], (ctab_t)M.rad, (ctab_t)M.ang, nullptr,
+                          nullptr, nullptr, nullptr, nullptr, nullptr, k, strip, chunk, lane);
     }
 }
 
@@ -395,10 +713,23 @@ hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStr
     return hipGetLastError();
 }
 
+hipError_t launch_step2(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s) {
+    const int nb = (a.k.n_strips * a.k.n_chunks + waves_per_block - 1) / waves_per_block;
+    const dim3 block(kWave * waves_per_block), grid(nb);
+    auto kern = kerr ? lw_step2_kernel<true> : lw_step2_kernel<false>;
+    hipLaunchKernelGGL(kern, grid, block, 0, s, a.u_in, a.u_out, a.rad, a.ang, a.uci, a.uch, a.ext, a.series,
+                       a.series_mid, a.win, a.k);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch(const BatchMember* members, int n_members, int total_tiles, int parity, int n_blocks,
-                        int waves_per_block, hipStream_t s) {
-    hipLaunchKernelGGL(lw_batch_kernel, dim3(n_blocks), dim3(kWave * waves_per_block), 0, s, members, n_members,
-                       total_tiles, parity);
+                        int waves_per_block, bool two, hipStream_t s) {
+    if (two)
+        hipLaunchKernelGGL(lw_batch2_kernel, dim3(n_blocks), dim3(kWave * (waves_per_block < 4 ? waves_per_block : 4)), 0, s, members,
+                           n_members, total_tiles, parity);
+    else
+        hipLaunchKernelGGL(lw_batch_kernel, dim3(n_blocks), dim3(kWave * waves_per_block), 0, s, members, n_members,
+                           total_tiles, parity);
     return hipGetLastError();
 }
 

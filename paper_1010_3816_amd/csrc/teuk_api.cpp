@@ -165,6 +165,8 @@ struct teuk_grid {
     int rows = 64;        // theta rows per wavefront tile
     int wpb = 4;          // wavefronts per workgroup
     bool fused_ext = true;
+    int steps_per_pass = 2;  // 2: pairs of steps in one pass (temporal blocking)
+    bool fused_ext2 = true;  // extraction fusable with the two-step strips
     bool coef_set = false;
     // adjoint (teuk_enable_adjoint)
     char* aws = nullptr;      // adjoint workspace
@@ -180,13 +182,18 @@ namespace {
 
 // Fused extraction handles at most one point per tile (its state is held
 // in scalar registers of the tile's wavefront).
-bool fused_extraction_ok(const teuk_grid* g) {
+bool fused_extraction_ok(const teuk_grid* g, int strip_cols = kStripCols) {
     const auto& E = g->ext;
     for (size_t i = 0; i < E.size(); ++i)
         for (size_t k = i + 1; k < E.size(); ++k)
-            if (E[i].col / kStripCols == E[k].col / kStripCols && E[i].rowa / g->rows == E[k].rowa / g->rows)
+            if (E[i].col / strip_cols == E[k].col / strip_cols && E[i].rowa / g->rows == E[k].rowa / g->rows)
                 return false;
     return true;
+}
+
+void update_fusion(teuk_grid* g) {
+    g->fused_ext = fused_extraction_ok(g);
+    g->fused_ext2 = fused_extraction_ok(g, kStripCols2);
 }
 
 StepArgs step_args(const teuk_grid* g) {
@@ -328,7 +335,7 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
     g->dr = dr;
     g->dth = dth;
     g->sigma = (std::abs(p->m) % 2 == 0) ? 1 : -1;
-    g->rows = std::min(nth, 16);
+    g->rows = std::min(nth, 32);
     g->adj_rows = std::min(nth, 16);
     g->adj_chunks = (nth + g->adj_rows - 1) / g->adj_rows;
     g->adj_strips = ((int)p->nr + kStripCols - 1) / kStripCols;
@@ -338,7 +345,7 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
     g->p.extract_theta = g->ext_t.data();
     for (int e = 0; e < p->n_extract; ++e)
         g->ext.push_back(ext_point(g->ext_r[e], g->ext_t[e], p->rstar_min, dr, nr, nth, g->sigma));
-    g->fused_ext = fused_extraction_ok(g);
+    update_fusion(g);
     g->coef_set = p->coef_mode == TEUK_COEF_KERR;
 
     auto bail = [&](int rc) {
@@ -404,31 +411,70 @@ int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window) {
     char* win = static_cast<char*>(d_window);
     auto window_state = [&](int64_t k) { return reinterpret_cast<double2*>(win + (size_t)k * g->L.state); };
     // Without a window the state ping-pongs between the grid's two buffers.
-    // With one, step k reads window[k] and writes window[k+1] directly (the
-    // window is the sequence of input states), the first step copies the
-    // grid's state into window[0] on the way, and the last step writes the
-    // grid's other buffer: no state is written twice.
+    // With one, state k (0 < k < n) is written straight into window slot k,
+    // the first step copies the grid's state into slot 0 on the way, and the
+    // last step writes the grid's other buffer: no state is written twice.
     const int cur0 = g->cur;
-    for (int64_t k = 0; k < n; ++k) {
-        if (win) {
-            a.u_in = (k == 0) ? g->u(cur0) : window_state(k);
-            a.u_out = (k + 1 < n) ? window_state(k + 1) : g->u(1 - cur0);
-            a.win = (k == 0) ? window_state(0) : nullptr;
+    int cur = cur0;
+    double2* in = g->u(cur0);
+    auto next_buffer = [&](int64_t knext) -> double2* {
+        if (win) return (knext < n) ? window_state(knext) : g->u(1 - cur0);
+        return g->u(1 - cur);
+    };
+    auto advance = [&](double2* out) {
+        if (!win) cur = 1 - cur;
+        in = out;
+    };
+    // Pairs of steps run as one two-step pass (not the first step of a
+    // window run, which also copies its input).
+    const bool two = g->steps_per_pass == 2 && (ne == 0 || g->fused_ext2);
+    StepArgs a2 = a;
+    a2.k.n_strips = (a2.k.nr + kStripCols2 - 1) / kStripCols2;
+    a2.k.n_ext = ne;
+    const int wpb2 = std::min(g->wpb, 4);
+    // Sample of state j (after step j) goes to series row j-1.  Launches
+    // with fused extraction sample their input (and a pass its intermediate
+    // state); otherwise a separate pass samples each new state.
+    const bool fused = g->fused_ext;
+    int64_t sampled = 0;
+    auto extract_state = [&](const double2* u, int64_t j) -> int {
+        HIP_TRY(launch_extract(u, g->L.pitch, ext, ne, series + (j - 1) * ne, g->stream));
+        sampled = j;
+        return TEUK_OK;
+    };
+    for (int64_t k = 0; k < n;) {
+        if (two && k + 2 <= n && !(win && k == 0)) {
+            double2* out = next_buffer(k + 2);
+            a2.u_in = in;
+            a2.u_out = out;
+            a2.win = win ? window_state(k + 1) : nullptr;
+            a2.series = (series && k > 0) ? series + (k - 1) * ne : nullptr;
+            a2.series_mid = series ? series + k * ne : nullptr;
+            HIP_TRY(launch_step2(a2, kerr, wpb2, g->stream));
+            if (series) sampled = k + 1;
+            advance(out);
+            k += 2;
+            g->steps += 2;
         } else {
-            a.u_in = g->u(g->cur);
-            a.u_out = g->u(1 - g->cur);
-            a.win = nullptr;
-            g->cur = 1 - g->cur;
+            if (series && !fused && k > sampled)
+                if (int rc = extract_state(in, k)) return rc;
+            double2* out = next_buffer(k + 1);
+            a.u_in = in;
+            a.u_out = out;
+            a.win = (win && k == 0) ? window_state(0) : nullptr;
+            a.series = (series && fused && k > 0) ? series + (k - 1) * ne : nullptr;
+            HIP_TRY(launch_step(a, kerr, g->wpb, g->stream));
+            if (series && fused && k > 0) sampled = k;
+            advance(out);
+            k += 1;
+            g->steps += 1;
+            if (series && !fused)
+                if (int rc = extract_state(out, k)) return rc;
         }
-        // fused: step k samples its input, i.e. the state after step k-1
-        a.series = (series && g->fused_ext && k > 0) ? series + (k - 1) * ne : nullptr;
-        HIP_TRY(launch_step(a, kerr, g->wpb, g->stream));
-        g->steps += 1;
-        if (series && !g->fused_ext) HIP_TRY(launch_extract(a.u_out, g->L.pitch, ext, ne, series + k * ne, g->stream));
     }
-    if (win) g->cur = 1 - cur0;
-    if (series && g->fused_ext)
-        HIP_TRY(launch_extract(g->u(g->cur), g->L.pitch, ext, ne, series + (n - 1) * ne, g->stream));
+    if (series && sampled < n)
+        if (int rc = extract_state(in, n)) return rc;
+    g->cur = win ? 1 - cur0 : cur;
     return TEUK_OK;
 }
 
@@ -508,7 +554,21 @@ int teuk_set_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per_block) 
         return fail(TEUK_E_INVALID_ARG, "waves_per_block=%d not in {1, 2, 4, 8}", waves_per_block);
     g->rows = rows_per_tile;
     g->wpb = waves_per_block;
-    g->fused_ext = fused_extraction_ok(g);
+    update_fusion(g);
+    return TEUK_OK;
+}
+
+int teuk_set_steps_per_pass(teuk_grid* g, int32_t steps_per_pass) {
+    if (int rc = check_grid(g)) return rc;
+    if (steps_per_pass != 1 && steps_per_pass != 2)
+        return fail(TEUK_E_INVALID_ARG, "steps_per_pass=%d not in {1, 2}", steps_per_pass);
+    g->steps_per_pass = steps_per_pass;
+    return TEUK_OK;
+}
+
+int teuk_get_steps_per_pass(const teuk_grid* g, int32_t* steps_per_pass) {
+    if (int rc = check_grid(g)) return rc;
+    if (steps_per_pass) *steps_per_pass = g->steps_per_pass;
     return TEUK_OK;
 }
 
@@ -682,10 +742,11 @@ struct teuk_batch {
     hipStream_t stream = nullptr;
     int device = 0;
     int rows = 16, wpb = 4, n_blocks = 0;
-    int total_tiles = 0;
+    int total_tiles = 0, total_tiles2 = 0;  // single-step and two-step work lists
+    int steps_per_pass = 2;
     int parity = 0;                 // which state buffer of every member is the input
     hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;  // two steps (parity 0 then 1)
+    hipGraphExec_t exec = nullptr;  // two launches (parity 0 then 1)
     hipStream_t cap = nullptr;      // private stream the graph is captured on
     int64_t steps = 0;
 };
@@ -713,7 +774,7 @@ void batch_drop_graph(teuk_batch* b) {
 // Descriptor table for the current tile rows; uploaded synchronously.
 int batch_upload(teuk_batch* b) {
     std::vector<BatchMember> d(b->members.size());
-    int tiles = 0;
+    int tiles = 0, tiles2 = 0;
     for (size_t k = 0; k < b->members.size(); ++k) {
         teuk_grid* g = b->members[k];
         g->rows = std::min<int>(b->rows, (int)g->p.ntheta);
@@ -727,28 +788,34 @@ int batch_upload(teuk_batch* b) {
         M.k.n_ext = 0;
         M.tile_begin = tiles;
         tiles += a.k.n_strips * a.k.n_chunks;
+        M.n_strips2 = (a.k.nr + kStripCols2 - 1) / kStripCols2;
+        M.tile_begin2 = tiles2;
+        tiles2 += M.n_strips2 * a.k.n_chunks;
     }
     b->total_tiles = tiles;
+    b->total_tiles2 = tiles2;
     HIP_TRY(hipMemcpyAsync(b->ws + b->desc_off, d.data(), d.size() * sizeof(BatchMember), hipMemcpyHostToDevice,
                            b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     return TEUK_OK;
 }
 
-int batch_launch(teuk_batch* b, int parity, hipStream_t s) {
-    const hipError_t e = launch_batch(reinterpret_cast<const BatchMember*>(b->ws + b->desc_off),
-                                      (int)b->members.size(), b->total_tiles, parity, b->n_blocks, b->wpb, s);
+int batch_launch(teuk_batch* b, int parity, bool two, hipStream_t s) {
+    const hipError_t e =
+        launch_batch(reinterpret_cast<const BatchMember*>(b->ws + b->desc_off), (int)b->members.size(),
+                     two ? b->total_tiles2 : b->total_tiles, parity, b->n_blocks, b->wpb, two, s);
     return e == hipSuccess ? TEUK_OK : fail(TEUK_E_HIP, "batched step launch failed: %s", hipGetErrorString(e));
 }
 
-// Capture two steps (parity 0, then 1) into a graph.  The capture runs on a
+// Capture two launches (parity 0, then 1; two or four steps) into a graph.  The capture runs on a
 // private stream (capturing the caller's stream may not be allowed, e.g. the
 // legacy default stream); the graph is launched on the caller's stream.
 int batch_capture(teuk_batch* b) {
     if (!b->cap) HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    const int rc0 = batch_launch(b, 0, b->cap);
-    const int rc1 = batch_launch(b, 1, b->cap);
+    const bool two = b->steps_per_pass == 2;
+    const int rc0 = batch_launch(b, 0, two, b->cap);
+    const int rc1 = batch_launch(b, 1, two, b->cap);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(b->cap, &graph);
     if (rc0 || rc1 || e != hipSuccess || !graph) {
@@ -813,7 +880,7 @@ int teuk_batch_init(const teuk_params* members, int32_t count, void* hip_stream,
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || cus < 1)
         cus = 256;
-    b->n_blocks = cus * 8 / b->wpb;  // two wavefronts per SIMD, four SIMDs per CU
+    b->n_blocks = cus * 4 / b->wpb;  // one wavefront per SIMD (the two-step kernel's occupancy)
     if (int rc = batch_upload(b)) {
         for (teuk_grid* m : b->members) teuk_free(m);
         delete b;
@@ -846,20 +913,21 @@ int teuk_batch_step_n(teuk_batch* b, int64_t n) {
     if (n < 0) return fail(TEUK_E_INVALID_ARG, "n=%lld < 0", (long long)n);
     if (n == 0) return TEUK_OK;
     if (int rc = set_device(b->members[0])) return rc;
+    // launches of `per` steps each flip the parity; whole graphs (two
+    // launches) start from parity 0; an odd last step runs alone
+    const int per = b->steps_per_pass;
     int64_t left = n;
-    if (b->parity == 1) {  // single step back to parity 0
-        if (int rc = batch_launch(b, 1, b->stream)) return rc;
-        b->parity = 0;
-        --left;
-    }
-    if (left >= 2) {
-        if (!b->exec)  // captured once per launch configuration
-            if (int rc = batch_capture(b)) return rc;
-        for (int64_t k = 0; k + 1 < left; k += 2) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
-    }
-    if (left % 2) {
-        if (int rc = batch_launch(b, 0, b->stream)) return rc;
-        b->parity = 1;
+    while (left > 0) {
+        if (b->parity == 0 && left >= 2 * per) {
+            if (!b->exec)  // captured once per launch configuration
+                if (int rc = batch_capture(b)) return rc;
+            for (; left >= 2 * per; left -= 2 * per) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+            continue;
+        }
+        const bool two = left >= per && per == 2;
+        if (int rc = batch_launch(b, b->parity, two, b->stream)) return rc;
+        b->parity = 1 - b->parity;
+        left -= two ? 2 : 1;
     }
     b->steps += n;
     for (teuk_grid* g : b->members) {
@@ -883,6 +951,18 @@ int teuk_batch_set_launch(teuk_batch* b, int32_t rows_per_tile, int32_t waves_pe
     b->wpb = waves_per_block;
     b->n_blocks = n_blocks;
     return batch_upload(b);
+}
+
+int teuk_batch_set_steps_per_pass(teuk_batch* b, int32_t steps_per_pass) {
+    if (int rc = batch_check(b, 0)) return rc;
+    if (steps_per_pass != 1 && steps_per_pass != 2)
+        return fail(TEUK_E_INVALID_ARG, "steps_per_pass=%d not in {1, 2}", steps_per_pass);
+    if (steps_per_pass == b->steps_per_pass) return TEUK_OK;
+    if (int rc = set_device(b->members[0])) return rc;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    batch_drop_graph(b);
+    b->steps_per_pass = steps_per_pass;
+    return TEUK_OK;
 }
 
 int teuk_batch_get_launch(const teuk_batch* b, int32_t* rows_per_tile, int32_t* waves_per_block,

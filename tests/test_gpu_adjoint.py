@@ -240,3 +240,37 @@ def test_full_workload_gradients_against_finite_differences(gpu):
 
     rich = (4 * cd(5e-4) - cd(1e-3)) / 3
     assert abs(rich - float(A.grad)) <= 1e-6 * abs(rich), (rich, float(A.grad))
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8])
+def test_window_two_step_identical(gpu, n):
+    """teuk_step_n_store with two steps per pass (intermediate states written
+    from registers) leaves the same window, state and series as one step per
+    pass, and the adjoint over it is unchanged."""
+    w = small_case(0.7, -2, 2, 150, 24, ext=((20.0, math.pi / 2),))
+    phi0, pi0 = inputs.random_state(150, 24, seed=91)
+    lam0 = inputs.random_state(150, 24, seed=92)
+    gser = np.ones((n, 1), dtype=np.complex128)
+    out = []
+    for spp in (1, 2):
+        g = _gpu_grid(gpu, w)
+        g.set_steps_per_pass(spp)
+        g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
+        win = g.new_window(n)
+        ser = g.step_store(n, win)
+        st = [t.cpu().numpy() for t in g.state()]
+        lp = torch.from_numpy(lam0[0].copy()).cuda()
+        lq = torch.from_numpy(lam0[1].copy()).cuda()
+        dlda = g.adjoint(n, lp, lq, torch.from_numpy(gser).cuda(), win)
+        raw = win.cpu().numpy()
+        slot = len(raw) // n
+        pitch = (150 + 7) // 8 * 8  # the library's row pitch: nr rounded up to 8
+        states = [raw[k * slot:k * slot + 2 * 24 * pitch * 16].view(np.complex128).reshape(2, 24, pitch)[:, :, :150]
+                  for k in range(n)]
+        out.append((np.stack(states), st, ser.cpu().numpy(), lp.cpu().numpy(), lq.cpu().numpy(), dlda))
+        g.close()
+    a, b = out
+    assert np.array_equal(a[0], b[0])
+    assert np.array_equal(a[1][0], b[1][0]) and np.array_equal(a[1][1], b[1][1])
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4])
+    assert a[5] == b[5]

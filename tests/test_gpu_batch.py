@@ -112,3 +112,23 @@ def test_autotuners_pick_valid_shapes(gpu, tmp_path, monkeypatch):
     res = autotune.tune_batch(b, rows=(8, 16), waves=(4,), blocks_per_cu=(1, 2), steps=3)
     assert b.launch() == (res["rows"], res["waves"], res["blocks"])
     b.close()
+
+
+def test_two_step_launches_identical(gpu):
+    """Two steps per launch (the default) against one step per launch, over
+    runs of odd and even lengths (parity changes, graph replays, a single
+    last step), bit for bit."""
+    mbs = _members()
+    data = [inputs.random_state(m["nr"], m["ntheta"], seed=300 + k) for k, m in enumerate(mbs)]
+    res = []
+    for spp in (1, 2):
+        b = gpu.TeukBatch(mbs)
+        b.set_steps_per_pass(spp)
+        for k, (p, q) in enumerate(data):
+            b.set_initial_data(k, torch.from_numpy(p).cuda(), torch.from_numpy(q).cuda())
+        for n in (1, 5, 2, 3, 4):
+            b.step(n)
+        res.append([[t.cpu().numpy() for t in b.state(k)] for k in range(len(mbs))])
+        b.close()
+    for k in range(len(mbs)):
+        assert np.array_equal(res[0][k][0], res[1][k][0]) and np.array_equal(res[0][k][1], res[1][k][1]), k

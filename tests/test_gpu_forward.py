@@ -177,3 +177,52 @@ def test_step_split_invariance_and_zero_steps(gpu):
     assert np.array_equal(phi, ref[0]) and np.array_equal(pi, ref[1])
     assert np.array_equal(np.concatenate(parts), ref[2])
     g.close()
+
+
+@pytest.mark.parametrize("a,s,m,nr,nth,n,tile", [
+    (0.7, -2, 2, 130, 20, 9, (16, 4)),   # ragged strips (130 = 2*60 + 10), odd n: a single last step
+    (0.9, 0, -3, 187, 70, 8, (16, 4)),   # odd |m|, five chunks with a ragged last one
+    (0.99, -1, 4, 64, 9, 6, (3, 2)),     # three-row chunks: halo rows from two chunks away
+    (0.5, 2, 0, 3, 2, 5, (1, 1)),        # smallest grid, one-row chunks
+    (0.3, -2, -2, 63, 2, 4, (2, 4)),     # both rows are pole rows
+    (0.8, -2, 1, 300, 41, 10, (41, 8)),  # one chunk; eight waves requested, four used
+])
+def test_two_step_passes_bit_identical(gpu, a, s, m, nr, nth, n, tile):
+    """Two steps per pass (temporal blocking) give exactly the single-step
+    results, state and extraction series included."""
+    w = small_case(a, s, m, nr, nth, ext=((20.0, math.pi / 2), (-12.0, 0.3)))
+    phi0, pi0 = inputs.random_state(nr, nth, seed=nr * 7 + nth)
+    one = run_gpu(gpu, w, phi0, pi0, n, tile=tile, steps_per_pass=1)
+    two = run_gpu(gpu, w, phi0, pi0, n, tile=tile, steps_per_pass=2)
+    for k in range(3):
+        assert np.array_equal(two[k], one[k]), k
+    o = run_oracle(w, phi0, pi0, n)
+    assert rel_err(two[0], o[0]) <= TOL
+    assert rel_err(two[2], o[2]) <= TOL
+
+
+def test_two_step_extraction_fallback(gpu):
+    """Two extraction points in one two-step tile: the pairs of steps fall
+    back to single steps with the separate extraction pass."""
+    w = small_case(0.6, -2, 2, 150, 24, ext=((20.0, math.pi / 2), (20.5, math.pi / 2 + 0.1), (-3.0, 1.0)))
+    phi0, pi0 = inputs.random_state(150, 24, seed=23)
+    one = run_gpu(gpu, w, phi0, pi0, 7, steps_per_pass=1)
+    two = run_gpu(gpu, w, phi0, pi0, 7, steps_per_pass=2)
+    for k in range(3):
+        assert np.array_equal(two[k], one[k]), k
+
+
+@pytest.mark.parametrize("name", ["kerr_a0.9_6400x256", "kerr_a0.99_25600x512"])
+def test_two_step_full_size(gpu, name):
+    """Full-size grids, two steps per pass, against the oracle."""
+    w = inputs.workload(name)
+    phi0, pi0 = inputs.initial_data(w)
+    rnd = inputs.random_state(w["nr"], w["ntheta"], seed=13)
+    phi0 = phi0 + 1e-3 * rnd[0]
+    pi0 = pi0 + 1e-3 * rnd[1]
+    g = run_gpu(gpu, w, phi0, pi0, 2, steps_per_pass=2)
+    o = run_oracle(w, phi0, pi0, 2)
+    assert rel_err(g[0], o[0]) <= TOL
+    assert rel_err(g[1], o[1]) <= TOL
+    if g[2] is not None:
+        assert rel_err(g[2], o[2]) <= TOL
