@@ -121,9 +121,10 @@ int64_t teuk_steps_taken(const teuk_grid* g);
 double teuk_get_dt(const teuk_grid* g);
 
 /* Launch shape of the step kernels: rows of theta per wavefront tile
- * (1..ntheta, default min(ntheta, 32)) and wavefronts per workgroup (1, 2,
- * 4 or 8, default 4).  Results do not depend on it (every point's
- * arithmetic is the same). */
+ * (1..ntheta) and wavefronts per workgroup (1, 2, 4 or 8).  The default is
+ * 32 rows and 4 wavefronts, with the rows halved (down to 8) while the grid
+ * has fewer than 1024 tiles (then 1 wavefront per workgroup).  Results do
+ * not depend on it (every point's arithmetic is the same). */
 int teuk_set_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per_block);
 int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per_block);
 

@@ -37,6 +37,11 @@ constexpr int kDppWaveShl1 = 0x130;
 #define TEUK_WAVES_PER_SIMD 2
 #endif
 constexpr int kRowsInFlight = TEUK_ROWS_IN_FLIGHT;
+// The same for the two-step pass.
+#ifndef TEUK_ROWS_IN_FLIGHT2
+#define TEUK_ROWS_IN_FLIGHT2 2
+#endif
+constexpr int kRowsInFlight2 = TEUK_ROWS_IN_FLIGHT2;
 constexpr int kDppWaveShr1 = 0x138;
 
 // bound_ctrl: a lane whose source lane does not exist reads 0, so the

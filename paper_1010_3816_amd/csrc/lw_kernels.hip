@@ -471,9 +471,9 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
 
     // ---- main sweep: A completes row r (reading row r+1 from the ring), B
     // completes row r-1 --------------------------------------------------
-    cd bp[kRowsInFlight], bq[kRowsInFlight];
+    cd bp[kRowsInFlight2], bq[kRowsInFlight2];
 #pragma unroll
-    for (int u = 0; u < kRowsInFlight; ++u) load_row(j0 + 2 + u, bp[u], bq[u]);
+    for (int u = 0; u < kRowsInFlight2; ++u) load_row(j0 + 2 + u, bp[u], bq[u]);
     Ang g_next = ang_row(j0 + 2);
 
     auto step_row = [&](int r, cd& rp, cd& rq) {
@@ -491,7 +491,7 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
             hbp_p = cscale(sg, a_cur.hbp);
             a_nxt = a_cur;  // unused: the sweep ends with this row
         }
-        load_row(r + 1 + kRowsInFlight, rp, rq);
+        load_row(r + 1 + kRowsInFlight2, rp, rq);
         cd vp, vq;
         out_row(r, a_cur, a_hbp_m, ubp_p, hbp_p, vp, vq);
         store_mid(r, vp, vq);
@@ -513,12 +513,12 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
     };
 
     int r0 = j0 + 1;
-    for (; r0 + kRowsInFlight - 1 <= aE; r0 += kRowsInFlight) {
+    for (; r0 + kRowsInFlight2 - 1 <= aE; r0 += kRowsInFlight2) {
 #pragma unroll
-        for (int u = 0; u < kRowsInFlight; ++u) step_row(r0 + u, bp[u], bq[u]);
+        for (int u = 0; u < kRowsInFlight2; ++u) step_row(r0 + u, bp[u], bq[u]);
     }
 #pragma unroll
-    for (int u = 0; u < kRowsInFlight; ++u)
+    for (int u = 0; u < kRowsInFlight2; ++u)
         if (r0 + u <= aE) step_row(r0 + u, bp[u], bq[u]);
 
     // the grid's last row: step B with the pole ghost row

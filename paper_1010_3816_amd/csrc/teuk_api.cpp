@@ -335,7 +335,17 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
     g->dr = dr;
     g->dth = dth;
     g->sigma = (std::abs(p->m) % 2 == 0) ? 1 : -1;
-    g->rows = std::min(nth, 32);
+    // Default tile: 32 rows, halved while the grid has fewer tiles than a
+    // wavefront per SIMD of the device (1024 on 256 CUs) would need; small
+    // grids then also take one wavefront per workgroup to spread over CUs.
+    {
+        const int strips2 = (nr + kStripCols2 - 1) / kStripCols2;
+        auto tiles = [&](int r) { return (int64_t)strips2 * ((nth + r - 1) / r); };
+        int r = std::min(nth, 32);
+        while (r > 8 && tiles(r) < 1024) r = (r + 1) / 2;
+        g->rows = r;
+        g->wpb = tiles(r) < 1024 ? 1 : 4;
+    }
     g->adj_rows = std::min(nth, 16);
     g->adj_chunks = (nth + g->adj_rows - 1) / g->adj_rows;
     g->adj_strips = ((int)p->nr + kStripCols - 1) / kStripCols;
