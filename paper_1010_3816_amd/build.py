@@ -9,8 +9,11 @@ SOURCES = ["lw_kernels.hip", "adjoint_kernels.hip", "teuk_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: no packed FP32 instructions are generated (all arithmetic
-# here is FP64 anyway).
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
+# here is FP64 anyway).  -ffp-contract=on: a multiply and an add are fused
+# only within one source expression, never across statements, so code shared
+# by several kernels rounds the same way in each of them (the one-step,
+# two-step and batched kernels give bit-identical results).
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-x", "hip"]
 

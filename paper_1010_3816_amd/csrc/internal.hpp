@@ -64,6 +64,7 @@ struct ExtPoint {
 struct StepScalars {
     int32_t nr, nth, pitch, sigma;
     int32_t rows, n_strips, n_chunks, n_ext;
+    int32_t zero, pad0;         // zero: always 0 (an opaque row offset of LDS reads)
     int64_t plane;              // nth * pitch: offset of the Pi plane in a state
     double dt, hdt, dt_dr, hdt_dr;
     double inv_dth2, inv_2dth;  // USER mode scalings

@@ -273,25 +273,72 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
 // valid on lanes 1..62 and B's on lanes 2..61, hence 60-column strips.
 // Boundary rules are those of one step: A's radial boundary columns are
 // zero before B reads them, and both sweeps use the pole ghost rows.
+// Both steps need the same coefficients at the same points: B takes those A
+// built one row earlier (the half-point set of row r, the integer-point set
+// of row r-1) instead of rebuilding them.  The wavefront's radial factors
+// live in its own LDS slice (rs: [integer/half][field][lane]), which frees
+// the registers the carried coefficients need.
 // Extraction is fused for both states a pass samples: the input (sample of
 // step n-1) and the intermediate state (sample of step n).
+typedef __attribute__((address_space(3))) double* lds_t;
+
 template <bool KERR>
 __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __restrict__ u_out, ctab_t rad,
                                             ctab_t ang, ctab_t uci, ctab_t uch, cext_t ext,
                                             double2* __restrict__ series_in, double2* __restrict__ series_mid,
-                                            gout_t __restrict__ u_mid, const StepScalars& A, int strip, int chunk,
-                                            int lane) {
+                                            gout_t __restrict__ u_mid, lds_t rs, const StepScalars& A, int strip,
+                                            int chunk, int lane) {
     const int nr = A.nr, nth = A.nth, P = A.pitch;
     const int col = strip * kStripCols2 - 2 + lane;
     const unsigned long long in = ((col >= 0) && (col < nr)) ? ~0ull : 0ull;
     const int ci = min(max(col, 0), nr - 1);
     const int hi = min(max(col, 0), nr - 2);
 
-    Rad Ri, Rh;
     if constexpr (KERR) {
-        Ri = load_rad(rad, P, 0, ci);
-        Rh = load_rad(rad, P, 1, hi);
+        // this wavefront's slice: lane-private values, written and read by
+        // the same lane, so no barrier is needed
+#pragma unroll
+        for (int f = 0; f < kNumRad; ++f) {
+            rs[(0 * kNumRad + f) * kWave + lane] = rad[((size_t)f * 2 + 0) * P + ci];
+            rs[(1 * kNumRad + f) * kWave + lane] = rad[((size_t)f * 2 + 1) * P + hi];
+        }
     }
+    // radial factors of this lane's column (kind 0) or half point (kind 1);
+    // the row-dependent zero offset keeps the reads next to their use
+    auto rad_lds = [&](int kind, int t) -> Rad {
+        const __attribute__((address_space(3))) double* r = rs + kind * kNumRad * kWave + lane + (t & A.zero);
+        Rad R;
+        R.rho = r[R_RHO * kWave];
+        R.rho2 = r[R_RHO2 * kWave];
+        R.a2d = r[R_A2D * kWave];
+        R.rb1 = r[R_RB1 * kWave];
+        R.rb2 = r[R_RB2 * kWave];
+        R.rb3 = r[R_RB3 * kWave];
+        R.ctr = r[R_CTR * kWave];
+        R.cti0 = r[R_CTI0 * kWave];
+        R.cti1 = r[R_CTI1 * kWave];
+        R.b1n = r[R_B1N * kWave];
+        R.dl2 = r[R_DL2 * kWave];
+        R.v0r = r[R_V0R * kWave];
+        R.v0i = r[R_V0I * kWave];
+        return R;
+    };
+    auto coef_h = [&](int t, const Ang& G) -> Coef {
+        if constexpr (KERR) {
+            const Rad R = rad_lds(1, t);
+            return kerr_coef(R, G, kerr_sigma(R, G));
+        } else {
+            return user_coef(uch, nth, P, t, hi, A.inv_dth2, A.inv_2dth);
+        }
+    };
+    auto coef_i = [&](int t, const Ang& G) -> Coef {
+        if constexpr (KERR) {
+            const Rad R = rad_lds(0, t);
+            return kerr_coef(R, G, kerr_sigma(R, G));
+        } else {
+            return user_coef(uci, nth, P, t, ci, A.inv_dth2, A.inv_2dth);
+        }
+    };
 
     const bool store_ok = (lane >= 2) && (lane <= kWave - 3) && (col < nr);
     const bool boundary = (col == 0) || (col == nr - 1);
@@ -334,9 +381,10 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
         return G;
     };
 
-    // Stage-1 pieces of row t (as in sweep_tile).  FULL = false: only the
-    // averages needed from a halo row.
-    auto fresh = [&](int t, cd p, cd q, cd ubp_prev, bool full, const Ang& G) -> Row {
+    // Stage-1 pieces of row t (as in sweep_tile) with the half-point
+    // coefficients kh of the row.  FULL = false: only the averages needed
+    // from a halo row.
+    auto fresh = [&](int t, cd p, cd q, cd ubp_prev, bool full, const Ang& G, const Coef& kh) -> Row {
         p = masked(p, in);
         q = masked(q, in);
         Row R;
@@ -347,20 +395,7 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
         R.ubp = cavg(p, pr);
         const cd ubq = cavg(q, qr);
         const cd dp = csub(pr, p);
-        Coef kh;
-        double bh;
-        if constexpr (KERR) {
-            if (full) {
-                kh = kerr_coef(Rh, G, kerr_sigma(Rh, G));
-                bh = kh.b;
-            } else {
-                bh = Rh.rho * kerr_sigma(Rh, G).isig;
-            }
-        } else {
-            kh = user_coef(uch, nth, P, t, hi, A.inv_dth2, A.inv_2dth);
-            bh = kh.b;
-        }
-        const double tb = A.hdt_dr * bh;
+        const double tb = A.hdt_dr * kh.b;
         const cd hp = {fma(-tb, dp.re, fma(A.hdt, ubq.re, R.ubp.re)), fma(-tb, dp.im, fma(A.hdt, ubq.im, R.ubp.im))};
         const cd hpl = from_left(hp);
         R.hbp = cavg(hp, hpl);
@@ -376,19 +411,14 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
         return R;
     };
 
-    // Stage 2 at (i, t): the new (Phi, Pi) of row t from its stage-1 state
-    // c, hbar_Phi of row t-1 and (ubar_Phi, hbar_Phi) of row t+1.
-    auto out_row = [&](int t, const Row& c, cd hbp_m, cd ubp_p, cd hbp_p, cd& np, cd& nq) {
+    // Stage 2 at (i, t) with the integer-point coefficients ki of row t: the
+    // new (Phi, Pi) of row t from its stage-1 state c, hbar_Phi of row t-1
+    // and (ubar_Phi, hbar_Phi) of row t+1.
+    auto out_row = [&](const Row& c, const Coef& ki, cd hbp_m, cd ubp_p, cd hbp_p, cd& np, cd& nq) {
         const cd hq = {fma(c.wp, ubp_p.re, c.x.re), fma(c.wp, ubp_p.im, c.x.im)};
         const cd hql = from_left(hq);
         const cd hbq = cavg(hq, hql);
         const cd dhq = csub(hq, hql);
-        Coef ki;
-        if constexpr (KERR) {
-            ki = kerr_coef(Ri, c.g, kerr_sigma(Ri, c.g));
-        } else {
-            ki = user_coef(uci, nth, P, t, ci, A.inv_dth2, A.inv_2dth);
-        }
         const double tb = A.dt_dr * ki.b;
         np = {fma(-tb, c.dhp.re, fma(A.dt, hbq.re, c.p.re)), fma(-tb, c.dhp.im, fma(A.dt, hbq.im, c.p.im))};
         const cd dq2 = d_pi(ki, c.dhp, dhq);
@@ -417,7 +447,11 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
 
     // ---- prologue: step A completes rows j0-1 (if j0 > 0) and j0; step B
     // takes them as its halo row and its first row ------------------------
+    // Carried between the sweeps: kh_a = half-point coefficients of A's
+    // current row (step B's next row), ki_b = integer-point coefficients of
+    // the row step B completes next.
     Row a_cur, b_cur;
+    Coef kh_a, ki_b;
     cd a_hbp_m, b_hbp_m;
     {
         cd p, q;
@@ -426,22 +460,30 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
         const int aS = max(j0 - 1, 0);
         if (aS > 0) {
             load_row(aS - 1, p, q);
-            const Row h = fresh(aS - 1, p, q, ubp_m, false, ang_row(aS - 1));
+            const Ang G = ang_row(aS - 1);
+            const Row h = fresh(aS - 1, p, q, ubp_m, false, G, coef_h(aS - 1, G));
             sample(aS - 1, h.p, acc_in);
             ubp_m = h.ubp;
             a_hbp_m = h.hbp;
         }
         load_row(aS, p, q);
-        a_cur = fresh(aS, p, q, ubp_m, true, ang_row(aS));
+        {
+            const Ang G = ang_row(aS);
+            kh_a = coef_h(aS, G);
+            a_cur = fresh(aS, p, q, ubp_m, true, G, kh_a);
+        }
         sample(aS, a_cur.p, acc_in);
         if (aS == 0) a_hbp_m = cscale(sg, a_cur.hbp);
         cd b_ubp_m = {0.0, 0.0};
         for (int r = aS; r <= j0; ++r) {  // one or two rows, wavefront-uniform
             Row a_nxt;
+            Coef kh_n;
             cd ubp_p, hbp_p;
             if (r + 1 < nth) {
                 load_row(r + 1, p, q);
-                a_nxt = fresh(r + 1, p, q, a_cur.ubp, true, ang_row(r + 1));
+                const Ang G = ang_row(r + 1);
+                kh_n = coef_h(r + 1, G);
+                a_nxt = fresh(r + 1, p, q, a_cur.ubp, true, G, kh_n);
                 sample(r + 1, a_nxt.p, acc_in);
                 ubp_p = a_nxt.ubp;
                 hbp_p = a_nxt.hbp;
@@ -449,23 +491,26 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
                 ubp_p = cscale(sg, a_cur.ubp);
                 hbp_p = cscale(sg, a_cur.hbp);
                 a_nxt = a_cur;
+                kh_n = kh_a;
             }
+            ki_b = coef_i(r, a_cur.g);
             cd vp, vq;
-            out_row(r, a_cur, a_hbp_m, ubp_p, hbp_p, vp, vq);
+            out_row(a_cur, ki_b, a_hbp_m, ubp_p, hbp_p, vp, vq);
             store_mid(r, vp, vq);
             const Ang gr = a_cur.g;
             a_hbp_m = a_cur.hbp;
             a_cur = a_nxt;
             if (r < j0) {  // step B's halo row j0-1
-                const Row h = fresh(r, vp, vq, b_ubp_m, false, gr);
+                const Row h = fresh(r, vp, vq, b_ubp_m, false, gr, kh_a);
                 sample(r, h.p, acc_mid);
                 b_ubp_m = h.ubp;
                 b_hbp_m = h.hbp;
             } else {
-                b_cur = fresh(r, vp, vq, b_ubp_m, true, gr);
+                b_cur = fresh(r, vp, vq, b_ubp_m, true, gr, kh_a);
                 sample(r, b_cur.p, acc_mid);
                 if (r == 0) b_hbp_m = cscale(sg, b_cur.hbp);
             }
+            kh_a = kh_n;
         }
     }
 
@@ -478,11 +523,13 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
 
     auto step_row = [&](int r, cd& rp, cd& rq) {
         Row a_nxt;
+        Coef kh_n;
         cd ubp_p, hbp_p;
         const Ang g1 = g_next;
         g_next = ang_row(r + 2);
         if (r + 1 < nth) {
-            a_nxt = fresh(r + 1, rp, rq, a_cur.ubp, true, g1);
+            kh_n = coef_h(r + 1, g1);
+            a_nxt = fresh(r + 1, rp, rq, a_cur.ubp, true, g1, kh_n);
             sample(r + 1, a_nxt.p, acc_in);
             ubp_p = a_nxt.ubp;
             hbp_p = a_nxt.hbp;
@@ -490,19 +537,21 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
             ubp_p = cscale(sg, a_cur.ubp);
             hbp_p = cscale(sg, a_cur.hbp);
             a_nxt = a_cur;  // unused: the sweep ends with this row
+            kh_n = kh_a;
         }
         load_row(r + 1 + kRowsInFlight2, rp, rq);
+        const Coef ki_r = coef_i(r, a_cur.g);
         cd vp, vq;
-        out_row(r, a_cur, a_hbp_m, ubp_p, hbp_p, vp, vq);
+        out_row(a_cur, ki_r, a_hbp_m, ubp_p, hbp_p, vp, vq);
         store_mid(r, vp, vq);
         const Ang gr = a_cur.g;
         a_hbp_m = a_cur.hbp;
         a_cur = a_nxt;
 
-        const Row b_nxt = fresh(r, vp, vq, b_cur.ubp, true, gr);
+        const Row b_nxt = fresh(r, vp, vq, b_cur.ubp, true, gr, kh_a);
         sample(r, b_nxt.p, acc_mid);
         cd wp, wq;
-        out_row(r - 1, b_cur, b_hbp_m, b_nxt.ubp, b_nxt.hbp, wp, wq);
+        out_row(b_cur, ki_b, b_hbp_m, b_nxt.ubp, b_nxt.hbp, wp, wq);
         if (store_ok) {
             const size_t o = (size_t)(r - 1) * P + col;
             st(u_out, o, wp);
@@ -510,6 +559,8 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
         }
         b_hbp_m = b_cur.hbp;
         b_cur = b_nxt;
+        kh_a = kh_n;
+        ki_b = ki_r;
     };
 
     int r0 = j0 + 1;
@@ -524,7 +575,7 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
     // the grid's last row: step B with the pole ghost row
     if (j1 == nth) {
         cd wp, wq;
-        out_row(nth - 1, b_cur, b_hbp_m, cscale(sg, b_cur.ubp), cscale(sg, b_cur.hbp), wp, wq);
+        out_row(b_cur, ki_b, b_hbp_m, cscale(sg, b_cur.ubp), cscale(sg, b_cur.hbp), wp, wq);
         if (store_ok) {
             const size_t o = (size_t)(nth - 1) * P + col;
             st(u_out, o, wp);
@@ -538,6 +589,10 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
     }
 }
 
+// LDS for the radial factors of the two-step kernels: one slice of
+// 2 x kNumRad x 64 doubles (13 KB) per wavefront, sized at launch.
+constexpr size_t kRadSliceBytes = 2 * kNumRad * kWave * sizeof(double);
+
 template <bool KERR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4)))
     lw_step2_kernel(const double2* __restrict__ u_in, double2* __restrict__ u_out, const double* __restrict__ rad,
@@ -549,9 +604,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))
     const int tile = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * wpb + (threadIdx.x / kWave));
     const int strip = tile % A.n_strips;
     const int chunk = tile / A.n_strips;
+    extern __shared__ double rad_s[];
     if (chunk >= A.n_chunks) return;  // tiles beyond the last
     sweep_tile2<KERR>((gin_t)u_in, (gout_t)u_out, (ctab_t)rad, (ctab_t)ang, (ctab_t)uci, (ctab_t)uch, (cext_t)ext,
-                      series_in, series_mid, (gout_t)u_mid, A, strip, chunk, lane);
+                      series_in, series_mid, (gout_t)u_mid,
+                      (lds_t)(rad_s + (threadIdx.x / kWave) * 2 * kNumRad * kWave), A, strip, chunk, lane);
 }
 
 template <bool KERR>
@@ -615,6 +672,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_W
 // members' two-step tiles.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4)))
     lw_batch2_kernel(const BatchMember* __restrict__ members, int n_members, int total_tiles, int parity) {
+    extern __shared__ double rad_s[];
+    const lds_t rs = (lds_t)(rad_s + (threadIdx.x / kWave) * 2 * kNumRad * kWave);
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
     const int nwaves = gridDim.x * wpb;
@@ -635,7 +694,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))
         const int strip = local % k.n_strips;
         const int chunk = local / k.n_strips;
         sweep_tile2<true>((gin_t)M.u[parity], (gout_t)M.u[1 - parity], (ctab_t)M.rad, (ctab_t)M.ang, nullptr,
-                          nullptr, nullptr, nullptr, nullptr, nullptr, k, strip, chunk, lane);
+                          nullptr, nullptr, nullptr, nullptr, nullptr, rs, k, strip, chunk, lane);
     }
 }
 
@@ -717,19 +776,21 @@ hipError_t launch_step2(const StepArgs& a, bool kerr, int waves_per_block, hipSt
     const int nb = (a.k.n_strips * a.k.n_chunks + waves_per_block - 1) / waves_per_block;
     const dim3 block(kWave * waves_per_block), grid(nb);
     auto kern = kerr ? lw_step2_kernel<true> : lw_step2_kernel<false>;
-    hipLaunchKernelGGL(kern, grid, block, 0, s, a.u_in, a.u_out, a.rad, a.ang, a.uci, a.uch, a.ext, a.series,
-                       a.series_mid, a.win, a.k);
+    hipLaunchKernelGGL(kern, grid, block, kerr ? waves_per_block * kRadSliceBytes : 0, s, a.u_in, a.u_out, a.rad, a.ang,
+                       a.uci, a.uch, a.ext, a.series, a.series_mid, a.win, a.k);
     return hipGetLastError();
 }
 
 hipError_t launch_batch(const BatchMember* members, int n_members, int total_tiles, int parity, int n_blocks,
                         int waves_per_block, bool two, hipStream_t s) {
-    if (two)
-        hipLaunchKernelGGL(lw_batch2_kernel, dim3(n_blocks), dim3(kWave * (waves_per_block < 4 ? waves_per_block : 4)), 0, s, members,
+    if (two) {
+        const int w = waves_per_block < 4 ? waves_per_block : 4;
+        hipLaunchKernelGGL(lw_batch2_kernel, dim3(n_blocks), dim3(kWave * w), w * kRadSliceBytes, s, members,
                            n_members, total_tiles, parity);
-    else
+    } else {
         hipLaunchKernelGGL(lw_batch_kernel, dim3(n_blocks), dim3(kWave * waves_per_block), 0, s, members, n_members,
                            total_tiles, parity);
+    }
     return hipGetLastError();
 }
 
