@@ -110,7 +110,7 @@ def _gpu_loss_and_grads(w, phi0, pi0, target, n, K, a=None):
     ser = evolve(P, Q, A, _cfg(w), n, K)
     L = ((ser - torch.from_numpy(target).cuda()).abs() ** 2).sum()
     L.backward()
-    return float(L), P.grad.cpu().numpy(), Q.grad.cpu().numpy(), float(A.grad), ser.detach().cpu().numpy()
+    return float(L.detach()), P.grad.cpu().numpy(), Q.grad.cpu().numpy(), float(A.grad), ser.detach().cpu().numpy()
 
 
 def test_autograd_against_oracle_reverse_pass(gpu):
