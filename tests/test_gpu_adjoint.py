@@ -215,7 +215,7 @@ def test_full_workload_gradients_against_finite_differences(gpu):
     A = torch.tensor(w["a"], dtype=torch.float64, device="cuda", requires_grad=True)
     L = ((evolve(P, Q, A, cfg, n, K) - target).abs() ** 2).sum()
     L.backward()
-    assert float(L) > 0 and float(A.grad) != 0.0
+    assert float(L.detach()) > 0 and float(A.grad) != 0.0
 
     def loss(dp, dq, a):
         with torch.no_grad():
