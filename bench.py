@@ -14,7 +14,7 @@ Prints one JSON line.  `value` is grid-point updates per second (one update
 = one (r*, theta) point advanced one full step).  `roofline` describes the
 dominant kernel, the two-step pass: it moves 64 algorithmic bytes per point
 per pass (Phi, Pi read and written once, complex128), i.e. 32 B per update,
-and executes about 222 FP64 flops per update (FMA = 2; counted from its
+and executes about 195 FP64 flops per update (FMA = 2; counted from its
 instruction stream, coefficient rebuild included), so with the state traffic
 halved its ceiling is FP64 arithmetic: `bound` "alu", peak 78.6 TFLOP/s;
 the HBM view is given beside it.  `batched` reports the 64-member uneven
@@ -39,7 +39,7 @@ METRIC = "FP64 grid-point updates/s + % HBM roofline; adjoint/forward time ratio
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 BYTES_PER_POINT_PASS = 64   # Phi, Pi read and written once per pass (complex128)
-FLOPS_PER_UPDATE = {1: 233, 2: 222}  # FP64 flops per point and step, single-step and two-step kernels
+FLOPS_PER_UPDATE = {1: 232, 2: 195}  # FP64 flops per point and step, single-step and two-step kernels
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1010_3816_amd", "csrc", f)
                for f in ("lw_kernels.hip", "device_common.hpp", "internal.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lw_step_kerr_a0.99_25600x512_traffic.txt")
