@@ -175,9 +175,27 @@ def adjoint_leg(n_steps=None, checkpoint_every=None):
         dlda = float(A.grad)
         P.grad = Q.grad = A.grad = None
     fwd, bwd = times[-1]
+    # the same loss, gradients with respect to the initial data only: no
+    # checkpoints, one cotangent sweep (nothing to recompute)
+    A0 = A.detach()
+    times0 = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ser = evolve(P, Q, A0, cfg, n_steps, checkpoint_every)
+        L0 = ((ser - target).abs() ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L0.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times0.append((t1 - t0, t2 - t1))
+        P.grad = Q.grad = None
+    fwd0, bwd0 = times0[-1]
     return {"workload": "adjoint_a0.7_6400x256", "steps": n_steps, "checkpoint_every": checkpoint_every,
             "extract": [w["extract_rstar"][0], w["extract_theta"][0]], "loss": float(L.detach()), "dL_da": dlda,
-            "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3, "ratio": bwd / fwd}
+            "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3, "ratio": bwd / fwd,
+            "initial_data_only": {"forward_ms": fwd0 * 1e3, "backward_ms": bwd0 * 1e3, "ratio": bwd0 / fwd0}}
 
 
 def main():

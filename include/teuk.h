@@ -198,6 +198,9 @@ int teuk_get_adjoint_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* w
  *       with respect to the series written by the forward call.
  *   flags: 0 or TEUK_ADJ_PROJECT_INITIAL.
  *   h_dL_da_accum: += this segment's part of dL/da (the call synchronises).
+ *       NULL: dL/da is not computed; the cotangents of the linear step do
+ *       not depend on the forward states, so d_window may then be NULL (it
+ *       is not read) and the call returns without synchronising.
  * Segments are processed last to first; the result of one is the input of
  * the previous one. */
 int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi, const void* d_dL_dseries,

@@ -9,6 +9,10 @@ library's adjoint over the segment (teuk_adjoint_step_n), which carries the
 cotangent of the state and accumulates dL/da.  Device memory: the
 checkpoints (one state per K steps) plus one window of K states.
 
+When the spin needs no gradient, no checkpoints are kept and the backward
+is one adjoint sweep over all steps: the cotangents of the linear step do
+not depend on the forward states, so nothing is recomputed.
+
 Gradients follow PyTorch's convention for complex tensors
 (dL/dRe + i dL/dIm).  All arithmetic runs in the library's HIP kernels; this
 module only moves tensors and handles between the calls.
@@ -41,12 +45,16 @@ class TeukEvolve(torch.autograd.Function):
             raise ValueError("the loss is a function of the extraction series: give extraction points")
         grid.set_initial_data(phi0.detach(), pi0.detach())
         series = torch.empty((n, grid.n_extract), dtype=torch.complex128, device=grid.device)
+        need_a = ctx.needs_input_grad[2]
         ckpts = []
-        for k in range(0, n, K):
-            m = min(K, n - k)
-            ckpts.append(grid.state())
-            binding.teuk_step_n(grid.handle, m, series[k:k + m])
-        ctx.grid, ctx.ckpts, ctx.n, ctx.K = grid, ckpts, n, K
+        if need_a:
+            for k in range(0, n, K):
+                m = min(K, n - k)
+                ckpts.append(grid.state())
+                binding.teuk_step_n(grid.handle, m, series[k:k + m])
+        else:
+            binding.teuk_step_n(grid.handle, n, series)
+        ctx.grid, ctx.ckpts, ctx.n, ctx.K, ctx.need_a = grid, ckpts, n, K, need_a
         ctx.a_meta = (a.dtype, a.device, a.shape)
         return series
 
@@ -54,19 +62,23 @@ class TeukEvolve(torch.autograd.Function):
     def backward(ctx, gseries):
         grid, n, K = ctx.grid, ctx.n, ctx.K
         grid.enable_adjoint()
-        window = grid.new_window(min(K, n))
         gseries = gseries.to(dtype=torch.complex128).contiguous()
         lam_phi = torch.zeros(grid.shape, dtype=torch.complex128, device=grid.device)
         lam_pi = torch.zeros_like(lam_phi)
-        dlda = 0.0
-        segs = [(k, min(K, n - k)) for k in range(0, n, K)]
-        for idx in range(len(segs) - 1, -1, -1):
-            k, m = segs[idx]
-            grid.set_initial_data(*ctx.ckpts[idx])
-            grid.step_store(m, window, series=False)
-            dlda += grid.adjoint(m, lam_phi, lam_pi, gseries[k:k + m], window, project_initial=(idx == 0))
-        dtype, device, shape = ctx.a_meta
-        grad_a = torch.full(shape, dlda, dtype=dtype, device=device)
+        grad_a = None
+        if ctx.need_a:
+            window = grid.new_window(min(K, n))
+            dlda = 0.0
+            segs = [(k, min(K, n - k)) for k in range(0, n, K)]
+            for idx in range(len(segs) - 1, -1, -1):
+                k, m = segs[idx]
+                grid.set_initial_data(*ctx.ckpts[idx])
+                grid.step_store(m, window, series=False)
+                dlda += grid.adjoint(m, lam_phi, lam_pi, gseries[k:k + m], window, project_initial=(idx == 0))
+            dtype, device, shape = ctx.a_meta
+            grad_a = torch.full(shape, dlda, dtype=dtype, device=device)
+        else:
+            grid.adjoint(n, lam_phi, lam_pi, gseries, None, project_initial=True, spin=False)
         ctx.grid = None
         ctx.ckpts = None
         grid.close()

@@ -253,12 +253,14 @@ def teuk_enable_adjoint(h, workspace):
     return _check(_lib.teuk_enable_adjoint(h, _dptr(workspace), workspace.numel() * workspace.element_size()))
 
 
-def teuk_adjoint_step_n(h, n, lam_phi, lam_pi, dseries, window, flags=0):
-    """Returns this segment's contribution to dL/da; lam_phi, lam_pi are updated in place."""
+def teuk_adjoint_step_n(h, n, lam_phi, lam_pi, dseries, window, flags=0, spin=True):
+    """Returns this segment's contribution to dL/da (None with spin=False, when
+    only the cotangents are computed and window may be None); lam_phi, lam_pi
+    are updated in place."""
     acc = ctypes.c_double(0.0)
     _check(_lib.teuk_adjoint_step_n(h, int(n), _dptr(lam_phi), _dptr(lam_pi), _dptr(dseries), _dptr(window),
-                                    int(flags), ctypes.byref(acc)))
-    return acc.value
+                                    int(flags), ctypes.byref(acc) if spin else None))
+    return acc.value if spin else None
 
 
 def _aligned_bytes(torch, nbytes, device):
@@ -358,15 +360,16 @@ class TeukGrid:
         teuk_step_n_store(self.handle, n, out, window)
         return out
 
-    def adjoint(self, n, lam_phi, lam_pi, dseries, window, project_initial=False):
-        """Reverse of n stored steps; updates (lam_phi, lam_pi) in place, returns the dL/da part."""
+    def adjoint(self, n, lam_phi, lam_pi, dseries, window, project_initial=False, spin=True):
+        """Reverse of n stored steps; updates (lam_phi, lam_pi) in place, returns the dL/da part
+        (spin=False: cotangents only, window may be None, returns None)."""
         self.enable_adjoint()
         if dseries is not None:
             dseries = self.torch.as_tensor(dseries, dtype=self.torch.complex128, device=self.device).contiguous()
             if tuple(dseries.shape) != (int(n), self.n_extract):
                 raise ValueError("dseries must have shape (n, n_extract)")
         flags = TEUK_ADJ_PROJECT_INITIAL if project_initial else 0
-        return teuk_adjoint_step_n(self.handle, n, lam_phi, lam_pi, dseries, window, flags)
+        return teuk_adjoint_step_n(self.handle, n, lam_phi, lam_pi, dseries, window, flags, spin)
 
     def check_finite(self):
         return teuk_check_finite(self.handle)

@@ -90,14 +90,26 @@ __device__ __forceinline__ cd cmul(double x, double y, cd v) {
 #define TEUK_ADJ_ROWS_IN_FLIGHT 1
 #endif
 constexpr int kAdjRowsInFlight = TEUK_ADJ_ROWS_IN_FLIGHT;
+// The cotangent-only kernel holds far fewer values per row.
+#ifndef TEUK_ADJ_ROWS_IN_FLIGHT_NOSPIN
+#define TEUK_ADJ_ROWS_IN_FLIGHT_NOSPIN 3
+#endif
 
-// Per-row state carried from the row's arrival to its completion.
-struct AdjRow {
-    // forward recompute of step m at this row
+// Per-row state carried from the row's arrival to its completion.  The
+// forward recompute is needed for the spin gradient only.
+template <bool SPIN>
+struct AdjFwd {
     cd ubp, ubq, dp, dq;  // half point i+1/2
     cd hbp, dhp;          // integer point i
     cd x;                 // stage-1 Pi value at the half, minus its row-(t+1) term
     double wp;
+};
+template <>
+struct AdjFwd<false> {};
+
+template <bool SPIN>
+struct AdjRow {
+    AdjFwd<SPIN> f;       // forward recompute of step m at this row
     // adjoint
     cd np, nq;            // nu at (i, t), radial boundary columns zeroed
     cd lhq;               // cotangent of the stage-1 Pi value at the half
@@ -108,12 +120,17 @@ struct AdjRow {
     Ang g;                // angular factors of the row (wavefront-uniform)
 };
 
+// SPIN = false: the cotangents only.  The step is linear in the state, so
+// they do not need u^m: no state rows are read, nothing of the forward step
+// is recomputed and no spin gradient is accumulated.
+template <bool SPIN>
 __global__ void __launch_bounds__(256)
     lw_adjoint_kernel(const double2* __restrict__ nu_in, const double2* __restrict__ u_in,
                       double2* __restrict__ lam_out, const double* __restrict__ rad,
                       const double* __restrict__ rad_da, const double* __restrict__ ang,
                       double* __restrict__ dlda_slots, const ExtPoint* __restrict__ ext,
                       const double* __restrict__ gsample, AdjScalars A) {
+    constexpr int kRIF = SPIN ? kAdjRowsInFlight : TEUK_ADJ_ROWS_IN_FLIGHT_NOSPIN;
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
     // a workgroup owns one strip and wpb consecutive theta chunks, so that it
@@ -130,7 +147,7 @@ __global__ void __launch_bounds__(256)
     const int hi = min(max(col, 0), nr - 2);
 
     __shared__ double rad_s[4 * kNumRad * kWave];
-    for (int f = wave; f < 4 * kNumRad; f += wpb) {
+    for (int f = wave; f < (SPIN ? 4 : 2) * kNumRad; f += wpb) {
         const int deriv = f / (2 * kNumRad), kind = (f / kNumRad) % 2, field = f % kNumRad;
         const double* src = deriv ? rad_da : rad;
         rad_s[f * kWave + lane] = src[((size_t)field * 2 + kind) * P + (kind == 0 ? ci : hi)];
@@ -163,34 +180,36 @@ __global__ void __launch_bounds__(256)
 
     // Arrival of row t: forward stage-1 pieces of u^m and the same-row part
     // of the transposed step applied to nu.
-    auto fresh = [&](int t, cd p, cd q, cd np, cd nq, cd ubp_prev, const Ang& G) -> AdjRow {
-        AdjRow R;
+    auto fresh = [&](int t, cd p, cd q, cd np, cd nq, cd ubp_prev, const Ang& G) -> AdjRow<SPIN> {
+        AdjRow<SPIN> R;
         Coef ki, kh;
         Sig si, sh;
         coefs(t, G, ki, kh, si, sh);
         R.si = si;
         R.sh = sh;
         R.g = G;
-        // forward (as in the step kernel)
-        p = masked(p, in);
-        q = masked(q, in);
-        const cd pr = from_right(p), qr = from_right(q);
-        R.ubp = cavg(p, pr);
-        R.ubq = cavg(q, qr);
-        R.dp = csub(pr, p);
-        R.dq = csub(qr, q);
-        const double tb = A.hdt_dr * kh.b;
-        const cd hp = {fma(-tb, R.dp.re, fma(A.hdt, R.ubq.re, R.ubp.re)),
-                       fma(-tb, R.dp.im, fma(A.hdt, R.ubq.im, R.ubp.im))};
-        const cd hpl = from_left(hp);
-        R.hbp = cavg(hp, hpl);
-        R.dhp = csub(hp, hpl);
-        const cd um = (t == 0) ? cscale(sg, R.ubp) : ubp_prev;
-        const cd dq1 = d_pi(kh, R.dp, R.dq);
-        const cd s1 = s_pi(kh, um, R.ubp, cd{0.0, 0.0}, R.ubq);
-        R.x = {fma(A.hdt, s1.re, fma(-A.hdt_dr, dq1.re, R.ubq.re)),
-               fma(A.hdt, s1.im, fma(-A.hdt_dr, dq1.im, R.ubq.im))};
-        R.wp = A.hdt * (kh.a2s + kh.a1s);
+        if constexpr (SPIN) {  // forward (as in the step kernel)
+            AdjFwd<true>& F = R.f;
+            p = masked(p, in);
+            q = masked(q, in);
+            const cd pr = from_right(p), qr = from_right(q);
+            F.ubp = cavg(p, pr);
+            F.ubq = cavg(q, qr);
+            F.dp = csub(pr, p);
+            F.dq = csub(qr, q);
+            const double tb = A.hdt_dr * kh.b;
+            const cd hp = {fma(-tb, F.dp.re, fma(A.hdt, F.ubq.re, F.ubp.re)),
+                           fma(-tb, F.dp.im, fma(A.hdt, F.ubq.im, F.ubp.im))};
+            const cd hpl = from_left(hp);
+            F.hbp = cavg(hp, hpl);
+            F.dhp = csub(hp, hpl);
+            const cd um = (t == 0) ? cscale(sg, F.ubp) : ubp_prev;
+            const cd dq1 = d_pi(kh, F.dp, F.dq);
+            const cd s1 = s_pi(kh, um, F.ubp, cd{0.0, 0.0}, F.ubq);
+            F.x = {fma(A.hdt, s1.re, fma(-A.hdt_dr, dq1.re, F.ubq.re)),
+                   fma(A.hdt, s1.im, fma(-A.hdt_dr, dq1.im, F.ubq.im))};
+            F.wp = A.hdt * (kh.a2s + kh.a1s);
+        }
         // adjoint, stage 2 at (i, t):
         //   Phi' = Phi + dt hbar_Pi - dt/dr b dh_Phi
         //   Pi'  = Pi - dt/dr (c dh_Phi - b dh_Pi) + dt S_Pi(hbar)
@@ -216,64 +235,79 @@ __global__ void __launch_bounds__(256)
         return R;
     };
 
+    // rows of u^m are read only for the spin gradient
+    auto ldu = [&](size_t o) -> cd {
+        if constexpr (SPIN) return ld(u_in, o);
+        return cd{0.0, 0.0};
+    };
+
     // ---- prologue ----------------------------------------------------------
-    AdjRow cur;
+    AdjRow<SPIN> cur;
     cd ubp_m, hbp_m, below, below_h;
     {
         cd ubp_prev = {0.0, 0.0};
         if (j0 > 0) {
             const size_t o = (size_t)(j0 - 1) * P + ci;
-            const AdjRow rm = fresh(j0 - 1, ld(u_in, o), ld(u_in, o + A.plane), ld(nu_in, o), ld(nu_in, o + A.plane),
-                                    ubp_prev, ang_row(j0 - 1));
-            ubp_prev = rm.ubp;
-            ubp_m = rm.ubp;
-            hbp_m = rm.hbp;
+            const AdjRow<SPIN> rm = fresh(j0 - 1, ldu(o), ldu(o + A.plane), ld(nu_in, o), ld(nu_in, o + A.plane),
+                                          ubp_prev, ang_row(j0 - 1));
+            if constexpr (SPIN) {
+                ubp_prev = rm.f.ubp;
+                ubp_m = rm.f.ubp;
+                hbp_m = rm.f.hbp;
+            }
             below = rm.up;
             below_h = rm.uph;
         }
         const size_t o = (size_t)j0 * P + ci;
-        cur = fresh(j0, ld(u_in, o), ld(u_in, o + A.plane), ld(nu_in, o), ld(nu_in, o + A.plane), ubp_prev,
-                    ang_row(j0));
+        cur = fresh(j0, ldu(o), ldu(o + A.plane), ld(nu_in, o), ld(nu_in, o + A.plane), ubp_prev, ang_row(j0));
         if (j0 == 0) {
-            ubp_m = cscale(sg, cur.ubp);
-            hbp_m = cscale(sg, cur.hbp);
+            if constexpr (SPIN) {
+                ubp_m = cscale(sg, cur.f.ubp);
+                hbp_m = cscale(sg, cur.f.hbp);
+            }
             below = cscale(sg, cur.dn);
             below_h = cscale(sg, cur.dnh);
         }
     }
     Ang g_next = ang_row(j0 + 1);  // angular factors one row ahead
-    cd bu[kAdjRowsInFlight][2], bn[kAdjRowsInFlight][2];
+    cd bu[kRIF][2], bn[kRIF][2];
 #pragma unroll
-    for (int k = 0; k < kAdjRowsInFlight; ++k) {
+    for (int k = 0; k < kRIF; ++k) {
         const size_t o = (size_t)min(j0 + 1 + k, last) * P + ci;
-        bu[k][0] = ld(u_in, o);
-        bu[k][1] = ld(u_in, o + A.plane);
+        bu[k][0] = ldu(o);
+        bu[k][1] = ldu(o + A.plane);
         bn[k][0] = ld(nu_in, o);
         bn[k][1] = ld(nu_in, o + A.plane);
     }
 
     auto finish_row = [&](int t, cd* ru, cd* rn) {
-        AdjRow nxt;
+        AdjRow<SPIN> nxt;
         cd ubp_p, hbp_p, above, above_h;
         const Ang g1 = g_next;
         g_next = ang_row(t + 2);
         if (t + 1 < nth) {
-            nxt = fresh(t + 1, ru[0], ru[1], rn[0], rn[1], cur.ubp, g1);
-            ubp_p = nxt.ubp;
-            hbp_p = nxt.hbp;
+            cd ubp_cur = {0.0, 0.0};
+            if constexpr (SPIN) ubp_cur = cur.f.ubp;
+            nxt = fresh(t + 1, ru[0], ru[1], rn[0], rn[1], ubp_cur, g1);
+            if constexpr (SPIN) {
+                ubp_p = nxt.f.ubp;
+                hbp_p = nxt.f.hbp;
+            }
             above = nxt.dn;
             above_h = nxt.dnh;
         } else {
-            ubp_p = cscale(sg, cur.ubp);
-            hbp_p = cscale(sg, cur.hbp);
+            if constexpr (SPIN) {
+                ubp_p = cscale(sg, cur.f.ubp);
+                hbp_p = cscale(sg, cur.f.hbp);
+            }
             above = cscale(sg, cur.up);
             above_h = cscale(sg, cur.uph);
             nxt = cur;  // unused: the sweep ends with this row
         }
         {
-            const size_t o = (size_t)min(t + 1 + kAdjRowsInFlight, last) * P + ci;
-            ru[0] = ld(u_in, o);
-            ru[1] = ld(u_in, o + A.plane);
+            const size_t o = (size_t)min(t + 1 + kRIF, last) * P + ci;
+            ru[0] = ldu(o);
+            ru[1] = ldu(o + A.plane);
             rn[0] = ld(nu_in, o);
             rn[1] = ld(nu_in, o + A.plane);
         }
@@ -287,12 +321,6 @@ __global__ void __launch_bounds__(256)
             ki = kerr_coef(rad_from_lds(rvi, o), G, si);
             kh = kerr_coef(rad_from_lds(rvh, o), G, sh);
         }
-
-        // forward stage-1 Pi value at the halves i+1/2, i-1/2 of row t
-        const cd hq = {fma(cur.wp, ubp_p.re, cur.x.re), fma(cur.wp, ubp_p.im, cur.x.im)};
-        const cd hql = from_left(hq);
-        const cd hbq = cavg(hq, hql);
-        const cd dhq = csub(hq, hql);
 
         // adjoint: hbar_Phi cotangent complete, then stage 1 transposed at the half
         const cd lhbp = cadd3(cur.mid, below, above);
@@ -335,19 +363,25 @@ __global__ void __launch_bounds__(256)
 
         // spin gradient: coefficient derivatives against the cotangents of
         // the stage outputs, at the owned half point and integer point
-        {
+        if constexpr (SPIN) {
+            // forward stage-1 Pi value at the halves i+1/2, i-1/2 of row t
+            const AdjFwd<true>& F = cur.f;
+            const cd hq = {fma(F.wp, ubp_p.re, F.x.re), fma(F.wp, ubp_p.im, F.x.im)};
+            const cd hql = from_left(hq);
+            const cd hbq = cavg(hq, hql);
+            const cd dhq = csub(hq, hql);
             const int o = t & A.zero;
             const Coef dkh = kerr_coef_da(rad_from_lds(rvh, o), rad_from_lds(rdh, o), G, sh, kh);
             const Coef dki = kerr_coef_da(rad_from_lds(rvi, o), rad_from_lds(rdi, o), G, si, ki);
             // half: dh_Phi = -dt/2dr db delta_Phi;  dh_Pi = -dt/2dr (dc dP - db dQ) + dt/2 dS(ubar)
-            const cd dhP = cscale(-A.hdt_dr * dkh.b, cur.dp);
-            const cd dd1 = d_pi(dkh, cur.dp, cur.dq);
-            const cd ds1 = s_pi(dkh, ubp_m, cur.ubp, ubp_p, cur.ubq);
+            const cd dhP = cscale(-A.hdt_dr * dkh.b, F.dp);
+            const cd dd1 = d_pi(dkh, F.dp, F.dq);
+            const cd ds1 = s_pi(dkh, ubp_m, F.ubp, ubp_p, F.ubq);
             const cd dhQ = {fma(A.hdt, ds1.re, -A.hdt_dr * dd1.re), fma(A.hdt, ds1.im, -A.hdt_dr * dd1.im)};
             // integer: dPhi' = -dt/dr db dh_Phi;  dPi' = -dt/dr (dc dhP - db dhQ) + dt dS(hbar)
-            const cd dPp = cscale(-A.dt_dr * dki.b, cur.dhp);
-            const cd dd2 = d_pi(dki, cur.dhp, dhq);
-            const cd ds2 = s_pi(dki, hbp_m, cur.hbp, hbp_p, hbq);
+            const cd dPp = cscale(-A.dt_dr * dki.b, F.dhp);
+            const cd dd2 = d_pi(dki, F.dhp, dhq);
+            const cd ds2 = s_pi(dki, hbp_m, F.hbp, hbp_p, hbq);
             const cd dQp = {fma(A.dt, ds2.re, -A.dt_dr * dd2.re), fma(A.dt, ds2.im, -A.dt_dr * dd2.im)};
             double c = lhp.re * dhP.re + lhp.im * dhP.im;
             c = fma(cur.lhq.re, dhQ.re, fma(cur.lhq.im, dhQ.im, c));
@@ -358,23 +392,27 @@ __global__ void __launch_bounds__(256)
 
         below = cur.up;
         below_h = cur.uph;
-        ubp_m = cur.ubp;
-        hbp_m = cur.hbp;
+        if constexpr (SPIN) {
+            ubp_m = cur.f.ubp;
+            hbp_m = cur.f.hbp;
+        }
         cur = nxt;
     };
 
     int t0 = j0;
-    for (; t0 + kAdjRowsInFlight <= j1; t0 += kAdjRowsInFlight) {
+    for (; t0 + kRIF <= j1; t0 += kRIF) {
 #pragma unroll
-        for (int k = 0; k < kAdjRowsInFlight; ++k) finish_row(t0 + k, bu[k], bn[k]);
+        for (int k = 0; k < kRIF; ++k) finish_row(t0 + k, bu[k], bn[k]);
     }
 #pragma unroll
-    for (int k = 0; k < kAdjRowsInFlight; ++k)
+    for (int k = 0; k < kRIF; ++k)
         if (t0 + k < j1) finish_row(t0 + k, bu[k], bn[k]);
 
     // fixed-order reduction over the wavefront, one slot per tile
-    for (int off = kWave / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, kWave);
-    if (lane == 0) dlda_slots[(size_t)chunk * A.n_strips + strip] += acc;
+    if constexpr (SPIN) {
+        for (int off = kWave / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+        if (lane == 0) dlda_slots[(size_t)chunk * A.n_strips + strip] += acc;
+    }
 }
 
 // lam_Phi += E^T g for every extraction point, in point order (one thread).
@@ -428,11 +466,12 @@ __global__ void zero_radial_boundary_kernel(double2* __restrict__ u, int nr, int
 
 }  // namespace
 
-hipError_t launch_adjoint(const AdjArgs& a, int waves_per_block, hipStream_t s) {
+hipError_t launch_adjoint(const AdjArgs& a, int waves_per_block, bool spin, hipStream_t s) {
     const int groups = (a.k.n_chunks + waves_per_block - 1) / waves_per_block;
     const dim3 block(kWave * waves_per_block), grid(a.k.n_strips * groups);
-    hipLaunchKernelGGL(lw_adjoint_kernel, grid, block, 0, s, a.nu_in, a.u_in, a.lam_out, a.rad, a.rad_da, a.ang,
-                       a.slots, a.ext, a.gsample, a.k);
+    auto kern = spin ? lw_adjoint_kernel<true> : lw_adjoint_kernel<false>;
+    hipLaunchKernelGGL(kern, grid, block, 0, s, a.nu_in, a.u_in, a.lam_out, a.rad, a.rad_da, a.ang, a.slots, a.ext,
+                       a.gsample, a.k);
     return hipGetLastError();
 }
 

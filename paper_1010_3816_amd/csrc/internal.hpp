@@ -130,7 +130,8 @@ hipError_t launch_import(const double2* src, double2* u, int f, int nr, int nth,
 hipError_t launch_export(const double2* u, double2* dst, int f, int nr, int nth, int pitch, hipStream_t s);
 hipError_t launch_extract(const double2* u, int pitch, const ExtPoint* pts, int n, double2* out, hipStream_t s);
 hipError_t launch_nonfinite(const double2* u, int nr, int nth, int pitch, int* flag, hipStream_t s);
-hipError_t launch_adjoint(const AdjArgs& a, int waves_per_block, hipStream_t s);
+// spin = false: cotangents only (u_in, rad_da and slots are not read).
+hipError_t launch_adjoint(const AdjArgs& a, int waves_per_block, bool spin, hipStream_t s);
 hipError_t launch_extract_adjoint(double2* lam, int pitch, const ExtPoint* pts, int n, const double2* g,
                                   hipStream_t s);
 hipError_t launch_reduce_slots(const double* slots, int n, double* out, hipStream_t s);

@@ -678,7 +678,10 @@ int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi
     if (!g->aws) return fail(TEUK_E_STATE, "teuk_enable_adjoint has not been called");
     if (n < 0) return fail(TEUK_E_INVALID_ARG, "n=%lld < 0", (long long)n);
     if (!d_lam_phi || !d_lam_pi) return fail(TEUK_E_INVALID_ARG, "cotangent pointers are NULL");
-    if (n > 0 && !d_window) return fail(TEUK_E_INVALID_ARG, "window is NULL");
+    // without a dL/da accumulator only the cotangents are computed, and they
+    // do not depend on the forward states (the step is linear)
+    const bool spin = h_dL_da_accum != nullptr;
+    if (n > 0 && spin && !d_window) return fail(TEUK_E_INVALID_ARG, "window is NULL");
     if (flags & ~TEUK_ADJ_PROJECT_INITIAL) return fail(TEUK_E_INVALID_ARG, "unknown flags 0x%x", flags);
     if (int rc = set_device(g)) return rc;
     const int nr = (int)g->p.nr, nth = (int)g->p.ntheta, P = g->L.pitch;
@@ -694,8 +697,10 @@ int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi
     int c = 0;
     HIP_TRY(launch_import(static_cast<const double2*>(d_lam_phi), lam(c), 0, nr, nth, P, s));
     HIP_TRY(launch_import(static_cast<const double2*>(d_lam_pi), lam(c), 1, nr, nth, P, s));
-    HIP_TRY(hipMemsetAsync(slots, 0, (size_t)nslots * sizeof(double), s));
-    HIP_TRY(hipMemsetAsync(sum, 0, sizeof(double), s));
+    if (spin) {
+        HIP_TRY(hipMemsetAsync(slots, 0, (size_t)nslots * sizeof(double), s));
+        HIP_TRY(hipMemsetAsync(sum, 0, sizeof(double), s));
+    }
     // the sample of the segment's last state
     if (gs && n > 0) HIP_TRY(launch_extract_adjoint(lam(c), P, ext, ne, gs + (n - 1) * ne, s));
     AdjArgs a{};
@@ -724,21 +729,22 @@ int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi
     const char* win = static_cast<const char*>(d_window);
     for (int64_t k = n - 1; k >= 0; --k) {
         a.nu_in = lam(c);
-        a.u_in = reinterpret_cast<const double2*>(win + (size_t)k * g->L.state);
+        a.u_in = spin ? reinterpret_cast<const double2*>(win + (size_t)k * g->L.state) : nullptr;
         a.lam_out = lam(1 - c);
         a.gsample = (gs && k >= 1 && fused) ? reinterpret_cast<const double*>(gs + (k - 1) * ne) : nullptr;
-        HIP_TRY(launch_adjoint(a, g->adj_wpb, s));
+        HIP_TRY(launch_adjoint(a, g->adj_wpb, spin, s));
         c = 1 - c;
         if (gs && k >= 1 && !fused) HIP_TRY(launch_extract_adjoint(lam(c), P, ext, ne, gs + (k - 1) * ne, s));
     }
     if (flags & TEUK_ADJ_PROJECT_INITIAL) HIP_TRY(launch_zero_radial_boundary(lam(c), nr, nth, P, s));
     HIP_TRY(launch_export(lam(c), static_cast<double2*>(d_lam_phi), 0, nr, nth, P, s));
     HIP_TRY(launch_export(lam(c), static_cast<double2*>(d_lam_pi), 1, nr, nth, P, s));
+    if (!spin) return TEUK_OK;  // asynchronous
     HIP_TRY(launch_reduce_slots(slots, nslots, sum, s));
     double h = 0.0;
     HIP_TRY(hipMemcpyAsync(&h, sum, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (h_dL_da_accum) *h_dL_da_accum += h;
+    *h_dL_da_accum += h;
     return TEUK_OK;
 }
 

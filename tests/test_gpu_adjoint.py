@@ -274,3 +274,44 @@ def test_window_two_step_identical(gpu, n):
     assert np.array_equal(a[1][0], b[1][0]) and np.array_equal(a[1][1], b[1][1])
     assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4])
     assert a[5] == b[5]
+
+
+def test_cotangent_only_adjoint(gpu):
+    """Without a dL/da accumulator the adjoint reads no forward states (the
+    window may be NULL) and gives bit-identical cotangents."""
+    n = 5
+    w = small_case(0.8, -2, 3, 187, 41, ext=((20.0, math.pi / 2), (-3.3, 0.4)))
+    phi0, pi0 = inputs.random_state(187, 41, seed=95)
+    lam0 = inputs.random_state(187, 41, seed=96)
+    rng = np.random.default_rng(97)
+    gser = torch.from_numpy(rng.standard_normal((n, 2)) + 1j * rng.standard_normal((n, 2))).cuda()
+    g = _gpu_grid(gpu, w)
+    g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
+    win = g.new_window(n)
+    g.step_store(n, win)
+    out = []
+    for spin, window in ((True, win), (False, None)):
+        lp = torch.from_numpy(lam0[0].copy()).cuda()
+        lq = torch.from_numpy(lam0[1].copy()).cuda()
+        r = g.adjoint(n, lp, lq, gser, window, project_initial=True, spin=spin)
+        assert (r is None) == (not spin)
+        out.append((lp.cpu().numpy(), lq.cpu().numpy()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    g.close()
+
+
+def test_autograd_without_spin_gradient(gpu):
+    """A spin that needs no gradient: no checkpoints, one adjoint sweep, and
+    the same initial-data gradients, bit for bit."""
+    from paper_1010_3816_amd.autograd import evolve
+
+    w, phi0, pi0, target, n = _train_case(45)
+    full = _gpu_loss_and_grads(w, phi0, pi0, target, n, K=10)
+    P = torch.from_numpy(phi0).cuda().requires_grad_(True)
+    Q = torch.from_numpy(pi0).cuda().requires_grad_(True)
+    A = torch.tensor(w["a"], dtype=torch.float64, device="cuda")
+    ser = evolve(P, Q, A, _cfg(w), n, 10)
+    L = ((ser - torch.from_numpy(target).cuda()).abs() ** 2).sum()
+    L.backward()
+    assert float(L.detach()) == full[0]
+    assert np.array_equal(P.grad.cpu().numpy(), full[1]) and np.array_equal(Q.grad.cpu().numpy(), full[2])
