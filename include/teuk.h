@@ -141,6 +141,13 @@ int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per
 int teuk_set_steps_per_pass(teuk_grid* g, int32_t steps_per_pass);
 int teuk_get_steps_per_pass(const teuk_grid* g, int32_t* steps_per_pass);
 
+/* Host-only: the Boyer-Lindquist radius r (M = 1) at tortoise coordinate
+ * rstar for spin a (the inverse of r*(r) of Sec. 3.2 as read here: r* = r +
+ * 2r+/(r+ - r-) ln((r - r+)/2) - 2r-/(r+ - r-) ln((r - r-)/2)), e.g. for the
+ * factor r^3 between Phi and Psi.  TEUK_E_INVALID_ARG for a outside [0, 1),
+ * a non-finite rstar or a NULL h_r. */
+int teuk_radius(double a, double rstar, double* h_r);
+
 /* Host-only: a time step for n_steps steps of this problem.  Returns
  * min(courant * dr, dt_g), where dt_g bounds the growth of the fastest
  * angular mode of the explicit scheme over n_steps to `growth` (for modes
@@ -207,11 +214,15 @@ int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi
                         const void* d_window, int32_t flags, double* h_dL_da_accum);
 
 /* ---- Batched evolutions ------------------------------------------------
- * Many independent grids (each its own a, s, m, nr, ntheta, r* range and dt;
- * TEUK_COEF_KERR, no extraction points) advanced together: one persistent
- * launch per step walks a single work list of all members' tiles, and runs
- * of two steps are replayed from a captured HIP graph.  Every member's
- * arithmetic is identical to that of a single grid with the same tile rows. */
+ * Many independent grids (each its own a, s, m, nr, ntheta, r* range, dt
+ * and extraction points; TEUK_COEF_KERR) advanced together: one persistent
+ * launch per pass walks a single work list of all members' tiles, and runs
+ * of two launches are replayed from a captured HIP graph.  Every member's
+ * arithmetic is identical to that of a single grid.  The azimuthal modes of
+ * one field are one use (Sec. 3.2: the m-modes evolve independently): a
+ * batch of modes m = -m_max .. m_max sampled with teuk_batch_extract gives
+ * the Phi_m whose sum e^{i m phi} r^3 Phi_m is the field Psi at an
+ * observer. */
 typedef struct teuk_batch teuk_batch;
 
 /* Device bytes for a batch of `count` members (0 if a member is invalid). */
@@ -228,6 +239,27 @@ int teuk_batch_get_state(teuk_batch* b, int32_t member, void* d_phi, void* d_pi)
 
 /* Advance every member by n >= 0 steps. */
 int teuk_batch_step_n(teuk_batch* b, int64_t n);
+
+/* Bilinear samples of Phi of every member's current state at its extraction
+ * points (as teuk_extract), all in one launch: d_out is complex128
+ * [teuk_batch_n_extract(b)], the points of member 0 first, each member's in
+ * the order of its extract_rstar/extract_theta.  Asynchronous on the batch
+ * stream.  TEUK_E_STATE if no member has extraction points. */
+int teuk_batch_extract(teuk_batch* b, void* d_out);
+int32_t teuk_batch_n_extract(const teuk_batch* b);
+
+/* The field from its azimuthal modes (Sec. 3.2: Psi = e^{i m phi} r^3 Phi
+ * for each mode, and the modes add): for every sample k and observer o,
+ *   psi[k][o] = r_o^3 * sum_j e^{i m_j phi_o} samples[k][j][o],
+ * modes summed in the given order.  h_m: the n_modes (<= 64) mode numbers;
+ * h_phi, h_r: the n_obs (<= 64) observers' azimuth and Boyer-Lindquist
+ * radius (teuk_radius).  d_samples: complex128 [n_samples][n_modes][n_obs]
+ * (the layout of teuk_batch_extract over a batch of one member per mode,
+ * each with the same observers); d_psi: complex128 [n_samples][n_obs].
+ * Asynchronous on hip_stream.  TEUK_E_INVALID_ARG for sizes out of range,
+ * NULL pointers or an observer with r <= 0. */
+int teuk_assemble_modes(int64_t n_samples, int32_t n_modes, const int32_t* h_m, int32_t n_obs, const double* h_phi,
+                        const double* h_r, const void* d_samples, void* d_psi, void* hip_stream);
 
 /* Launch shape: theta rows per tile, wavefronts per workgroup (1, 2, 4, 8)
  * and workgroups of the persistent launch.  Waits for queued work. */

@@ -84,6 +84,11 @@ def _load():
         "teuk_batch_step_n": (ctypes.c_int, [V, I64]),
         "teuk_batch_set_launch": (ctypes.c_int, [V, I32, I32, I32]),
         "teuk_batch_set_steps_per_pass": (ctypes.c_int, [V, I32]),
+        "teuk_batch_extract": (ctypes.c_int, [V, V]),
+        "teuk_batch_n_extract": (I32, [V]),
+        "teuk_radius": (ctypes.c_int, [D, D, ctypes.POINTER(D)]),
+        "teuk_assemble_modes": (ctypes.c_int, [I64, I32, ctypes.POINTER(I32), I32, ctypes.POINTER(D),
+                                               ctypes.POINTER(D), V, V, V]),
         "teuk_batch_get_launch": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "teuk_batch_total_points": (I64, [V]),
         "teuk_batch_free": (ctypes.c_int, [V]),
@@ -104,7 +109,8 @@ EXPORTED = ("teuk_workspace_bytes", "teuk_init_grid", "teuk_set_coefficients", "
             "teuk_set_steps_per_pass", "teuk_get_steps_per_pass", "teuk_batch_workspace_bytes", "teuk_batch_init",
             "teuk_batch_set_initial_data", "teuk_batch_get_state", "teuk_batch_step_n", "teuk_batch_set_launch",
             "teuk_batch_get_launch", "teuk_batch_total_points", "teuk_batch_free",
-            "teuk_batch_set_steps_per_pass")
+            "teuk_batch_set_steps_per_pass", "teuk_batch_extract", "teuk_batch_n_extract", "teuk_radius",
+            "teuk_assemble_modes")
 
 
 def _check(rc):
@@ -407,7 +413,8 @@ class TeukGrid:
 class TeukBatch:
     """Many grids advanced by one persistent launch per step (C ABI teuk_batch_*).
 
-    members: list of dicts with a, s, m, nr, ntheta, rstar_min, rstar_max, dt."""
+    members: list of dicts with a, s, m, nr, ntheta, rstar_min, rstar_max, dt and
+    optionally extract_rstar, extract_theta."""
 
     def __init__(self, members, device=None, stream=None):
         import torch
@@ -417,10 +424,13 @@ class TeukBatch:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.members = [dict(m) for m in members]
         arr = (teuk_params * len(members))()
+        keep = []
         for k, m in enumerate(members):
-            arr[k] = make_params(m["a"], m["s"], m["m"], m["nr"], m["ntheta"], m["rstar_min"], m["rstar_max"],
-                                 m["dt"])
-        self._arr = arr
+            p = make_params(m["a"], m["s"], m["m"], m["nr"], m["ntheta"], m["rstar_min"], m["rstar_max"], m["dt"],
+                            extract_rstar=m.get("extract_rstar", ()), extract_theta=m.get("extract_theta", ()))
+            keep.append(p._keep)  # the extraction coordinate arrays the copied structs point to
+            arr[k] = p
+        self._arr, self._keep = arr, keep
         nb = _lib.teuk_batch_workspace_bytes(arr, len(members))
         if nb == 0:
             raise TeukError(TEUK_E_INVALID_ARG, teuk_last_error())
@@ -461,6 +471,16 @@ class TeukBatch:
     def set_steps_per_pass(self, steps_per_pass):
         _check(_lib.teuk_batch_set_steps_per_pass(self.handle, int(steps_per_pass)))
 
+    def n_extract(self):
+        return int(_lib.teuk_batch_n_extract(self.handle))
+
+    def extract(self, out=None):
+        """Samples of all members' extraction points (complex128, member order)."""
+        if out is None:
+            out = self.torch.empty(self.n_extract(), dtype=self.torch.complex128, device=self.device)
+        _check(_lib.teuk_batch_extract(self.handle, _dptr(out)))
+        return out
+
     def launch(self):
         r, w, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(_lib.teuk_batch_get_launch(self.handle, ctypes.byref(r), ctypes.byref(w), ctypes.byref(b)))
@@ -479,6 +499,26 @@ class TeukBatch:
             self.close()
         except Exception:
             pass
+
+
+def teuk_radius(a, rstar):
+    """Boyer-Lindquist radius at tortoise coordinate rstar (M = 1)."""
+    r = ctypes.c_double()
+    _check(_lib.teuk_radius(float(a), float(rstar), ctypes.byref(r)))
+    return r.value
+
+
+def teuk_assemble_modes(samples, m_values, phi, r, psi, stream):
+    """psi[k][o] = r_o^3 sum_j e^{i m_j phi_o} samples[k][j][o] (device tensors)."""
+    m = np.ascontiguousarray(m_values, dtype=np.int32)
+    ph = np.ascontiguousarray(phi, dtype=np.float64)
+    rr = np.ascontiguousarray(r, dtype=np.float64)
+    n_samples = int(samples.shape[0]) if samples.dim() == 3 else 0
+    _check(_lib.teuk_assemble_modes(n_samples, int(m.size), m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                    int(ph.size), ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    rr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _dptr(samples), _dptr(psi),
+                                    ctypes.c_void_p(stream.cuda_stream)))
+    return psi
 
 
 def suggest_dt(a, s, m, nr, ntheta, rstar_min, rstar_max, n_steps, growth=10.0, courant=0.5):

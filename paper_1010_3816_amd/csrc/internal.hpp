@@ -96,6 +96,23 @@ struct BatchMember {
     int32_t pad;
 };
 
+// One extraction point of a batched evolution: the member's two state
+// buffers (the current one is selected by the batch parity) and its point.
+struct BatchExtPoint {
+    const double2* u[2];
+    int32_t pitch, pad;
+    ExtPoint e;
+};
+
+// Mode sum at observers: up to kMaxModes modes and kMaxObservers points.
+constexpr int kMaxModes = 64;
+constexpr int kMaxObservers = 64;
+struct AssembleArgs {
+    int32_t n_modes, n_obs;
+    int32_t m[kMaxModes];
+    double phi[kMaxObservers], r3[kMaxObservers];
+};
+
 // Scalar launch parameters of the adjoint kernel.
 struct AdjScalars {
     int32_t nr, nth, pitch, sigma;
@@ -129,6 +146,9 @@ hipError_t launch_batch(const BatchMember* members, int n_members, int total_til
 hipError_t launch_import(const double2* src, double2* u, int f, int nr, int nth, int pitch, hipStream_t s);
 hipError_t launch_export(const double2* u, double2* dst, int f, int nr, int nth, int pitch, hipStream_t s);
 hipError_t launch_extract(const double2* u, int pitch, const ExtPoint* pts, int n, double2* out, hipStream_t s);
+hipError_t launch_batch_extract(const BatchExtPoint* pts, int n, int parity, double2* out, hipStream_t s);
+hipError_t launch_assemble(const AssembleArgs& a, int64_t n_samples, const double2* samples, double2* psi,
+                           hipStream_t s);
 hipError_t launch_nonfinite(const double2* u, int nr, int nth, int pitch, int* flag, hipStream_t s);
 // spin = false: cotangents only (u_in, rad_da and slots are not read).
 hipError_t launch_adjoint(const AdjArgs& a, int waves_per_block, bool spin, hipStream_t s);

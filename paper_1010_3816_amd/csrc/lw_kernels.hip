@@ -721,11 +721,9 @@ __global__ void export_kernel(const double2* __restrict__ u, double2* __restrict
     dst[(size_t)j * nr + i] = u[(size_t)f * nth * pitch + (size_t)j * pitch + i];
 }
 
-__global__ void extract_kernel(const double2* __restrict__ u, int pitch, const ExtPoint* __restrict__ pts, int n,
-                               double2* __restrict__ out) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    const ExtPoint E = pts[e];
+// Bilinear sample of Phi at one extraction point (rows rowa, rowb with the
+// pole ghost signs folded into the weights).
+__device__ __forceinline__ double2 sample_point(const double2* __restrict__ u, int pitch, const ExtPoint& E) {
     auto row = [&](int j) {
         const double2 a = u[(size_t)j * pitch + E.col];
         const double2 b = u[(size_t)j * pitch + E.col + 1];
@@ -741,7 +739,44 @@ __global__ void extract_kernel(const double2* __restrict__ u, int pitch, const E
     double2 w;
     w.x = v.re;
     w.y = v.im;
-    out[e] = w;
+    return w;
+}
+
+__global__ void extract_kernel(const double2* __restrict__ u, int pitch, const ExtPoint* __restrict__ pts, int n,
+                               double2* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    out[e] = sample_point(u, pitch, pts[e]);
+}
+
+// Psi(t_k, observer o) = sum over modes j of e^{i m_j phi_o} r_o^3 Phi_{m_j}(t_k, o)
+// (the field from its azimuthal modes, Sec. 3.2); samples are
+// [n_samples][n_modes][n_obs], psi [n_samples][n_obs].  The modes are summed
+// in their given order.
+__global__ void assemble_kernel(AssembleArgs A, int64_t n_samples, const double2* __restrict__ samples,
+                                double2* __restrict__ psi) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n_samples * A.n_obs) return;
+    const int64_t k = id / A.n_obs;
+    const int o = (int)(id % A.n_obs);
+    double re = 0.0, im = 0.0;
+    for (int j = 0; j < A.n_modes; ++j) {
+        double sn, cs;
+        sincos(A.m[j] * A.phi[o], &sn, &cs);
+        const double2 f = samples[(k * A.n_modes + j) * A.n_obs + o];
+        re = fma(cs, f.x, fma(-sn, f.y, re));
+        im = fma(cs, f.y, fma(sn, f.x, im));
+    }
+    psi[id] = double2{A.r3[o] * re, A.r3[o] * im};
+}
+
+// Samples of every member's extraction points of a batch, in member order.
+__global__ void batch_extract_kernel(const BatchExtPoint* __restrict__ pts, int n, int parity,
+                                     double2* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const BatchExtPoint& P = pts[e];
+    out[e] = sample_point(P.u[parity], P.pitch, P.e);
 }
 
 __global__ void nonfinite_kernel(const double2* __restrict__ u, int nr, int nth, int pitch, int* flag) {
@@ -810,6 +845,22 @@ hipError_t launch_extract(const double2* u, int pitch, const ExtPoint* pts, int 
     if (n <= 0) return hipSuccess;
     const dim3 block(64), grid((n + 63) / 64);
     hipLaunchKernelGGL(extract_kernel, grid, block, 0, s, u, pitch, pts, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_extract(const BatchExtPoint* pts, int n, int parity, double2* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const dim3 block(64), grid((n + 63) / 64);
+    hipLaunchKernelGGL(batch_extract_kernel, grid, block, 0, s, pts, n, parity, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble(const AssembleArgs& a, int64_t n_samples, const double2* samples, double2* psi,
+                           hipStream_t s) {
+    const int64_t n = n_samples * a.n_obs;
+    if (n <= 0) return hipSuccess;
+    const dim3 block(256), grid((unsigned)((n + 255) / 256));
+    hipLaunchKernelGGL(assemble_kernel, grid, block, 0, s, a, n_samples, samples, psi);
     return hipGetLastError();
 }
 

@@ -276,6 +276,15 @@ size_t teuk_workspace_bytes(const teuk_params* p) {
     return make_layout(p).total;
 }
 
+int teuk_radius(double a, double rstar, double* h_r) {
+    if (!(a >= 0.0 && a < 1.0)) return fail(TEUK_E_INVALID_ARG, "spin a=%g outside [0, 1)", a);
+    if (!std::isfinite(rstar) || !h_r) return fail(TEUK_E_INVALID_ARG, "need a finite r* and an output pointer");
+    double x;
+    if (!tortoise_inverse(a, rstar, &x)) return fail(TEUK_E_INVALID_ARG, "tortoise inversion failed at r*=%g", rstar);
+    *h_r = 1.0 + std::sqrt(1.0 - a * a) + x;
+    return TEUK_OK;
+}
+
 int teuk_suggest_dt(const teuk_params* p, int64_t n_steps, double growth, double courant, double* h_dt) {
     if (validate(p) != TEUK_OK) return TEUK_E_INVALID_ARG;
     if (!h_dt) return fail(TEUK_E_INVALID_ARG, "h_dt is NULL");
@@ -754,6 +763,8 @@ struct teuk_batch {
     std::vector<teuk_grid*> members;
     std::vector<size_t> ws_off;     // member workspace offsets in the batch workspace
     size_t desc_off = 0;            // descriptor table offset
+    size_t ext_off = 0;             // extraction point table offset
+    int n_points = 0;               // extraction points of all members
     char* ws = nullptr;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -769,14 +780,19 @@ struct teuk_batch {
 
 namespace {
 
-size_t batch_layout(const teuk_params* members, int count, std::vector<size_t>* offs, size_t* desc_off) {
+size_t batch_layout(const teuk_params* members, int count, std::vector<size_t>* offs, size_t* desc_off,
+                    size_t* ext_off = nullptr) {
     size_t o = 0;
+    int64_t points = 0;
     for (int k = 0; k < count; ++k) {
         if (offs) offs->push_back(o);
         o += align_up(make_layout(&members[k]).total);
+        points += members[k].n_extract;
     }
     if (desc_off) *desc_off = o;
     o += align_up((size_t)count * sizeof(BatchMember));
+    if (ext_off) *ext_off = o;
+    o += align_up((size_t)std::max<int64_t>(points, 1) * sizeof(BatchExtPoint));
     return o;
 }
 
@@ -869,13 +885,11 @@ int teuk_batch_init(const teuk_params* members, int32_t count, void* hip_stream,
         if (int rc = validate(&members[k])) return rc;
         if (members[k].coef_mode != TEUK_COEF_KERR)
             return fail(TEUK_E_INVALID_ARG, "member %d: batched members use TEUK_COEF_KERR", k);
-        if (members[k].n_extract != 0)
-            return fail(TEUK_E_INVALID_ARG, "member %d: batched members take no extraction points", k);
     }
     if (!d_workspace || reinterpret_cast<uintptr_t>(d_workspace) % kAlign)
         return fail(TEUK_E_WORKSPACE, "batch workspace NULL or not %zu-byte aligned", kAlign);
     teuk_batch* b = new teuk_batch();
-    const size_t need = batch_layout(members, count, &b->ws_off, &b->desc_off);
+    const size_t need = batch_layout(members, count, &b->ws_off, &b->desc_off, &b->ext_off);
     if (bytes < need) {
         delete b;
         return fail(TEUK_E_WORKSPACE, "batch workspace has %zu bytes, needs %zu", bytes, need);
@@ -897,6 +911,29 @@ int teuk_batch_init(const teuk_params* members, int32_t count, void* hip_stream,
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || cus < 1)
         cus = 256;
     b->n_blocks = cus * 4 / b->wpb;  // one wavefront per SIMD (the two-step kernel's occupancy)
+    // the extraction points of all members, in member order
+    std::vector<BatchExtPoint> pts;
+    for (teuk_grid* g : b->members)
+        for (const ExtPoint& e : g->ext) {
+            BatchExtPoint q{};
+            q.u[0] = g->u(0);
+            q.u[1] = g->u(1);
+            q.pitch = g->L.pitch;
+            q.e = e;
+            pts.push_back(q);
+        }
+    b->n_points = (int)pts.size();
+    hipError_t e = hipSuccess;
+    if (!pts.empty()) {
+        e = hipMemcpyAsync(b->ws + b->ext_off, pts.data(), pts.size() * sizeof(BatchExtPoint), hipMemcpyHostToDevice,
+                           b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    }
+    if (e != hipSuccess) {
+        for (teuk_grid* m : b->members) teuk_free(m);
+        delete b;
+        return fail(TEUK_E_HIP, "uploading the extraction points: %s", hipGetErrorString(e));
+    }
     if (int rc = batch_upload(b)) {
         for (teuk_grid* m : b->members) teuk_free(m);
         delete b;
@@ -987,6 +1024,40 @@ int teuk_batch_get_launch(const teuk_batch* b, int32_t* rows_per_tile, int32_t* 
     if (rows_per_tile) *rows_per_tile = b->rows;
     if (waves_per_block) *waves_per_block = b->wpb;
     if (n_blocks) *n_blocks = b->n_blocks;
+    return TEUK_OK;
+}
+
+int teuk_batch_extract(teuk_batch* b, void* d_out) {
+    if (int rc = batch_check(b, 0)) return rc;
+    if (b->n_points == 0) return fail(TEUK_E_STATE, "no member has extraction points");
+    if (!d_out) return fail(TEUK_E_INVALID_ARG, "output pointer is NULL");
+    if (int rc = set_device(b->members[0])) return rc;
+    HIP_TRY(launch_batch_extract(reinterpret_cast<const BatchExtPoint*>(b->ws + b->ext_off), b->n_points, b->parity,
+                                 static_cast<double2*>(d_out), b->stream));
+    return TEUK_OK;
+}
+
+int32_t teuk_batch_n_extract(const teuk_batch* b) { return b ? b->n_points : -1; }
+
+int teuk_assemble_modes(int64_t n_samples, int32_t n_modes, const int32_t* h_m, int32_t n_obs, const double* h_phi,
+                        const double* h_r, const void* d_samples, void* d_psi, void* hip_stream) {
+    if (n_samples < 0) return fail(TEUK_E_INVALID_ARG, "n_samples=%lld < 0", (long long)n_samples);
+    if (n_modes < 1 || n_modes > kMaxModes) return fail(TEUK_E_INVALID_ARG, "n_modes=%d outside [1, %d]", n_modes, kMaxModes);
+    if (n_obs < 1 || n_obs > kMaxObservers) return fail(TEUK_E_INVALID_ARG, "n_obs=%d outside [1, %d]", n_obs, kMaxObservers);
+    if (!h_m || !h_phi || !h_r) return fail(TEUK_E_INVALID_ARG, "mode or observer arrays are NULL");
+    if (n_samples > 0 && (!d_samples || !d_psi)) return fail(TEUK_E_INVALID_ARG, "device pointers are NULL");
+    AssembleArgs a{};
+    a.n_modes = n_modes;
+    a.n_obs = n_obs;
+    for (int j = 0; j < n_modes; ++j) a.m[j] = h_m[j];
+    for (int o = 0; o < n_obs; ++o) {
+        if (!std::isfinite(h_phi[o]) || !std::isfinite(h_r[o]) || !(h_r[o] > 0.0))
+            return fail(TEUK_E_INVALID_ARG, "observer %d: need finite phi and r > 0", o);
+        a.phi[o] = h_phi[o];
+        a.r3[o] = h_r[o] * h_r[o] * h_r[o];
+    }
+    HIP_TRY(launch_assemble(a, n_samples, static_cast<const double2*>(d_samples), static_cast<double2*>(d_psi),
+                            reinterpret_cast<hipStream_t>(hip_stream)));
     return TEUK_OK;
 }
 

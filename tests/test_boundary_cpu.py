@@ -90,3 +90,31 @@ def test_suggest_dt_host_only(b):
     dt2 = b.suggest_dt(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"],
                        16 * w["steps"])
     assert dt2 == pytest.approx(dt / 2, rel=1e-12)
+
+
+def test_radius_and_mode_sum_validation():
+    """teuk_radius inverts the oracle's tortoise coordinate; the mode sum
+    rejects bad sizes and observers before any device work."""
+    import ctypes
+
+    import oracle
+    from paper_1010_3816_amd import binding as b
+
+    for a, rs in [(0.0, 10.0), (0.9, -50.0), (0.99, 500.0), (0.5, 3.0), (0.7, -100.0)]:
+        r = b.teuk_radius(a, rs)
+        r_oracle = 1.0 + math.sqrt(1.0 - a * a) + oracle.tortoise_x(a, rs)
+        assert abs(r - r_oracle) <= 4 * math.ulp(r_oracle), (a, rs, r, r_oracle)
+    with pytest.raises(b.TeukError):
+        b.teuk_radius(1.0, 5.0)
+    with pytest.raises(b.TeukError):
+        b.teuk_radius(0.5, float("nan"))
+    m = (ctypes.c_int32 * 2)(1, 2)
+    phi = (ctypes.c_double * 2)(0.0, 1.0)
+    r_ok = (ctypes.c_double * 2)(10.0, 20.0)
+    r_bad = (ctypes.c_double * 2)(10.0, 0.0)
+    lib = b._lib
+    assert lib.teuk_assemble_modes(1, 0, m, 2, phi, r_ok, None, None, None) == b.TEUK_E_INVALID_ARG
+    assert lib.teuk_assemble_modes(1, 2, m, 65, phi, r_ok, None, None, None) == b.TEUK_E_INVALID_ARG
+    assert lib.teuk_assemble_modes(1, 2, m, 2, phi, r_bad, None, None, None) == b.TEUK_E_INVALID_ARG
+    assert lib.teuk_assemble_modes(1, 2, m, 2, phi, r_ok, None, None, None) == b.TEUK_E_INVALID_ARG  # NULL tensors
+    assert lib.teuk_assemble_modes(0, 2, m, 2, phi, r_ok, None, None, None) == b.TEUK_OK  # nothing to do
