@@ -92,8 +92,11 @@ __device__ __forceinline__ cd cmul(double x, double y, cd v) {
 constexpr int kAdjRowsInFlight = TEUK_ADJ_ROWS_IN_FLIGHT;
 // The cotangent-only kernel holds far fewer values per row.
 #ifndef TEUK_ADJ_ROWS_IN_FLIGHT_NOSPIN
-#define TEUK_ADJ_ROWS_IN_FLIGHT_NOSPIN 3
+#define TEUK_ADJ_ROWS_IN_FLIGHT_NOSPIN 2
 #endif
+static_assert(TEUK_ADJ_ROWS_IN_FLIGHT == 1 || TEUK_ADJ_ROWS_IN_FLIGHT == 2, "the row loop takes rows in pairs");
+static_assert(TEUK_ADJ_ROWS_IN_FLIGHT_NOSPIN == 1 || TEUK_ADJ_ROWS_IN_FLIGHT_NOSPIN == 2,
+              "the row loop takes rows in pairs");
 
 // Per-row state carried from the row's arrival to its completion.  The
 // forward recompute is needed for the spin gradient only.
@@ -113,9 +116,8 @@ struct AdjRow {
     // adjoint
     cd np, nq;            // nu at (i, t), radial boundary columns zeroed
     cd lhq;               // cotangent of the stage-1 Pi value at the half
-    cd mid, up, dn;       // stage-2 theta-stencil pieces (to rows t, t+1, t-1)
-    cd ldhp;              // cotangent of dh_Phi at i
-    cd midh, uph, dnh;    // stage-1 theta-stencil pieces
+    cd up, dn;            // stage-2 theta-stencil pieces to rows t+1, t-1
+    cd uph, dnh;          // stage-1 theta-stencil pieces to rows t+1, t-1
     Sig si, sh;           // 1/Sigma, 1/Sigma^2 at the integer and half point
     Ang g;                // angular factors of the row (wavefront-uniform)
 };
@@ -216,12 +218,9 @@ __global__ void __launch_bounds__(256)
         R.np = masked(np, interior);
         R.nq = masked(nq, interior);
         const cd sq = cscale(A.dt, R.nq);                                   // cotangent of S_Pi(hbar)
-        R.mid = cmul(-2.0 * ki.a2s - ki.v0r, ki.v0i, sq);                   // (-2 A2 - conj V0) sq
         R.up = cscale(ki.a2s + ki.a1s, sq);
         R.dn = cscale(ki.a2s - ki.a1s, sq);
         const cd lhbq = cadd(cscale(A.dt, R.np), cmul(-ki.ctr, ki.cti, sq));  // + conj(-Ct) sq
-        const cd cnq = cmul(ki.cre, -ki.cim, R.nq);                          // conj(c) nq
-        R.ldhp = {-A.dt_dr * fma(ki.b, R.np.re, cnq.re), -A.dt_dr * fma(ki.b, R.np.im, cnq.im)};
         const cd ldhq = cscale(A.dt_dr * ki.b, R.nq);
         // hbar/dh -> half point i+1/2: own (1/2 hbar + dh) + right neighbour's (1/2 hbar - dh)
         const cd aq = {fma(0.5, lhbq.re, ldhq.re), fma(0.5, lhbq.im, ldhq.im)};
@@ -229,7 +228,6 @@ __global__ void __launch_bounds__(256)
         R.lhq = cadd(aq, from_right(bq));
         // stage 1 at (i+1/2, t): h_Pi = ubar_Pi - dt/2dr (c delta_Phi - b delta_Pi) + dt/2 S_Pi(ubar)
         const cd tq = cscale(A.hdt, R.lhq);
-        R.midh = cmul(-2.0 * kh.a2s - kh.v0r, kh.v0i, tq);
         R.uph = cscale(kh.a2s + kh.a1s, tq);
         R.dnh = cscale(kh.a2s - kh.a1s, tq);
         return R;
@@ -280,8 +278,9 @@ __global__ void __launch_bounds__(256)
         bn[k][1] = ld(nu_in, o + A.plane);
     }
 
-    auto finish_row = [&](int t, cd* ru, cd* rn) {
-        AdjRow<SPIN> nxt;
+    // Row t is in cur; row t+1 arrives into nxt (the two alternate roles
+    // from row to row, so no row state is copied).
+    auto finish_row = [&](int t, AdjRow<SPIN>& cur, AdjRow<SPIN>& nxt, cd* ru, cd* rn) {
         cd ubp_p, hbp_p, above, above_h;
         const Ang g1 = g_next;
         g_next = ang_row(t + 2);
@@ -323,12 +322,18 @@ __global__ void __launch_bounds__(256)
         }
 
         // adjoint: hbar_Phi cotangent complete, then stage 1 transposed at the half
-        const cd lhbp = cadd3(cur.mid, below, above);
-        const cd ap = {fma(0.5, lhbp.re, cur.ldhp.re), fma(0.5, lhbp.im, cur.ldhp.im)};
-        const cd bp = {fma(0.5, lhbp.re, -cur.ldhp.re), fma(0.5, lhbp.im, -cur.ldhp.im)};
+        // the row's own stage-2 theta piece and dh_Phi cotangent (rebuilt
+        // here rather than kept in registers since the row arrived)
+        const cd mid = cmul(-2.0 * ki.a2s - ki.v0r, ki.v0i, cscale(A.dt, cur.nq));  // (-2 A2 - conj V0) sq
+        const cd cnq = cmul(ki.cre, -ki.cim, cur.nq);                                // conj(c) nq
+        const cd ldhp = {-A.dt_dr * fma(ki.b, cur.np.re, cnq.re), -A.dt_dr * fma(ki.b, cur.np.im, cnq.im)};
+        const cd lhbp = cadd3(mid, below, above);
+        const cd ap = {fma(0.5, lhbp.re, ldhp.re), fma(0.5, lhbp.im, ldhp.im)};
+        const cd bp = {fma(0.5, lhbp.re, -ldhp.re), fma(0.5, lhbp.im, -ldhp.im)};
         const cd lhp = cadd(ap, from_right(bp));
         //   h_Phi = ubar_Phi + dt/2 ubar_Pi - dt/2dr b delta_Phi
-        const cd lubp = cadd(lhp, cadd3(cur.midh, below_h, above_h));
+        const cd midh = cmul(-2.0 * kh.a2s - kh.v0r, kh.v0i, cscale(A.hdt, cur.lhq));
+        const cd lubp = cadd(lhp, cadd3(midh, below_h, above_h));
         const cd ctq = cmul(-kh.ctr, kh.cti, cur.lhq);                      // conj(-Ct) lhq
         const cd lubq = {fma(A.hdt, lhp.re, fma(A.hdt, ctq.re, cur.lhq.re)),
                          fma(A.hdt, lhp.im, fma(A.hdt, ctq.im, cur.lhq.im))};
@@ -396,17 +401,16 @@ __global__ void __launch_bounds__(256)
             ubp_m = cur.f.ubp;
             hbp_m = cur.f.hbp;
         }
-        cur = nxt;
     };
 
+    // rows in pairs (the ring slot of row t+1 is (t - j0) mod kRIF)
+    AdjRow<SPIN> other;
     int t0 = j0;
-    for (; t0 + kRIF <= j1; t0 += kRIF) {
-#pragma unroll
-        for (int k = 0; k < kRIF; ++k) finish_row(t0 + k, bu[k], bn[k]);
+    for (; t0 + 2 <= j1; t0 += 2) {
+        finish_row(t0, cur, other, bu[0], bn[0]);
+        finish_row(t0 + 1, other, cur, bu[1 % kRIF], bn[1 % kRIF]);
     }
-#pragma unroll
-    for (int k = 0; k < kRIF; ++k)
-        if (t0 + k < j1) finish_row(t0 + k, bu[k], bn[k]);
+    if (t0 < j1) finish_row(t0, cur, other, bu[0], bn[0]);
 
     // fixed-order reduction over the wavefront, one slot per tile
     if constexpr (SPIN) {
