@@ -521,66 +521,69 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
     for (int u = 0; u < kRowsInFlight2; ++u) load_row(j0 + 2 + u, bp[u], bq[u]);
     Ang g_next = ang_row(j0 + 2);
 
-    auto step_row = [&](int r, cd& rp, cd& rq) {
-        Row a_nxt;
-        Coef kh_n;
+    // Step A completes row r (reading row r+1 from the ring), step B row
+    // r-1.  The row states (A's and B's rows, the carried coefficient sets)
+    // live in two copies that swap roles from row to row: ac/bc/khc/kic
+    // hold row r's, the next row's arrive in an/bn/khn/kin.
+    static_assert(kRowsInFlight2 == 2, "the row loop takes rows in pairs");
+    auto step_row = [&](int r, cd& rp, cd& rq, Row& ac, Row& an, Row& bc, Row& bn, Coef& khc, Coef& khn, Coef& kic,
+                        Coef& kin) {
         cd ubp_p, hbp_p;
         const Ang g1 = g_next;
         g_next = ang_row(r + 2);
         if (r + 1 < nth) {
-            kh_n = coef_h(r + 1, g1);
-            a_nxt = fresh(r + 1, rp, rq, a_cur.ubp, true, g1, kh_n);
-            sample(r + 1, a_nxt.p, acc_in);
-            ubp_p = a_nxt.ubp;
-            hbp_p = a_nxt.hbp;
+            khn = coef_h(r + 1, g1);
+            an = fresh(r + 1, rp, rq, ac.ubp, true, g1, khn);
+            sample(r + 1, an.p, acc_in);
+            ubp_p = an.ubp;
+            hbp_p = an.hbp;
         } else {
-            ubp_p = cscale(sg, a_cur.ubp);
-            hbp_p = cscale(sg, a_cur.hbp);
-            a_nxt = a_cur;  // unused: the sweep ends with this row
-            kh_n = kh_a;
+            ubp_p = cscale(sg, ac.ubp);
+            hbp_p = cscale(sg, ac.hbp);
+            an = ac;  // unused: the sweep ends with this row
+            khn = khc;
         }
         load_row(r + 1 + kRowsInFlight2, rp, rq);
-        const Coef ki_r = coef_i(r, a_cur.g);
+        kin = coef_i(r, ac.g);
         cd vp, vq;
-        out_row(a_cur, ki_r, a_hbp_m, ubp_p, hbp_p, vp, vq);
+        out_row(ac, kin, a_hbp_m, ubp_p, hbp_p, vp, vq);
         store_mid(r, vp, vq);
-        const Ang gr = a_cur.g;
-        a_hbp_m = a_cur.hbp;
-        a_cur = a_nxt;
+        a_hbp_m = ac.hbp;
 
-        const Row b_nxt = fresh(r, vp, vq, b_cur.ubp, true, gr, kh_a);
-        sample(r, b_nxt.p, acc_mid);
+        bn = fresh(r, vp, vq, bc.ubp, true, ac.g, khc);
+        sample(r, bn.p, acc_mid);
         cd wp, wq;
-        out_row(b_cur, ki_b, b_hbp_m, b_nxt.ubp, b_nxt.hbp, wp, wq);
+        out_row(bc, kic, b_hbp_m, bn.ubp, bn.hbp, wp, wq);
         if (store_ok) {
             const size_t o = (size_t)(r - 1) * P + col;
             st(u_out, o, wp);
             st(u_out, o + A.plane, wq);
         }
-        b_hbp_m = b_cur.hbp;
-        b_cur = b_nxt;
-        kh_a = kh_n;
-        ki_b = ki_r;
+        b_hbp_m = bc.hbp;
     };
-
-    int r0 = j0 + 1;
-    for (; r0 + kRowsInFlight2 - 1 <= aE; r0 += kRowsInFlight2) {
-#pragma unroll
-        for (int u = 0; u < kRowsInFlight2; ++u) step_row(r0 + u, bp[u], bq[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < kRowsInFlight2; ++u)
-        if (r0 + u <= aE) step_row(r0 + u, bp[u], bq[u]);
-
     // the grid's last row: step B with the pole ghost row
-    if (j1 == nth) {
+    auto last_row = [&](const Row& bc, const Coef& kic) {
         cd wp, wq;
-        out_row(b_cur, ki_b, b_hbp_m, cscale(sg, b_cur.ubp), cscale(sg, b_cur.hbp), wp, wq);
+        out_row(bc, kic, b_hbp_m, cscale(sg, bc.ubp), cscale(sg, bc.hbp), wp, wq);
         if (store_ok) {
             const size_t o = (size_t)(nth - 1) * P + col;
             st(u_out, o, wp);
             st(u_out, o + A.plane, wq);
         }
+    };
+
+    Row a_oth, b_oth;
+    Coef kh_oth, ki_oth;
+    int r0 = j0 + 1;
+    for (; r0 + 1 <= aE; r0 += 2) {
+        step_row(r0, bp[0], bq[0], a_cur, a_oth, b_cur, b_oth, kh_a, kh_oth, ki_b, ki_oth);
+        step_row(r0 + 1, bp[1], bq[1], a_oth, a_cur, b_oth, b_cur, kh_oth, kh_a, ki_oth, ki_b);
+    }
+    if (r0 <= aE) {
+        step_row(r0, bp[0], bq[0], a_cur, a_oth, b_cur, b_oth, kh_a, kh_oth, ki_b, ki_oth);
+        if (j1 == nth) last_row(b_oth, ki_oth);
+    } else if (j1 == nth) {
+        last_row(b_cur, ki_b);
     }
 
     if (e_id >= 0 && lane == e_lane) {
@@ -594,7 +597,7 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
 constexpr size_t kRadSliceBytes = 2 * kNumRad * kWave * sizeof(double);
 
 template <bool KERR>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4)))
     lw_step2_kernel(const double2* __restrict__ u_in, double2* __restrict__ u_out, const double* __restrict__ rad,
                     const double* __restrict__ ang, const double* __restrict__ uci, const double* __restrict__ uch,
                     const ExtPoint* __restrict__ ext, double2* __restrict__ series_in,
@@ -670,7 +673,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_W
 
 // The batched launch of the two-step pass: as lw_batch_kernel, over the
 // members' two-step tiles.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4)))
     lw_batch2_kernel(const BatchMember* __restrict__ members, int n_members, int total_tiles, int parity) {
     extern __shared__ double rad_s[];
     const lds_t rs = (lds_t)(rad_s + (threadIdx.x / kWave) * 2 * kNumRad * kWave);
