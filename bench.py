@@ -14,7 +14,7 @@ Prints one JSON line.  `value` is grid-point updates per second (one update
 = one (r*, theta) point advanced one full step).  `roofline` describes the
 dominant kernel, the two-step pass: it moves 64 algorithmic bytes per point
 per pass (Phi, Pi read and written once, complex128), i.e. 32 B per update,
-and executes about 195 FP64 flops per update (FMA = 2; counted from its
+and executes about 192 FP64 flops per update (FMA = 2; counted from its
 instruction stream, coefficient rebuild included), so with the state traffic
 halved its ceiling is FP64 arithmetic: `bound` "alu", peak 78.6 TFLOP/s;
 the HBM view is given beside it.  `batched` reports the 64-member uneven
@@ -39,7 +39,10 @@ METRIC = "FP64 grid-point updates/s + % HBM roofline; adjoint/forward time ratio
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 BYTES_PER_POINT_PASS = 64   # Phi, Pi read and written once per pass (complex128)
-FLOPS_PER_UPDATE = {1: 232, 2: 195}  # FP64 flops per point and step, single-step and two-step kernels
+FLOPS_PER_UPDATE = {1: 232, 2: 192}  # FP64 flops per point and step, single-step and two-step kernels
+VALU_PER_UPDATE = {1: 221, 2: 188}   # vector ALU instructions per point and step (steady-state loop)
+# vector instruction issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per 4 cycles per SIMD
+VALU_PEAK_T = 256 * 4 * 2.4e9 * 64 / 4 / 1e12
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1010_3816_amd", "csrc", f)
                for f in ("lw_kernels.hip", "device_common.hpp", "internal.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lw_step_kerr_a0.99_25600x512_traffic.txt")
@@ -275,12 +278,18 @@ def main():
     tflops = FLOPS_PER_UPDATE[spp] * spp * pts / launch_s / 1e12
     traffic = measured_traffic(args.workload, spp)
     rows, wpb = g.tile()
+    valu = VALU_PER_UPDATE[spp] * spp * pts / launch_s / 1e12
     if spp == 2:
         roof = {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": tflops / FP64_PEAK_TFLOPS, "traffic": traffic, "kernel": "lw_step2_kernel",
                 "flops_per_update": FLOPS_PER_UPDATE[2], "steps_per_launch": 2,
+                "valu_issue": {"achieved": valu, "peak": VALU_PEAK_T, "unit": "T lane-instructions/s",
+                               "frac": valu / VALU_PEAK_T, "instructions_per_update": VALU_PER_UPDATE[2]},
                 "hbm": {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_gbs / HBM_PEAK_GBS,
-                        "bytes_per_update": BYTES_PER_POINT_PASS / 2}}
+                        "bytes_per_update": BYTES_PER_POINT_PASS / 2,
+                        # the one-step-per-pass bound (64 B per update at 8 TB/s) and this run against it
+                        "one_step_bound_updates_per_s": HBM_PEAK_GBS * 1e9 / BYTES_PER_POINT_PASS,
+                        "value_over_one_step_bound": ups / (HBM_PEAK_GBS * 1e9 / BYTES_PER_POINT_PASS)}}
     else:
         roof = {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": traffic, "kernel": "lw_step_kernel",
