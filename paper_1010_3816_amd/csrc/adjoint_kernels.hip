@@ -419,6 +419,240 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// Two adjoint steps per pass, cotangents only (temporal blocking, as the
+// forward two-step pass): sweep A takes lambda^{m+2} row by row and
+// completes lambda^{m+1}, which goes from registers into sweep B, one row
+// behind, completing lambda^m.  A covers rows j0-1 .. j1 (reading
+// j0-2 .. j1+1), B writes j0 .. j1-1; A's results are valid on lanes 1..62
+// and B's on 2..61 (60-column strips).  Every quantity is formed by the same
+// expressions as in lw_adjoint_kernel<false>, so the results are identical.
+struct AdjCot {
+    cd np, nq;          // nu at (i, t), radial boundary columns zeroed
+    cd lhq;             // cotangent of the stage-1 Pi value at the half
+    cd up, dn;          // stage-2 theta-stencil pieces to rows t+1, t-1
+    cd uph, dnh;        // stage-1 theta-stencil pieces to rows t+1, t-1
+    Sig si, sh;         // 1/Sigma, 1/Sigma^2 at the integer and half point
+    Ang g;              // angular factors of the row (wavefront-uniform)
+};
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+    lw_adjoint2_kernel(const double2* __restrict__ nu_in, double2* __restrict__ lam_out, const double* __restrict__ rad, const double* __restrict__ ang,
+                       const ExtPoint* __restrict__ ext, const double* __restrict__ gsample_a,
+                       const double* __restrict__ gsample_b, AdjScalars A) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wpb = blockDim.x / kWave;
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
+    const int strip = bid % A.n_strips;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int chunk = (bid / A.n_strips) * wpb + wave;
+    const int nr = A.nr, nth = A.nth, P = A.pitch;
+    const int col = strip * kStripCols2 - 2 + lane;
+    const unsigned long long interior = ((col >= 1) && (col < nr - 1)) ? ~0ull : 0ull;
+    const int ci = min(max(col, 0), nr - 1);
+    const int hi = min(max(col, 0), nr - 2);
+
+    __shared__ double rad_s[2 * kNumRad * kWave];
+    for (int f = wave; f < 2 * kNumRad; f += wpb) {
+        const int kind = f / kNumRad, field = f % kNumRad;
+        rad_s[f * kWave + lane] = rad[((size_t)field * 2 + kind) * P + (kind == 0 ? ci : hi)];
+    }
+    __syncthreads();
+    if (chunk >= A.n_chunks) return;  // wavefront-uniform
+    lds_cptr rvi = (lds_cptr)(rad_s + 0 * kNumRad * kWave + lane);
+    lds_cptr rvh = (lds_cptr)(rad_s + 1 * kNumRad * kWave + lane);
+
+    const bool own = (lane >= 2) && (lane <= kWave - 3) && (col < nr);
+    const int j0 = chunk * A.rows;
+    const int j1 = min(j0 + A.rows, nth);
+    const int aE = min(j1, nth - 1);        // last row sweep A completes
+    const int last = min(aE + 1, nth - 1);  // last row of lambda^{m+2} read
+    const double sg = (double)A.sigma;
+
+    auto ang_row = [&](int t) -> Ang { return load_ang(ang, nth, min(t, nth - 1)); };
+    // arrival of a row (as fresh() of lw_adjoint_kernel<false>)
+    auto fresh = [&](int t, cd np, cd nq, const Ang& G) -> AdjCot {
+        AdjCot R;
+        const int o = t & A.zero;
+        const Rad Ri = rad_from_lds(rvi, o), Rh = rad_from_lds(rvh, o);
+        R.si = kerr_sigma(Ri, G);
+        R.sh = kerr_sigma(Rh, G);
+        const Coef ki = kerr_coef(Ri, G, R.si);
+        const Coef kh = kerr_coef(Rh, G, R.sh);
+        R.g = G;
+        R.np = masked(np, interior);
+        R.nq = masked(nq, interior);
+        const cd sq = cscale(A.dt, R.nq);
+        R.up = cscale(ki.a2s + ki.a1s, sq);
+        R.dn = cscale(ki.a2s - ki.a1s, sq);
+        const cd lhbq = cadd(cscale(A.dt, R.np), cmul(-ki.ctr, ki.cti, sq));
+        const cd ldhq = cscale(A.dt_dr * ki.b, R.nq);
+        const cd aq = {fma(0.5, lhbq.re, ldhq.re), fma(0.5, lhbq.im, ldhq.im)};
+        const cd bq = {fma(0.5, lhbq.re, -ldhq.re), fma(0.5, lhbq.im, -ldhq.im)};
+        R.lhq = cadd(aq, from_right(bq));
+        const cd tq = cscale(A.hdt, R.lhq);
+        R.uph = cscale(kh.a2s + kh.a1s, tq);
+        R.dnh = cscale(kh.a2s - kh.a1s, tq);
+        return R;
+    };
+    // completion of row t (as in lw_adjoint_kernel<false>): the new
+    // cotangent, plus E^T g of the output state's sample
+    auto finish = [&](int t, const AdjCot& cur, cd below, cd below_h, cd above, cd above_h, const double* gsample,
+                      cd& outp, cd& outq) {
+        Coef ki, kh;
+        {
+            const int o = t & A.zero;
+            ki = kerr_coef(rad_from_lds(rvi, o), cur.g, cur.si);
+            kh = kerr_coef(rad_from_lds(rvh, o), cur.g, cur.sh);
+        }
+        const cd mid = cmul(-2.0 * ki.a2s - ki.v0r, ki.v0i, cscale(A.dt, cur.nq));
+        const cd cnq = cmul(ki.cre, -ki.cim, cur.nq);
+        const cd ldhp = {-A.dt_dr * fma(ki.b, cur.np.re, cnq.re), -A.dt_dr * fma(ki.b, cur.np.im, cnq.im)};
+        const cd lhbp = cadd3(mid, below, above);
+        const cd ap = {fma(0.5, lhbp.re, ldhp.re), fma(0.5, lhbp.im, ldhp.im)};
+        const cd bp = {fma(0.5, lhbp.re, -ldhp.re), fma(0.5, lhbp.im, -ldhp.im)};
+        const cd lhp = cadd(ap, from_right(bp));
+        const cd midh = cmul(-2.0 * kh.a2s - kh.v0r, kh.v0i, cscale(A.hdt, cur.lhq));
+        const cd lubp = cadd(lhp, cadd3(midh, below_h, above_h));
+        const cd ctq = cmul(-kh.ctr, kh.cti, cur.lhq);
+        const cd lubq = {fma(A.hdt, lhp.re, fma(A.hdt, ctq.re, cur.lhq.re)),
+                         fma(A.hdt, lhp.im, fma(A.hdt, ctq.im, cur.lhq.im))};
+        const cd cq = cmul(kh.cre, -kh.cim, cur.lhq);
+        const cd ldp = {-A.hdt_dr * fma(kh.b, lhp.re, cq.re), -A.hdt_dr * fma(kh.b, lhp.im, cq.im)};
+        const cd ldq = cscale(A.hdt_dr * kh.b, cur.lhq);
+        const cd cP = {fma(0.5, lubp.re, ldp.re), fma(0.5, lubp.im, ldp.im)};
+        const cd cQ = {fma(0.5, lubq.re, ldq.re), fma(0.5, lubq.im, ldq.im)};
+        const cd dP = {fma(0.5, lubp.re, -ldp.re), fma(0.5, lubp.im, -ldp.im)};
+        const cd dQ = {fma(0.5, lubq.re, -ldq.re), fma(0.5, lubq.im, -ldq.im)};
+        outp = cadd3(cur.np, dP, from_left(cP));
+        outq = cadd3(cur.nq, dQ, from_left(cQ));
+        if (gsample != nullptr) {
+            for (int e = 0; e < A.n_ext; ++e) {
+                const ExtPoint E = ext[e];
+                if (t != E.rowa && t != E.rowb) continue;  // wavefront-uniform
+                const double wrow = (t == E.rowa) ? E.wa : E.wb;
+                const double w = (col == E.col) ? wrow * (1.0 - E.wr) : (col == E.col + 1) ? wrow * E.wr : 0.0;
+                outp.re = fma(w, gsample[2 * e], outp.re);
+                outp.im = fma(w, gsample[2 * e + 1], outp.im);
+            }
+        }
+    };
+    auto load_row = [&](int t, cd& p, cd& q) {
+        const size_t o = (size_t)min(max(t, 0), last) * P + ci;
+        p = ld(nu_in, o);
+        q = ld(nu_in, o + A.plane);
+    };
+
+    // ---- prologue: A completes rows j0-1 (if j0 > 0) and j0; B takes them
+    // as its halo row and its first row -------------------------------------
+    AdjCot a_cur, b_cur;
+    cd a_below, a_below_h, b_below, b_below_h;
+    {
+        cd p, q;
+        const int aS = max(j0 - 1, 0);
+        if (aS > 0) {
+            load_row(aS - 1, p, q);
+            const AdjCot h = fresh(aS - 1, p, q, ang_row(aS - 1));
+            a_below = h.up;
+            a_below_h = h.uph;
+        }
+        load_row(aS, p, q);
+        a_cur = fresh(aS, p, q, ang_row(aS));
+        if (aS == 0) {
+            a_below = cscale(sg, a_cur.dn);
+            a_below_h = cscale(sg, a_cur.dnh);
+        }
+        for (int r = aS; r <= j0; ++r) {  // one or two rows, wavefront-uniform
+            AdjCot a_nxt;
+            cd above, above_h;
+            if (r + 1 < nth) {
+                load_row(r + 1, p, q);
+                a_nxt = fresh(r + 1, p, q, ang_row(r + 1));
+                above = a_nxt.dn;
+                above_h = a_nxt.dnh;
+            } else {
+                above = cscale(sg, a_cur.up);
+                above_h = cscale(sg, a_cur.uph);
+                a_nxt = a_cur;
+            }
+            cd vp, vq;
+            finish(r, a_cur, a_below, a_below_h, above, above_h, gsample_a, vp, vq);
+            a_below = a_cur.up;
+            a_below_h = a_cur.uph;
+            const Ang gr = a_cur.g;
+            a_cur = a_nxt;
+            if (r < j0) {  // B's halo row j0-1
+                const AdjCot h = fresh(r, vp, vq, gr);
+                b_below = h.up;
+                b_below_h = h.uph;
+            } else {
+                b_cur = fresh(r, vp, vq, gr);
+                if (r == 0) {
+                    b_below = cscale(sg, b_cur.dn);
+                    b_below_h = cscale(sg, b_cur.dnh);
+                }
+            }
+        }
+    }
+
+    // ---- main sweep: A completes row r, B row r-1; the row states swap
+    // roles from row to row instead of being copied --------------------------
+    cd rp[2], rq[2];
+    load_row(j0 + 2, rp[0], rq[0]);
+    load_row(j0 + 3, rp[1], rq[1]);
+    Ang g_next = ang_row(j0 + 2);
+    auto step_row = [&](int r, cd& lp, cd& lq, AdjCot& ac, AdjCot& an, AdjCot& bc, AdjCot& bn) {
+        cd above, above_h;
+        const Ang g1 = g_next;
+        g_next = ang_row(r + 2);
+        if (r + 1 < nth) {
+            an = fresh(r + 1, lp, lq, g1);
+            above = an.dn;
+            above_h = an.dnh;
+        } else {
+            above = cscale(sg, ac.up);
+            above_h = cscale(sg, ac.uph);
+            an = ac;  // unused: the sweep ends with this row
+        }
+        load_row(r + 3, lp, lq);
+        cd vp, vq;
+        finish(r, ac, a_below, a_below_h, above, above_h, gsample_a, vp, vq);
+        a_below = ac.up;
+        a_below_h = ac.uph;
+
+        bn = fresh(r, vp, vq, ac.g);
+        cd wp, wq;
+        finish(r - 1, bc, b_below, b_below_h, bn.dn, bn.dnh, gsample_b, wp, wq);
+        if (own) {
+            const size_t o = (size_t)(r - 1) * P + col;
+            st(lam_out, o, wp);
+            st(lam_out, o + A.plane, wq);
+        }
+        b_below = bc.up;
+        b_below_h = bc.uph;
+    };
+    auto last_row = [&](const AdjCot& bc) {  // the grid's last row: B with the pole ghost row
+        cd wp, wq;
+        finish(nth - 1, bc, b_below, b_below_h, cscale(sg, bc.up), cscale(sg, bc.uph), gsample_b, wp, wq);
+        if (own) {
+            const size_t o = (size_t)(nth - 1) * P + col;
+            st(lam_out, o, wp);
+            st(lam_out, o + A.plane, wq);
+        }
+    };
+    AdjCot a_oth, b_oth;
+    int r0 = j0 + 1;
+    for (; r0 + 1 <= aE; r0 += 2) {
+        step_row(r0, rp[0], rq[0], a_cur, a_oth, b_cur, b_oth);
+        step_row(r0 + 1, rp[1], rq[1], a_oth, a_cur, b_oth, b_cur);
+    }
+    if (r0 <= aE) {
+        step_row(r0, rp[0], rq[0], a_cur, a_oth, b_cur, b_oth);
+        if (j1 == nth) last_row(b_oth);
+    } else if (j1 == nth) {
+        last_row(b_cur);
+    }
+}
+
 // lam_Phi += E^T g for every extraction point, in point order (one thread).
 __global__ void extract_adjoint_kernel(double2* __restrict__ lam, int pitch, const ExtPoint* __restrict__ pts, int n,
                                        const double2* __restrict__ g) {
@@ -476,6 +710,14 @@ hipError_t launch_adjoint(const AdjArgs& a, int waves_per_block, bool spin, hipS
     auto kern = spin ? lw_adjoint_kernel<true> : lw_adjoint_kernel<false>;
     hipLaunchKernelGGL(kern, grid, block, 0, s, a.nu_in, a.u_in, a.lam_out, a.rad, a.rad_da, a.ang, a.slots, a.ext,
                        a.gsample, a.k);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint2(const AdjArgs& a, const double* gsample_b, int waves_per_block, hipStream_t s) {
+    const int groups = (a.k.n_chunks + waves_per_block - 1) / waves_per_block;
+    const dim3 block(kWave * waves_per_block), grid(a.k.n_strips * groups);
+    hipLaunchKernelGGL(lw_adjoint2_kernel, grid, block, 0, s, a.nu_in, a.lam_out, a.rad, a.ang, a.ext, a.gsample,
+                       gsample_b, a.k);
     return hipGetLastError();
 }
 

@@ -152,6 +152,10 @@ hipError_t launch_assemble(const AssembleArgs& a, int64_t n_samples, const doubl
 hipError_t launch_nonfinite(const double2* u, int nr, int nth, int pitch, int* flag, hipStream_t s);
 // spin = false: cotangents only (u_in, rad_da and slots are not read).
 hipError_t launch_adjoint(const AdjArgs& a, int waves_per_block, bool spin, hipStream_t s);
+// Two cotangent-only adjoint steps: nu_in = lambda^{m+2} -> lam_out = lambda^m
+// (k.n_strips counted in kStripCols2-column strips); a.gsample is the sample
+// gradient added to lambda^{m+1}, gsample_b the one added to lambda^m.
+hipError_t launch_adjoint2(const AdjArgs& a, const double* gsample_b, int waves_per_block, hipStream_t s);
 hipError_t launch_extract_adjoint(double2* lam, int pitch, const ExtPoint* pts, int n, const double2* g,
                                   hipStream_t s);
 hipError_t launch_reduce_slots(const double* slots, int n, double* out, hipStream_t s);

@@ -736,7 +736,21 @@ int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi
     const bool fused = ne <= kMaxFusedAdjointExtract;
     a.k.n_ext = fused ? ne : 0;
     const char* win = static_cast<const char*>(d_window);
-    for (int64_t k = n - 1; k >= 0; --k) {
+    int64_t k = n - 1;
+    if (!spin && fused && g->steps_per_pass == 2) {
+        // cotangents only: two adjoint steps (k, then k-1) per pass
+        AdjArgs a2 = a;
+        a2.k.n_strips = (nr + kStripCols2 - 1) / kStripCols2;
+        for (; k >= 1; k -= 2) {
+            a2.nu_in = lam(c);
+            a2.lam_out = lam(1 - c);
+            a2.gsample = gs ? reinterpret_cast<const double*>(gs + (k - 1) * ne) : nullptr;
+            const double* gb = (gs && k >= 2) ? reinterpret_cast<const double*>(gs + (k - 2) * ne) : nullptr;
+            HIP_TRY(launch_adjoint2(a2, gb, g->adj_wpb, s));
+            c = 1 - c;
+        }
+    }
+    for (; k >= 0; --k) {
         a.nu_in = lam(c);
         a.u_in = spin ? reinterpret_cast<const double2*>(win + (size_t)k * g->L.state) : nullptr;
         a.lam_out = lam(1 - c);

@@ -315,3 +315,52 @@ def test_autograd_without_spin_gradient(gpu):
     L.backward()
     assert float(L.detach()) == full[0]
     assert np.array_equal(P.grad.cpu().numpy(), full[1]) and np.array_equal(Q.grad.cpu().numpy(), full[2])
+
+
+def _strip_and_chunk_points(nr, nth, rows, rmin=-30.0, rmax=60.0, count=4):
+    """Extraction points whose stencils straddle two-step strip boundaries
+    (columns 59|60, 119|120) and tile-row boundaries (rows rows-1|rows)."""
+    dr = (rmax - rmin) / (nr - 1)
+    dth = math.pi / nth
+    pts = []
+    for k in range(count):
+        col = (60 * (k % 2 + 1) - 1) % (nr - 1)
+        row = min(rows * (k % 3 + 1) - 1, nth - 2)
+        pts.append((rmin + (col + 0.5) * dr, (row + 1.0) * dth))
+    return tuple(pts)
+
+
+@pytest.mark.parametrize("a,s,m,nr,nth,rows,wpb,n,npts", [
+    (0.8, -2, 3, 187, 41, 16, 4, 5, 4),    # odd step count: pairs then one single step
+    (0.6, -2, 2, 121, 33, 8, 2, 6, 16),    # the most points the fused pass takes
+    (0.9, 0, -1, 64, 9, 1, 1, 4, 2),       # one-row tiles: every tile meets both halo rows
+    (0.3, -2, 2, 61, 16, 16, 1, 7, 3),     # one tile row, one strip plus one column
+    (0.95, -2, -2, 240, 70, 4, 4, 2, 17),  # more points than the fused pass takes
+])
+def test_cotangent_only_two_step_identical(gpu, a, s, m, nr, nth, rows, wpb, n, npts):
+    """The cotangent-only adjoint taken two steps per pass gives the same
+    cotangents, bit for bit, as one step per pass, and agrees with the
+    oracle's transposed steps."""
+    w = small_case(a, s, m, nr, nth, ext=_strip_and_chunk_points(nr, nth, rows, count=npts))
+    lam0 = inputs.random_state(nr, nth, seed=101)
+    rng = np.random.default_rng(102)
+    gser_np = rng.standard_normal((n, npts)) + 1j * rng.standard_normal((n, npts))
+    gser = torch.from_numpy(gser_np).cuda()
+    g = _gpu_grid(gpu, w)
+    g.set_adjoint_tile(rows, wpb)
+    out = []
+    for spp in (1, 2):
+        g.set_steps_per_pass(spp)
+        lp = torch.from_numpy(lam0[0].copy()).cuda()
+        lq = torch.from_numpy(lam0[1].copy()).cuda()
+        assert g.adjoint(n, lp, lq, gser, None, project_initial=False, spin=False) is None
+        torch.cuda.synchronize()
+        out.append((lp.cpu().numpy(), lq.cpu().numpy()))
+    g.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    o = oracle.OracleGrid(w["a"], w["s"], w["m"], nr, nth, w["rstar_min"], w["rstar_max"], w["dt"])
+    states = [(np.zeros((nth, nr), complex), np.zeros((nth, nr), complex))] * n
+    ref_p, ref_q, _ = oracle_segment_adjoint(o, states, lam0[0], lam0[1], gser_np, w["extract_rstar"],
+                                             w["extract_theta"])
+    assert rel_err(out[1][0], ref_p) <= TOL
+    assert rel_err(out[1][1], ref_q) <= TOL
