@@ -246,7 +246,7 @@ def main():
     if args.tile:
         g.set_tile(*(int(x) for x in args.tile.split(",")))
     else:
-        autotune.tune_grid(g, rows=(16, 32, 64), waves=(1, 2, 4), steps=20, use_cache=False)
+        autotune.tune_grid(g, waves=(1, 2, 4), steps=20, use_cache=False)
     phi0, pi0 = inputs.initial_data(w)
     g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
     series = torch.empty((max(args.steps, args.warmup, 1), max(g.n_extract, 1)), dtype=torch.complex128,

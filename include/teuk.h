@@ -121,10 +121,12 @@ int64_t teuk_steps_taken(const teuk_grid* g);
 double teuk_get_dt(const teuk_grid* g);
 
 /* Launch shape of the step kernels: rows of theta per wavefront tile
- * (1..ntheta) and wavefronts per workgroup (1, 2, 4 or 8).  The default is
- * 32 rows and 4 wavefronts, with the rows halved (down to 8) while the grid
- * has fewer than 1024 tiles (then 1 wavefront per workgroup).  Results do
- * not depend on it (every point's arithmetic is the same). */
+ * (1..ntheta) and wavefronts per workgroup (1, 2, 4 or 8).  The default cuts
+ * the rows so that the tiles just fill a whole number of rounds of the
+ * device's resident wavefronts (two per SIMD), taking the fewest rounds that
+ * keep a tile within 64 rows, and at least 8 rows; 4 wavefronts per
+ * workgroup, or 1 when the grid has fewer tiles than the device has SIMDs.
+ * Results do not depend on it (every point's arithmetic is the same). */
 int teuk_set_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per_block);
 int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per_block);
 

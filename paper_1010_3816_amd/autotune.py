@@ -69,9 +69,26 @@ def _time(torch, stream, fn, steps, reps=3):
     return best
 
 
-def tune_grid(grid, rows=GRID_ROWS, waves=GRID_WAVES, steps=20, use_cache=True):
+def round_rows(nr, ntheta, cus, strip_cols=60, waves_per_simd=2, rounds=(1, 2, 3, 4), lo=8, hi=128):
+    """Tile heights that cut each strip into as many tiles as fill k whole
+    rounds of the device's resident wavefronts (k in `rounds`): a partly
+    filled last round leaves SIMDs idle."""
+    strips = -(-nr // strip_cols)
+    slots = cus * 4 * waves_per_simd
+    out = set()
+    for k in rounds:
+        chunks = k * slots // strips
+        if chunks >= 1:
+            r = -(-ntheta // chunks)
+            if lo <= r <= hi:
+                out.add(min(r, ntheta))
+    return sorted(out)
+
+
+def tune_grid(grid, rows=None, waves=GRID_WAVES, steps=20, use_cache=True):
     """Pick (rows_per_tile, waves_per_block) for a TeukGrid; returns
-    {"rows": r, "waves": w, "ms": t, "table": [...]}."""
+    {"rows": r, "waves": w, "ms": t, "table": [...]}.  rows=None: GRID_ROWS
+    and the heights of round_rows."""
     torch = grid.torch
     key = f"grid|{_device_key(torch, grid.device)}|{grid.nr}x{grid.ntheta}"
     if use_cache:
@@ -79,6 +96,9 @@ def tune_grid(grid, rows=GRID_ROWS, waves=GRID_WAVES, steps=20, use_cache=True):
         if hit:
             grid.set_tile(min(hit["rows"], grid.ntheta), hit["waves"])
             return dict(hit, cached=True)
+    if rows is None:
+        cus = torch.cuda.get_device_properties(grid.device).multi_processor_count
+        rows = tuple(GRID_ROWS) + tuple(round_rows(grid.nr, grid.ntheta, cus))
     table = []
     for r in sorted({min(r, grid.ntheta) for r in rows}):
         for w in waves:

@@ -50,7 +50,9 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
                                            int lane) {
     const int nr = A.nr, nth = A.nth, P = A.pitch;
     const int col = strip * kStripCols - 1 + lane;
-    const unsigned long long in = ((col >= 0) && (col < nr)) ? ~0ull : 0ull;
+    // Lanes outside the grid read the clamped edge column.  Their values
+    // reach only the radial boundary columns of the output, which are set to
+    // zero, so they need no masking.
     const int ci = min(max(col, 0), nr - 1);  // clamped integer column
     const int hi = min(max(col, 0), nr - 2);  // clamped half point col + 1/2
 
@@ -115,8 +117,6 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
     // FULL: also the Pi part x, wp (needs ubp(t-1): `ubp_prev`, or the ghost
     // row when t == 0).  Halo rows only need ubp and hbp.
     auto fresh = [&](int t, cd p, cd q, cd ubp_prev, bool full, const Ang& G) -> Row {
-        p = masked(p, in);
-        q = masked(q, in);
         Row R;
         R.p = p;
         R.q = q;
@@ -290,7 +290,9 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
                                             int chunk, int lane) {
     const int nr = A.nr, nth = A.nth, P = A.pitch;
     const int col = strip * kStripCols2 - 2 + lane;
-    const unsigned long long in = ((col >= 0) && (col < nr)) ? ~0ull : 0ull;
+    // lanes outside the grid need no masking (as in sweep_tile): step A's
+    // values there reach only its zeroed boundary columns, and step B's only
+    // B's
     const int ci = min(max(col, 0), nr - 1);
     const int hi = min(max(col, 0), nr - 2);
 
@@ -385,8 +387,6 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
     // coefficients kh of the row.  FULL = false: only the averages needed
     // from a halo row.
     auto fresh = [&](int t, cd p, cd q, cd ubp_prev, bool full, const Ang& G, const Coef& kh) -> Row {
-        p = masked(p, in);
-        q = masked(q, in);
         Row R;
         R.p = p;
         R.q = q;
@@ -526,12 +526,13 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
     // live in two copies that swap roles from row to row: ac/bc/khc/kic
     // hold row r's, the next row's arrive in an/bn/khn/kin.
     static_assert(kRowsInFlight2 == 2, "the row loop takes rows in pairs");
+    // POLE: row r may be the grid's last (the pair loop's rows never are)
     auto step_row = [&](int r, cd& rp, cd& rq, Row& ac, Row& an, Row& bc, Row& bn, Coef& khc, Coef& khn, Coef& kic,
-                        Coef& kin) {
+                        Coef& kin, bool pole) {
         cd ubp_p, hbp_p;
         const Ang g1 = g_next;
         g_next = ang_row(r + 2);
-        if (r + 1 < nth) {
+        if (!pole || r + 1 < nth) {
             khn = coef_h(r + 1, g1);
             an = fresh(r + 1, rp, rq, ac.ubp, true, g1, khn);
             sample(r + 1, an.p, acc_in);
@@ -576,12 +577,18 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
     Coef kh_oth, ki_oth;
     int r0 = j0 + 1;
     for (; r0 + 1 <= aE; r0 += 2) {
-        step_row(r0, bp[0], bq[0], a_cur, a_oth, b_cur, b_oth, kh_a, kh_oth, ki_b, ki_oth);
-        step_row(r0 + 1, bp[1], bq[1], a_oth, a_cur, b_oth, b_cur, kh_oth, kh_a, ki_oth, ki_b);
+        step_row(r0, bp[0], bq[0], a_cur, a_oth, b_cur, b_oth, kh_a, kh_oth, ki_b, ki_oth, true);
+        step_row(r0 + 1, bp[1], bq[1], a_oth, a_cur, b_oth, b_cur, kh_oth, kh_a, ki_oth, ki_b, true);
     }
+    // at most two rows left, the last of them possibly the pole row
     if (r0 <= aE) {
-        step_row(r0, bp[0], bq[0], a_cur, a_oth, b_cur, b_oth, kh_a, kh_oth, ki_b, ki_oth);
-        if (j1 == nth) last_row(b_oth, ki_oth);
+        step_row(r0, bp[0], bq[0], a_cur, a_oth, b_cur, b_oth, kh_a, kh_oth, ki_b, ki_oth, true);
+        if (r0 + 1 <= aE) {
+            step_row(r0 + 1, bp[1], bq[1], a_oth, a_cur, b_oth, b_cur, kh_oth, kh_a, ki_oth, ki_b, true);
+            if (j1 == nth) last_row(b_cur, ki_b);
+        } else if (j1 == nth) {
+            last_row(b_oth, ki_oth);
+        }
     } else if (j1 == nth) {
         last_row(b_cur, ki_b);
     }

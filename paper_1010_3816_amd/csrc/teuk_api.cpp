@@ -229,6 +229,31 @@ int check_grid(const teuk_grid* g) {
     return TEUK_OK;
 }
 
+// Default tile of the two-step pass.  The device holds two of its wavefronts
+// per SIMD, so its tiles run in rounds of 8 x CUs; a last round that is only
+// partly filled leaves SIMDs idle.  Take the fewest rounds k whose tiles, cut
+// so that the grid's tiles just fit k rounds, have at most 64 rows (at least
+// 8).  Grids with fewer tiles than SIMDs take one wavefront per workgroup, to
+// spread over the CUs.
+void default_tile(int nr, int nth, int cus, int* rows, int* wpb) {
+    const int64_t strips2 = (nr + kStripCols2 - 1) / kStripCols2;
+    const int64_t slots = (int64_t)cus * 8;
+    int64_t r = 64;
+    for (int64_t k = 1; k <= 64; ++k) {
+        const int64_t chunks = k * slots / strips2;
+        if (chunks < 1) continue;
+        const int64_t rk = (nth + chunks - 1) / chunks;
+        if (rk <= 64) {
+            r = rk;
+            break;
+        }
+    }
+    r = std::min<int64_t>(std::max<int64_t>(r, 8), nth);
+    const int64_t tiles = strips2 * ((nth + r - 1) / r);
+    *rows = (int)r;
+    *wpb = tiles < (int64_t)cus * 4 ? 1 : 4;
+}
+
 int set_device(const teuk_grid* g) {
     int cur = -1;
     HIP_TRY(hipGetDevice(&cur));
@@ -344,16 +369,12 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
     g->dr = dr;
     g->dth = dth;
     g->sigma = (std::abs(p->m) % 2 == 0) ? 1 : -1;
-    // Default tile: 32 rows, halved while the grid has fewer tiles than a
-    // wavefront per SIMD of the device (1024 on 256 CUs) would need; small
-    // grids then also take one wavefront per workgroup to spread over CUs.
     {
-        const int strips2 = (nr + kStripCols2 - 1) / kStripCols2;
-        auto tiles = [&](int r) { return (int64_t)strips2 * ((nth + r - 1) / r); };
-        int r = std::min(nth, 32);
-        while (r > 8 && tiles(r) < 1024) r = (r + 1) / 2;
-        g->rows = r;
-        g->wpb = tiles(r) < 1024 ? 1 : 4;
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        default_tile(nr, nth, cus, &g->rows, &g->wpb);
     }
     g->adj_rows = std::min(nth, 16);
     g->adj_chunks = (nth + g->adj_rows - 1) / g->adj_rows;
@@ -924,7 +945,7 @@ int teuk_batch_init(const teuk_params* members, int32_t count, void* hip_stream,
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || cus < 1)
         cus = 256;
-    b->n_blocks = cus * 4 / b->wpb;  // one wavefront per SIMD (the two-step kernel's occupancy)
+    b->n_blocks = cus * 8 / b->wpb;  // two wavefronts per SIMD (the two-step kernel's occupancy)
     // the extraction points of all members, in member order
     std::vector<BatchExtPoint> pts;
     for (teuk_grid* g : b->members)

@@ -118,3 +118,23 @@ def test_radius_and_mode_sum_validation():
     assert lib.teuk_assemble_modes(1, 2, m, 2, phi, r_bad, None, None, None) == b.TEUK_E_INVALID_ARG
     assert lib.teuk_assemble_modes(1, 2, m, 2, phi, r_ok, None, None, None) == b.TEUK_E_INVALID_ARG  # NULL tensors
     assert lib.teuk_assemble_modes(0, 2, m, 2, phi, r_ok, None, None, None) == b.TEUK_OK  # nothing to do
+
+
+def test_round_rows_fill_whole_rounds():
+    """Autotuner candidates: tile heights whose tiles just fit k rounds of
+    two wavefronts per SIMD (256 CUs: 2048 resident wavefronts)."""
+    from paper_1010_3816_amd.autotune import round_rows
+
+    # 25600 columns = 427 strips of 60; 512 rows cut into 4, 9, 14, 19 tiles
+    assert round_rows(25600, 512, 256) == [27, 37, 57, 128]
+    # 6400 columns = 107 strips: one round takes 19 tiles of 14 rows; two
+    # rounds would need 7-row tiles, below the 8-row floor
+    assert round_rows(6400, 256, 256) == [14]
+    # k rounds hold the tiles, k - 1 rounds would not
+    for nr, nth in ((25600, 512), (6400, 256), (12800, 128), (3000, 64)):
+        strips = -(-nr // 60)
+        for k in (1, 2, 3, 4):
+            (r,) = round_rows(nr, nth, 256, rounds=(k,), lo=1, hi=nth)
+            tiles = strips * -(-nth // r)
+            assert tiles <= k * 2048, (nr, nth, k, r)
+            assert r == 1 or strips * -(-nth // (r - 1)) > k * 2048, (nr, nth, k, r)

@@ -226,3 +226,63 @@ def test_two_step_full_size(gpu, name):
     assert rel_err(g[1], o[1]) <= TOL
     if g[2] is not None:
         assert rel_err(g[2], o[2]) <= TOL
+
+
+def _default_rows(nr, nth, cus):
+    """The documented default tile height: fewest rounds k of two wavefronts
+    per SIMD whose round-filling tiles have at most 64 rows; within [8, nth]."""
+    strips = -(-nr // 60)
+    r = 64
+    for k in range(1, 65):
+        chunks = k * cus * 8 // strips
+        if chunks >= 1 and -(-nth // chunks) <= 64:
+            r = -(-nth // chunks)
+            break
+    return min(max(r, 8), nth)
+
+
+@pytest.mark.parametrize("nr,nth", [(25600, 512), (6400, 256), (400, 32), (12800, 128)])
+def test_default_tile_fills_whole_rounds(gpu, nr, nth):
+    import torch
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    w = small_case(0.5, -2, 2, nr, nth)
+    g = gpu.TeukGrid(w["a"], w["s"], w["m"], nr, nth, w["rstar_min"], w["rstar_max"], w["dt"])
+    rows, wpb = g.tile()
+    g.close()
+    assert rows == _default_rows(nr, nth, cus)
+    tiles = -(-nr // 60) * -(-nth // rows)
+    assert wpb == (1 if tiles < 4 * cus else 4)
+    if cus == 256 and (nr, nth) == (25600, 512):
+        assert (rows, wpb) == (57, 4)
+
+
+def test_full_size_tile_independence(gpu):
+    """Every launch shape the benchmark's autotuner may pick gives the same
+    state, bit for bit, on the full 25600 x 512 grid (the default shape is
+    checked against the oracle in test_two_step_full_size)."""
+    import torch
+
+    from paper_1010_3816_amd import autotune
+
+    w = inputs.workload("kerr_a0.99_25600x512")
+    phi0, pi0 = inputs.initial_data(w)
+    rnd = inputs.random_state(w["nr"], w["ntheta"], seed=17)
+    phi0 = phi0 + 1e-3 * rnd[0]
+    pi0 = pi0 + 1e-3 * rnd[1]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    g = gpu.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"])
+    P0 = torch.from_numpy(phi0).cuda()
+    Q0 = torch.from_numpy(pi0).cuda()
+    g.set_initial_data(P0, Q0)
+    g.step(3)
+    ref = [t.clone() for t in g.state()]
+    rows = sorted(set(autotune.GRID_ROWS) | set(autotune.round_rows(w["nr"], w["ntheta"], cus)))
+    for r in rows:
+        for wpb in (1, 2, 4):
+            g.set_tile(r, wpb)
+            g.set_initial_data(P0, Q0)
+            g.step(3)
+            p, q = g.state()
+            assert torch.equal(p, ref[0]) and torch.equal(q, ref[1]), (r, wpb)
+    g.close()
