@@ -124,9 +124,10 @@ double teuk_get_dt(const teuk_grid* g);
  * (1..ntheta) and wavefronts per workgroup (1, 2, 4 or 8).  The default cuts
  * the rows so that the tiles just fill a whole number of rounds of the
  * device's resident wavefronts (two per SIMD), taking the fewest rounds that
- * keep a tile within 64 rows, and at least 8 rows; 4 wavefronts per
- * workgroup, or 1 when the grid has fewer tiles than the device has SIMDs.
- * Results do not depend on it (every point's arithmetic is the same). */
+ * keep a tile within 64 rows (so a grid that fits one round gets the
+ * shortest tiles that do, down to one row); 4 wavefronts per workgroup, or 1
+ * when the grid has fewer tiles than the device has SIMDs.  Results do not
+ * depend on it (every point's arithmetic is the same). */
 int teuk_set_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per_block);
 int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per_block);
 
@@ -192,8 +193,9 @@ size_t teuk_adjoint_workspace_bytes(teuk_grid* g);
 int teuk_enable_adjoint(teuk_grid* g, void* d_adj_workspace, size_t bytes);
 
 /* Launch shape of the adjoint kernel: theta rows per wavefront tile (1 ..
- * ntheta, default min(ntheta, 16)) and wavefronts per workgroup (1, 2 or 4,
- * default 4).  The cotangents do not depend on it; dL/da is summed per tile,
+ * ntheta) and wavefronts per workgroup (1, 2 or 4, default 4).  The default
+ * rows are the fewest whose workgroups (four theta chunks of one strip each)
+ * fit one round of two wavefronts per SIMD, at most 16.  The cotangents do not depend on it; dL/da is summed per tile,
  * so its last bits may.  TEUK_E_INVALID_ARG outside these ranges. */
 int teuk_set_adjoint_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per_block);
 int teuk_get_adjoint_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per_block);

@@ -17,7 +17,7 @@ import os
 
 from . import binding
 
-GRID_ROWS = (8, 12, 16, 24, 32, 48, 64)
+GRID_ROWS = (1, 2, 4, 8, 12, 16, 24, 32, 48, 64)
 GRID_WAVES = (1, 2, 4, 8)
 BATCH_ROWS = (8, 16, 24, 32)
 BATCH_WAVES = (2, 4, 8)
@@ -69,7 +69,7 @@ def _time(torch, stream, fn, steps, reps=3):
     return best
 
 
-def round_rows(nr, ntheta, cus, strip_cols=60, waves_per_simd=2, rounds=(1, 2, 3, 4), lo=8, hi=128):
+def round_rows(nr, ntheta, cus, strip_cols=60, waves_per_simd=2, rounds=(1, 2, 3, 4), lo=1, hi=128):
     """Tile heights that cut each strip into as many tiles as fill k whole
     rounds of the device's resident wavefronts (k in `rounds`): a partly
     filled last round leaves SIMDs idle."""

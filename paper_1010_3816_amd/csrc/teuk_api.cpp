@@ -231,10 +231,11 @@ int check_grid(const teuk_grid* g) {
 
 // Default tile of the two-step pass.  The device holds two of its wavefronts
 // per SIMD, so its tiles run in rounds of 8 x CUs; a last round that is only
-// partly filled leaves SIMDs idle.  Take the fewest rounds k whose tiles, cut
-// so that the grid's tiles just fit k rounds, have at most 64 rows (at least
-// 8).  Grids with fewer tiles than SIMDs take one wavefront per workgroup, to
-// spread over the CUs.
+// partly filled leaves SIMDs idle, and a wavefront walks its tile's rows one
+// after the other, so on a grid that fits one round shorter tiles finish
+// sooner.  Take the fewest rounds k whose tiles, cut so that the grid's tiles
+// just fit k rounds, have at most 64 rows.  Grids with fewer tiles than SIMDs
+// take one wavefront per workgroup, to spread over the CUs.
 void default_tile(int nr, int nth, int cus, int* rows, int* wpb) {
     const int64_t strips2 = (nr + kStripCols2 - 1) / kStripCols2;
     const int64_t slots = (int64_t)cus * 8;
@@ -248,10 +249,21 @@ void default_tile(int nr, int nth, int cus, int* rows, int* wpb) {
             break;
         }
     }
-    r = std::min<int64_t>(std::max<int64_t>(r, 8), nth);
+    r = std::min<int64_t>(r, nth);
     const int64_t tiles = strips2 * ((nth + r - 1) / r);
     *rows = (int)r;
     *wpb = tiles < (int64_t)cus * 4 ? 1 : 4;
+}
+
+// Default tile of the adjoint kernels (four wavefronts per workgroup, each
+// workgroup taking four theta chunks of one strip): the shortest tiles whose
+// workgroups fit one round of two wavefronts per SIMD, at most 16 rows.
+int default_adjoint_rows(int nr, int nth, int cus) {
+    const int64_t strips = (nr + kStripCols - 1) / kStripCols;
+    const int64_t groups = (int64_t)cus * 8 / 4 / strips;  // workgroups per strip in one round
+    if (groups < 1) return std::min(nth, 16);
+    const int64_t chunks = groups * 4;
+    return (int)std::min<int64_t>(std::min<int64_t>((nth + chunks - 1) / chunks, 16), nth);
 }
 
 int set_device(const teuk_grid* g) {
@@ -369,14 +381,15 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
     g->dr = dr;
     g->dth = dth;
     g->sigma = (std::abs(p->m) % 2 == 0) ? 1 : -1;
+    int cus = 0;
     {
-        int dev = 0, cus = 0;
+        int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
             cus = 256;
         default_tile(nr, nth, cus, &g->rows, &g->wpb);
     }
-    g->adj_rows = std::min(nth, 16);
+    g->adj_rows = default_adjoint_rows(nr, nth, cus);
     g->adj_chunks = (nth + g->adj_rows - 1) / g->adj_rows;
     g->adj_strips = ((int)p->nr + kStripCols - 1) / kStripCols;
     g->ext_r.assign(p->extract_rstar, p->extract_rstar + p->n_extract);

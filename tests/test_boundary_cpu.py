@@ -127,9 +127,10 @@ def test_round_rows_fill_whole_rounds():
 
     # 25600 columns = 427 strips of 60; 512 rows cut into 4, 9, 14, 19 tiles
     assert round_rows(25600, 512, 256) == [27, 37, 57, 128]
-    # 6400 columns = 107 strips: one round takes 19 tiles of 14 rows; two
-    # rounds would need 7-row tiles, below the 8-row floor
-    assert round_rows(6400, 256, 256) == [14]
+    # 6400 columns = 107 strips: one round takes 19 tiles of 14 rows, two
+    # rounds 38 of 7, three 57 of 5, four 76 of 4
+    assert round_rows(6400, 256, 256) == [4, 5, 7, 14]
+    assert round_rows(6400, 256, 256, lo=8) == [14]
     # k rounds hold the tiles, k - 1 rounds would not
     for nr, nth in ((25600, 512), (6400, 256), (12800, 128), (3000, 64)):
         strips = -(-nr // 60)

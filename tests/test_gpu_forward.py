@@ -230,7 +230,7 @@ def test_two_step_full_size(gpu, name):
 
 def _default_rows(nr, nth, cus):
     """The documented default tile height: fewest rounds k of two wavefronts
-    per SIMD whose round-filling tiles have at most 64 rows; within [8, nth]."""
+    per SIMD whose round-filling tiles have at most 64 rows."""
     strips = -(-nr // 60)
     r = 64
     for k in range(1, 65):
@@ -238,10 +238,17 @@ def _default_rows(nr, nth, cus):
         if chunks >= 1 and -(-nth // chunks) <= 64:
             r = -(-nth // chunks)
             break
-    return min(max(r, 8), nth)
+    return min(r, nth)
 
 
-@pytest.mark.parametrize("nr,nth", [(25600, 512), (6400, 256), (400, 32), (12800, 128)])
+def _default_adjoint_rows(nr, nth, cus):
+    groups = cus * 8 // 4 // -(-nr // 62)
+    if groups < 1:
+        return min(nth, 16)
+    return min(-(-nth // (4 * groups)), 16, nth)
+
+
+@pytest.mark.parametrize("nr,nth", [(25600, 512), (6400, 256), (400, 32), (12800, 128), (70000, 64)])
 def test_default_tile_fills_whole_rounds(gpu, nr, nth):
     import torch
 
@@ -249,12 +256,16 @@ def test_default_tile_fills_whole_rounds(gpu, nr, nth):
     w = small_case(0.5, -2, 2, nr, nth)
     g = gpu.TeukGrid(w["a"], w["s"], w["m"], nr, nth, w["rstar_min"], w["rstar_max"], w["dt"])
     rows, wpb = g.tile()
+    adj = g.adjoint_tile()
     g.close()
     assert rows == _default_rows(nr, nth, cus)
     tiles = -(-nr // 60) * -(-nth // rows)
     assert wpb == (1 if tiles < 4 * cus else 4)
-    if cus == 256 and (nr, nth) == (25600, 512):
-        assert (rows, wpb) == (57, 4)
+    assert adj == (_default_adjoint_rows(nr, nth, cus), 4)
+    if cus == 256:
+        expect = {(25600, 512): (57, 4, 16), (6400, 256): (14, 4, 16), (400, 32): (1, 1, 1)}.get((nr, nth))
+        if expect:
+            assert (rows, wpb, adj[0]) == expect
 
 
 def test_full_size_tile_independence(gpu):
