@@ -611,7 +611,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
                     double2* __restrict__ series_mid, double2* __restrict__ u_mid, StepScalars A) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
-    const int tile = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * wpb + (threadIdx.x / kWave));
+    const int tile = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x / kWave));
     const int strip = tile % A.n_strips;
     const int chunk = tile / A.n_strips;
     extern __shared__ double rad_s[];
@@ -630,11 +630,14 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_W
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
     // Tiles are numbered strip-fastest, so the wavefronts of a workgroup take
-    // neighbouring strips of one theta chunk (their halo columns overlap);
-    // workgroups are remapped so that each XCD receives a contiguous range.
-    // The tile index is made explicitly wavefront-uniform so that everything
-    // derived from it (rows, table reads, loop control) is scalar.
-    const int tile = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * wpb + (threadIdx.x / kWave));
+    // neighbouring strips of one theta chunk (their halo columns overlap).
+    // Workgroups are left in dispatch order, which deals them round-robin
+    // over the XCDs: measured faster for these streaming passes than giving
+    // each XCD a contiguous range (whose last, short theta chunk then falls
+    // on one XCD).  The tile index is made explicitly wavefront-uniform so
+    // that everything derived from it (rows, table reads, loop control) is
+    // scalar.
+    const int tile = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x / kWave));
 #if TEUK_CHUNK_FASTEST
     const int strip = tile / A.n_chunks;
     const int chunk = tile % A.n_chunks;
@@ -659,7 +662,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_W
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
     const int nwaves = gridDim.x * wpb;
-    const int w0 = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * wpb + (threadIdx.x / kWave));
+    const int w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x / kWave));
     for (int tile = w0; tile < total_tiles; tile += nwaves) {
         int lo = 0, hi = n_members - 1;  // last member with tile_begin <= tile
         while (lo < hi) {
@@ -687,7 +690,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
     const int nwaves = gridDim.x * wpb;
-    const int w0 = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * wpb + (threadIdx.x / kWave));
+    const int w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x / kWave));
     for (int tile = w0; tile < total_tiles; tile += nwaves) {
         int lo = 0, hi = n_members - 1;  // last member with tile_begin2 <= tile
         while (lo < hi) {
