@@ -39,8 +39,8 @@ METRIC = "FP64 grid-point updates/s + % HBM roofline; adjoint/forward time ratio
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 BYTES_PER_POINT_PASS = 64   # Phi, Pi read and written once per pass (complex128)
-FLOPS_PER_UPDATE = {1: 232, 2: 192}  # FP64 flops per point and step, single-step and two-step kernels
-VALU_PER_UPDATE = {1: 221, 2: 188}   # vector ALU instructions per point and step (steady-state loop)
+FLOPS_PER_UPDATE = {1: 230, 2: 192}  # FP64 flops per point and step, single-step and two-step kernels
+VALU_PER_UPDATE = {1: 217, 2: 183}   # vector ALU instructions per point and step (steady-state loop)
 # vector instruction issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per 4 cycles per SIMD
 VALU_PEAK_T = 256 * 4 * 2.4e9 * 64 / 4 / 1e12
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1010_3816_amd", "csrc", f)
