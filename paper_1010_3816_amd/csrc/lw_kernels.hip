@@ -290,9 +290,9 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
                                             int chunk, int lane) {
     const int nr = A.nr, nth = A.nth, P = A.pitch;
     const int col = strip * kStripCols2 - 2 + lane;
-    // lanes outside the grid need no masking (as in sweep_tile): step A's
-    // values there reach only its zeroed boundary columns, and step B's only
-    // B's
+    // Lanes outside the grid need no masking (as in sweep_tile): what they
+    // hold reaches only the radial boundary columns of step A's and step B's
+    // outputs, which both steps set to zero.
     const int ci = min(max(col, 0), nr - 1);
     const int hi = min(max(col, 0), nr - 2);
 
@@ -367,7 +367,7 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
         }
     }
     cd acc_in = {0.0, 0.0}, acc_mid = {0.0, 0.0};
-    // bilinear sample of a (masked) Phi row into acc
+    // bilinear sample of a Phi row into acc
     auto sample = [&](int t, cd p, cd& acc) {
         if (t == e_ra || t == e_rb) {  // wavefront-uniform
             const double w = (t == e_ra) ? e_wa : e_wb;
