@@ -266,7 +266,9 @@ int teuk_assemble_modes(int64_t n_samples, int32_t n_modes, const int32_t* h_m, 
                         const double* h_r, const void* d_samples, void* d_psi, void* hip_stream);
 
 /* Launch shape: theta rows per tile, wavefronts per workgroup (1, 2, 4, 8)
- * and workgroups of the persistent launch.  Waits for queued work. */
+ * and workgroups of the persistent launch.  Waits for queued work.  The
+ * default is 64 rows (each member's rows at most), 4 wavefronts and
+ * 4 x CUs workgroups (four wavefronts per SIMD). */
 int teuk_batch_set_launch(teuk_batch* b, int32_t rows_per_tile, int32_t waves_per_block, int32_t n_blocks);
 /* Steps per launch of the batch: 1 or 2 (default; see teuk_set_steps_per_pass).
  * Member results do not depend on it.  Synchronises the batch's stream. */

@@ -19,8 +19,8 @@ from . import binding
 
 GRID_ROWS = (1, 2, 4, 8, 12, 16, 24, 32, 48, 64)
 GRID_WAVES = (1, 2, 4, 8)
-BATCH_ROWS = (8, 16, 24, 32)
-BATCH_WAVES = (2, 4, 8)
+BATCH_ROWS = (8, 16, 32, 64, 128)
+BATCH_WAVES = (1, 2, 4)
 
 
 def _cache_path():
@@ -113,7 +113,7 @@ def tune_grid(grid, rows=None, waves=GRID_WAVES, steps=20, use_cache=True):
     return out
 
 
-def tune_batch(batch, rows=BATCH_ROWS, waves=BATCH_WAVES, blocks_per_cu=(1, 2, 4), steps=10, use_cache=True):
+def tune_batch(batch, rows=BATCH_ROWS, waves=BATCH_WAVES, blocks_per_cu=(1, 2, 4, 8), steps=10, use_cache=True):
     """Pick (rows_per_tile, waves_per_block, n_blocks) for a TeukBatch."""
     torch = batch.torch
     shapes = ",".join(f"{m['nr']}x{m['ntheta']}" for m in batch.members)

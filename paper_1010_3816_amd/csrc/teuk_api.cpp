@@ -816,7 +816,7 @@ struct teuk_batch {
     char* ws = nullptr;
     hipStream_t stream = nullptr;
     int device = 0;
-    int rows = 16, wpb = 4, n_blocks = 0;
+    int rows = 64, wpb = 4, n_blocks = 0;  // default launch: 64-row tiles, four wavefronts per SIMD
     int total_tiles = 0, total_tiles2 = 0;  // single-step and two-step work lists
     int steps_per_pass = 2;
     int parity = 0;                 // which state buffer of every member is the input
@@ -958,7 +958,9 @@ int teuk_batch_init(const teuk_params* members, int32_t count, void* hip_stream,
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || cus < 1)
         cus = 256;
-    b->n_blocks = cus * 8 / b->wpb;  // two wavefronts per SIMD (the two-step kernel's occupancy)
+    // four wavefronts per SIMD: two resident (the two-step kernel's
+    // occupancy), and a second round that takes over as the first drains
+    b->n_blocks = cus * 16 / b->wpb;
     // the extraction points of all members, in member order
     std::vector<BatchExtPoint> pts;
     for (teuk_grid* g : b->members)

@@ -63,7 +63,7 @@ def test_members_equal_single_grids(gpu):
     b.close()
 
 
-@pytest.mark.parametrize("launch", [(1, 1, 7), (3, 2, 64), (16, 8, 512), (64, 4, 2048)])
+@pytest.mark.parametrize("launch", [(1, 1, 7), (3, 2, 64), (16, 8, 512), (64, 4, 2048), (128, 1, 4096)])
 def test_launch_shapes_identical(gpu, launch):
     mbs = _members()
     data = [inputs.random_state(m["nr"], m["ntheta"], seed=200 + k) for k, m in enumerate(mbs)]
