@@ -9,6 +9,12 @@
   Phi = 1/r^3 with Pi = b Phi' is static; the scheme keeps it static up to its
   2nd-order truncation error.  This pins the radial coefficients (B1, b',
   the radial potential) including their a-dependence.
+* Static Kerr solution with m != 0: for s = 0 at zero frequency the radial
+  equation is Legendre's equation in x = (r - M)/sqrt(M^2 - a^2) with order
+  i gamma, gamma = a m / sqrt(M^2 - a^2), and for l = 1 it terminates:
+  R = ((x+1)/(x-1))^(i gamma/2) (x - i gamma).  Psi = R sin(th) e^(i phi) is
+  static; its gamma-dependence pins the a^2 m^2 part of the potential in a
+  full evolution.
 * Self-convergence of the extracted waveform under grid halving (ratio ~4).
 * Schwarzschild (a = 0) s = -2, l = 2 fundamental quasinormal ringdown,
   M omega = 0.37367 - 0.08896 i, recovered within 1 %.
@@ -65,6 +71,47 @@ def test_static_solution(a):
     d2 = _static_drift(a, 401, 16)
     # a wrong radial coefficient would give an O(1) drift over T = 2 M
     assert d1[0] < 2e-3 and d1[1] < 2e-2, d1
+    for k in range(2):
+        assert 3.3 < d1[k] / d2[k] < 4.7, (d1, d2)
+
+
+def _static_l1_drift(a, nr, nth, T=2.0):
+    """Drift of the static s = 0, l = 1, m = 1 Kerr solution (M = 1) over T."""
+    rmin, rmax = -20.0, 40.0
+    g = oracle.OracleGrid(a, 0, 1, nr, nth, rmin, rmax, 0.0)
+    g.dt = 0.25 * g.dr
+    n = int(round(T / g.dt))
+    g.dt = T / n
+    bq = math.sqrt(1 - a * a)
+    gam = a / bq
+    xi, _ = g.x_tables()                        # r - r_+
+    r = 1 + bq + xi
+    xm, xp = xi / bq, (xi + 2 * bq) / bq        # x - 1, x + 1 (x carried as r - r_+)
+    xl = 1 + xm
+    ph = np.exp(0.5j * gam * np.log(xp / xm))
+    R = ph * (xl - 1j * gam)
+    dR = ph * (1 - 1j * gam * (xl - 1j * gam) / (xm * xp))   # dR/dx
+    delta = xi * (xi + 2 * bq)
+    rho = r * r + a * a
+    th = g.theta()
+    phi0 = (R / r**3)[None, :] * np.sin(th)[:, None]
+    dphi = (dR / bq / r**3 - 3 * R / r**4) * delta / rho     # d(R/r^3)/dr*
+    # Pi = Phi_t + b Phi' with b = (r^2 + a^2) / sqrt((r^2 + a^2)^2 - a^2 Delta sin^2 th)
+    b = rho[None, :] / np.sqrt(rho[None, :] ** 2 - a * a * delta[None, :] * np.sin(th)[:, None] ** 2)
+    pi0 = b * dphi[None, :] * np.sin(th)[:, None]
+    phi, pi = g.step(phi0.astype(complex), pi0.astype(complex), n)
+    rs = g.rstar()
+    inner = (rs > rmin + T + 2.0) & (rs < rmax - T - 2.0)
+    return (np.max(np.abs(phi[:, inner] - phi0[:, inner])) / np.max(np.abs(phi0[:, inner])),
+            np.max(np.abs(pi[:, inner] - pi0[:, inner])) / np.max(np.abs(pi0[:, inner])))
+
+
+@pytest.mark.parametrize("a", [0.5, 0.9])
+def test_static_kerr_l1_m1_solution(a):
+    d1 = _static_l1_drift(a, 481, 24)
+    d2 = _static_l1_drift(a, 961, 48)
+    # a 10 % error in gamma (the a m dependence) drifts 18-120 x more than this
+    assert d1[0] < 1e-3 and d1[1] < 5e-3, d1
     for k in range(2):
         assert 3.3 < d1[k] / d2[k] < 4.7, (d1, d2)
 
