@@ -9,6 +9,14 @@ library's adjoint over the segment (teuk_adjoint_step_n), which carries the
 cotangent of the state and accumulates dL/da.  Device memory: the
 checkpoints (one state per K steps) plus one window of K states.
 
+With overlap (the default) the recompute of the next segment runs on a
+second grid and stream while the adjoint of the current one runs, into the
+other of two windows: the two passes use different device resources (the
+recompute streams the state, the adjoint is about half arithmetic and half
+memory latency), so they share the device better than they run one after
+the other.  The arithmetic and the order of the dL/da sums are unchanged, so
+the gradients are the same bit for bit.  Device memory: one more window.
+
 When the spin needs no gradient, no checkpoints are kept and the backward
 is one adjoint sweep over all steps: the cotangents of the linear step do
 not depend on the forward states, so nothing is recomputed.
@@ -22,21 +30,67 @@ import torch
 from . import binding
 
 
-def _make_grid(a, cfg):
+def _make_grid(a, cfg, stream=None):
     return binding.TeukGrid(a, cfg["s"], cfg["m"], cfg["nr"], cfg["ntheta"], cfg["rstar_min"], cfg["rstar_max"],
                             cfg["dt"], extract_rstar=cfg.get("extract_rstar", ()),
-                            extract_theta=cfg.get("extract_theta", ()))
+                            extract_theta=cfg.get("extract_theta", ()), stream=stream)
+
+
+def _reverse_sequential(grid, ckpts, segs, K, gseries, lam_phi, lam_pi):
+    window = grid.new_window(K)
+    dlda = 0.0
+    for idx in range(len(segs) - 1, -1, -1):
+        k, m = segs[idx]
+        grid.set_initial_data(*ckpts[idx])
+        grid.step_store(m, window, series=False)
+        dlda += grid.adjoint(m, lam_phi, lam_pi, gseries[k:k + m], window, project_initial=(idx == 0))
+    return dlda
+
+
+def _reverse_overlapped(grid, a, cfg, ckpts, segs, K, gseries, lam_phi, lam_pi):
+    """Segments in reverse; the recompute of segment idx-1 (second grid, own
+    stream, window (idx-1) % 2) is queued before the adjoint of segment idx
+    (this grid's stream, window idx % 2), which waits for its own recompute
+    only.  A window is rewritten two segments after it was filled; by then
+    its adjoint has returned (the adjoint with dL/da waits for its stream)."""
+    torch = grid.torch
+    rs = torch.cuda.Stream(device=grid.device)  # default priority
+    rs.wait_stream(grid.stream)                 # the checkpoints were written on the forward stream
+    rec = _make_grid(a, cfg, stream=rs)
+    windows = [grid.new_window(K), grid.new_window(K)]
+    done = [torch.cuda.Event(), torch.cuda.Event()]
+
+    def recompute(idx):
+        m = segs[idx][1]
+        rec.set_initial_data(*ckpts[idx])
+        rec.step_store(m, windows[idx % 2], series=False)
+        done[idx % 2].record(rs)
+
+    dlda = 0.0
+    last = len(segs) - 1
+    recompute(last)
+    for idx in range(last, -1, -1):
+        if idx > 0:
+            recompute(idx - 1)
+        grid.stream.wait_event(done[idx % 2])
+        k, m = segs[idx]
+        dlda += grid.adjoint(m, lam_phi, lam_pi, gseries[k:k + m], windows[idx % 2], project_initial=(idx == 0))
+    rs.synchronize()
+    rec.close()
+    return dlda
 
 
 class TeukEvolve(torch.autograd.Function):
-    """series = TeukEvolve.apply(phi0, pi0, a, cfg, n_steps, checkpoint_every)
+    """series = TeukEvolve.apply(phi0, pi0, a, cfg, n_steps, checkpoint_every, overlap)
 
     phi0, pi0: complex128 (ntheta, nr) on the GPU; a: 0-dim float64 tensor;
     cfg: dict with s, m, nr, ntheta, rstar_min, rstar_max, dt, extract_rstar,
-    extract_theta.  Returns the extraction series, complex128 (n_steps, n_extract)."""
+    extract_theta.  Returns the extraction series, complex128 (n_steps, n_extract).
+    overlap: run the recompute of the next segment beside the adjoint of the
+    current one (same results)."""
 
     @staticmethod
-    def forward(ctx, phi0, pi0, a, cfg, n_steps, checkpoint_every):
+    def forward(ctx, phi0, pi0, a, cfg, n_steps, checkpoint_every, overlap=True):
         n, K = int(n_steps), int(checkpoint_every)
         if n < 1 or K < 1:
             raise ValueError("need n_steps >= 1 and checkpoint_every >= 1")
@@ -55,6 +109,7 @@ class TeukEvolve(torch.autograd.Function):
         else:
             binding.teuk_step_n(grid.handle, n, series)
         ctx.grid, ctx.ckpts, ctx.n, ctx.K, ctx.need_a = grid, ckpts, n, K, need_a
+        ctx.cfg, ctx.overlap, ctx.a_val = cfg, bool(overlap), float(a)
         ctx.a_meta = (a.dtype, a.device, a.shape)
         return series
 
@@ -67,14 +122,12 @@ class TeukEvolve(torch.autograd.Function):
         lam_pi = torch.zeros_like(lam_phi)
         grad_a = None
         if ctx.need_a:
-            window = grid.new_window(min(K, n))
-            dlda = 0.0
             segs = [(k, min(K, n - k)) for k in range(0, n, K)]
-            for idx in range(len(segs) - 1, -1, -1):
-                k, m = segs[idx]
-                grid.set_initial_data(*ctx.ckpts[idx])
-                grid.step_store(m, window, series=False)
-                dlda += grid.adjoint(m, lam_phi, lam_pi, gseries[k:k + m], window, project_initial=(idx == 0))
+            if ctx.overlap and len(segs) > 1:
+                dlda = _reverse_overlapped(grid, ctx.a_val, ctx.cfg, ctx.ckpts, segs, min(K, n), gseries, lam_phi,
+                                           lam_pi)
+            else:
+                dlda = _reverse_sequential(grid, ctx.ckpts, segs, min(K, n), gseries, lam_phi, lam_pi)
             dtype, device, shape = ctx.a_meta
             grad_a = torch.full(shape, dlda, dtype=dtype, device=device)
         else:
@@ -82,11 +135,11 @@ class TeukEvolve(torch.autograd.Function):
         ctx.grid = None
         ctx.ckpts = None
         grid.close()
-        return lam_phi, lam_pi, grad_a, None, None, None
+        return lam_phi, lam_pi, grad_a, None, None, None, None
 
 
-def evolve(phi0, pi0, a, cfg, n_steps, checkpoint_every=100):
+def evolve(phi0, pi0, a, cfg, n_steps, checkpoint_every=100, overlap=True):
     """Extraction series of an n-step evolution, differentiable in phi0, pi0 and a."""
     if not torch.is_tensor(a):
         a = torch.tensor(float(a), dtype=torch.float64, device=phi0.device)
-    return TeukEvolve.apply(phi0, pi0, a, cfg, n_steps, checkpoint_every)
+    return TeukEvolve.apply(phi0, pi0, a, cfg, n_steps, checkpoint_every, overlap)

@@ -101,13 +101,13 @@ def _cfg(w):
                               "extract_theta")}
 
 
-def _gpu_loss_and_grads(w, phi0, pi0, target, n, K, a=None):
+def _gpu_loss_and_grads(w, phi0, pi0, target, n, K, a=None, overlap=True):
     from paper_1010_3816_amd.autograd import evolve
 
     P = torch.from_numpy(phi0).cuda().requires_grad_(True)
     Q = torch.from_numpy(pi0).cuda().requires_grad_(True)
     A = torch.tensor(w["a"] if a is None else a, dtype=torch.float64, device="cuda", requires_grad=True)
-    ser = evolve(P, Q, A, _cfg(w), n, K)
+    ser = evolve(P, Q, A, _cfg(w), n, K, overlap=overlap)
     L = ((ser - torch.from_numpy(target).cuda()).abs() ** 2).sum()
     L.backward()
     return float(L.detach()), P.grad.cpu().numpy(), Q.grad.cpu().numpy(), float(A.grad), ser.detach().cpu().numpy()
@@ -364,3 +364,17 @@ def test_cotangent_only_two_step_identical(gpu, a, s, m, nr, nth, rows, wpb, n, 
                                              w["extract_theta"])
     assert rel_err(out[1][0], ref_p) <= TOL
     assert rel_err(out[1][1], ref_q) <= TOL
+
+
+@pytest.mark.parametrize("n,K", [(60, 7), (45, 10), (30, 30)])
+def test_overlapped_reverse_identical(gpu, n, K):
+    """The reverse pass with the next segment's recompute running beside the
+    current adjoint (second grid, own stream, two windows) gives the same
+    loss and gradients, bit for bit, as one segment after the other: ragged
+    last segment, many segments, and a single segment (no overlap)."""
+    w, phi0, pi0, target, _ = _train_case(n)
+    seq = _gpu_loss_and_grads(w, phi0, pi0, target, n, K, overlap=False)
+    ovl = _gpu_loss_and_grads(w, phi0, pi0, target, n, K, overlap=True)
+    assert seq[0] == ovl[0] and seq[3] == ovl[3]
+    for k in (1, 2, 4):
+        assert np.array_equal(seq[k], ovl[k]), k
