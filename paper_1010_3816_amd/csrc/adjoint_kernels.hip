@@ -143,7 +143,6 @@ __global__ void __launch_bounds__(256)
     const int chunk = (bid / A.n_strips) * wpb + wave;
     const int nr = A.nr, nth = A.nth, P = A.pitch;
     const int col = strip * kStripCols - 1 + lane;
-    const unsigned long long in = ((col >= 0) && (col < nr)) ? ~0ull : 0ull;
     const unsigned long long interior = ((col >= 1) && (col < nr - 1)) ? ~0ull : 0ull;
     const int ci = min(max(col, 0), nr - 1);
     const int hi = min(max(col, 0), nr - 2);
@@ -191,9 +190,10 @@ __global__ void __launch_bounds__(256)
         R.sh = sh;
         R.g = G;
         if constexpr (SPIN) {  // forward (as in the step kernel)
+            // Lanes outside the grid hold the clamped edge column, unmasked:
+            // a spin term of an owned column reads them only at the radial
+            // boundary, multiplied by cotangents that are zero there.
             AdjFwd<true>& F = R.f;
-            p = masked(p, in);
-            q = masked(q, in);
             const cd pr = from_right(p), qr = from_right(q);
             F.ubp = cavg(p, pr);
             F.ubq = cavg(q, qr);
