@@ -296,13 +296,16 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
     const int ci = min(max(col, 0), nr - 1);
     const int hi = min(max(col, 0), nr - 2);
 
+    // This lane's radial factors (kind 0: its column, kind 1: its half
+    // point), loaded here and written to the wavefront's LDS slice once the
+    // loads of the first rows are in flight too, so that the two latencies
+    // overlap at the start of the tile.
+    double tv[2 * kNumRad];
     if constexpr (KERR) {
-        // this wavefront's slice: lane-private values, written and read by
-        // the same lane, so no barrier is needed
 #pragma unroll
         for (int f = 0; f < kNumRad; ++f) {
-            rs[(0 * kNumRad + f) * kWave + lane] = rad[((size_t)f * 2 + 0) * P + ci];
-            rs[(1 * kNumRad + f) * kWave + lane] = rad[((size_t)f * 2 + 1) * P + hi];
+            tv[f] = rad[((size_t)f * 2 + 0) * P + ci];
+            tv[kNumRad + f] = rad[((size_t)f * 2 + 1) * P + hi];
         }
     }
     // radial factors of this lane's column (kind 0) or half point (kind 1);
@@ -453,37 +456,49 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
     Row a_cur, b_cur;
     Coef kh_a, ki_b;
     cd a_hbp_m, b_hbp_m;
+    // The rows the prologue starts from (step A's rows aS-1 .. aS+2, i.e.
+    // j0-2 .. j0+1) and the first two of the main sweep's ring, all loaded
+    // before the radial factors are written to LDS.
+    const int aS = max(j0 - 1, 0);
+    cd pp[4], pq[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) load_row(aS - 1 + u, pp[u], pq[u]);
+    cd bp[kRowsInFlight2], bq[kRowsInFlight2];
+#pragma unroll
+    for (int u = 0; u < kRowsInFlight2; ++u) load_row(j0 + 2 + u, bp[u], bq[u]);
+    if constexpr (KERR) {
+        // this wavefront's slice: lane-private values, written and read by
+        // the same lane, so no barrier is needed
+#pragma unroll
+        for (int f = 0; f < 2 * kNumRad; ++f) rs[f * kWave + lane] = tv[f];
+    }
     {
-        cd p, q;
         // step A's rows j0-2 (halo) .. j0+1
         cd ubp_m = {0.0, 0.0};
-        const int aS = max(j0 - 1, 0);
         if (aS > 0) {
-            load_row(aS - 1, p, q);
             const Ang G = ang_row(aS - 1);
-            const Row h = fresh(aS - 1, p, q, ubp_m, false, G, coef_h(aS - 1, G));
+            const Row h = fresh(aS - 1, pp[0], pq[0], ubp_m, false, G, coef_h(aS - 1, G));
             sample(aS - 1, h.p, acc_in);
             ubp_m = h.ubp;
             a_hbp_m = h.hbp;
         }
-        load_row(aS, p, q);
         {
             const Ang G = ang_row(aS);
             kh_a = coef_h(aS, G);
-            a_cur = fresh(aS, p, q, ubp_m, true, G, kh_a);
+            a_cur = fresh(aS, pp[1], pq[1], ubp_m, true, G, kh_a);
         }
         sample(aS, a_cur.p, acc_in);
         if (aS == 0) a_hbp_m = cscale(sg, a_cur.hbp);
         cd b_ubp_m = {0.0, 0.0};
-        for (int r = aS; r <= j0; ++r) {  // one or two rows, wavefront-uniform
+        // A completes row r with row r+1 = (p1, q1) arriving; B takes row r
+        auto prologue_row = [&](int r, cd p1, cd q1) {
             Row a_nxt;
             Coef kh_n;
             cd ubp_p, hbp_p;
             if (r + 1 < nth) {
-                load_row(r + 1, p, q);
                 const Ang G = ang_row(r + 1);
                 kh_n = coef_h(r + 1, G);
-                a_nxt = fresh(r + 1, p, q, a_cur.ubp, true, G, kh_n);
+                a_nxt = fresh(r + 1, p1, q1, a_cur.ubp, true, G, kh_n);
                 sample(r + 1, a_nxt.p, acc_in);
                 ubp_p = a_nxt.ubp;
                 hbp_p = a_nxt.hbp;
@@ -511,14 +526,13 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
                 if (r == 0) b_hbp_m = cscale(sg, b_cur.hbp);
             }
             kh_a = kh_n;
-        }
+        };
+        prologue_row(aS, pp[2], pq[2]);                    // one or two rows,
+        if (j0 > aS) prologue_row(aS + 1, pp[3], pq[3]);  // wavefront-uniform
     }
 
     // ---- main sweep: A completes row r (reading row r+1 from the ring), B
     // completes row r-1 --------------------------------------------------
-    cd bp[kRowsInFlight2], bq[kRowsInFlight2];
-#pragma unroll
-    for (int u = 0; u < kRowsInFlight2; ++u) load_row(j0 + 2 + u, bp[u], bq[u]);
     Ang g_next = ang_row(j0 + 2);
 
     // Step A completes row r (reading row r+1 from the ring), step B row
