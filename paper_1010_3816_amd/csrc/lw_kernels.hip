@@ -70,6 +70,28 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
     const double sg = (double)A.sigma;
     const int last = (j1 < nth) ? j1 : nth - 1;  // last row this tile reads
 
+    // The prologue's rows (j0-1, or row 0 again for the first tile, and j0)
+    // and the ring's first rows, loaded right after the radial factors so
+    // that the latencies overlap at the start of the tile.
+    cd hp[2], hq[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const size_t o = (size_t)max(j0 - 1 + k, 0) * P + ci;
+        hp[k] = ld(u_in, o);
+        hq[k] = ld(u_in, o + A.plane);
+    }
+    // Ring of D row buffers: buffer u holds row t+1 when row t (t - j0 = u
+    // mod D) is finished, and is refilled with row t+1+D right after.  The
+    // loop is unrolled by D so that loaded registers are never copied (a copy
+    // would have to wait for the load), keeping D rows in flight.
+    cd bp[kRowsInFlight], bq[kRowsInFlight];
+#pragma unroll
+    for (int u = 0; u < kRowsInFlight; ++u) {
+        const size_t o = (size_t)min(j0 + 1 + u, last) * P + ci;
+        bp[u] = ld(u_in, o);
+        bq[u] = ld(u_in, o + A.plane);
+    }
+
     // the (at most one) extraction point of this tile, in scalar registers
     int e_id = -1, e_lane = 0, e_ra = -1, e_rb = -1;
     double e_wr = 0.0, e_wa = 0.0, e_wb = 0.0;
@@ -162,30 +184,16 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
     {
         cd ubp_m = {0.0, 0.0};
         if (j0 > 0) {
-            const size_t o = (size_t)(j0 - 1) * P + ci;
-            const Row rm = fresh(j0 - 1, ld(u_in, o), ld(u_in, o + A.plane), ubp_m, false, ang_row(j0 - 1));
+            const Row rm = fresh(j0 - 1, hp[0], hq[0], ubp_m, false, ang_row(j0 - 1));
             ubp_m = rm.ubp;
             hbp_m = rm.hbp;
         }
-        const size_t o = (size_t)j0 * P + ci;
-        cur = fresh(j0, ld(u_in, o), ld(u_in, o + A.plane), ubp_m, true, ang_row(j0));
+        cur = fresh(j0, hp[1], hq[1], ubp_m, true, ang_row(j0));
         if (j0 == 0) hbp_m = cscale(sg, cur.hbp);
     }
     // angular factors of the row after the next one to be finished, loaded
     // one row ahead so that their scalar loads are complete when needed
     Ang g_next = ang_row(j0 + 1);
-
-    // Ring of D row buffers: buffer u holds row t+1 when row t (t - j0 = u
-    // mod D) is finished, and is refilled with row t+1+D right after.  The
-    // loop is unrolled by D so that loaded registers are never copied (a copy
-    // would have to wait for the load), keeping D rows in flight.
-    cd bp[kRowsInFlight], bq[kRowsInFlight];
-#pragma unroll
-    for (int u = 0; u < kRowsInFlight; ++u) {
-        const size_t o = (size_t)min(j0 + 1 + u, last) * P + ci;
-        bp[u] = ld(u_in, o);
-        bq[u] = ld(u_in, o + A.plane);
-    }
 
     auto finish_row = [&](int t, cd& rp, cd& rq) {
         // row t+1: streamed, or the pole ghost row
