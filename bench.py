@@ -134,6 +134,53 @@ def cpu_baseline(w, target_seconds=10.0):
             "sample": f"{n} steps of the full {w['nr']}x{w['ntheta']} grid ({el:.1f} s), after 1 untimed step"}
 
 
+def waveform_leg(n_samples=500, sample_every=2):
+    """The field from its modes: nine modes m = -4..4 (s = -2, a = 0.7) on the
+    6400 x 256 grid, advanced as one batch and sampled at four observers every
+    `sample_every` steps (one launch for all modes and observers), then summed
+    into Psi = r^3 sum_m e^{i m phi} Phi_m.  Member grid-point updates/s over
+    the sampled evolution, the share of that time spent sampling, and the
+    assembly time."""
+    import torch
+
+    from paper_1010_3816_amd import inputs
+    from paper_1010_3816_amd.waveform import ModeSet
+
+    a, s, nr, nth, r0, r1 = 0.7, -2, 6400, 256, -100.0, 600.0
+    modes = list(range(-4, 5))
+    steps = n_samples * sample_every
+    dr = (r1 - r0) / (nr - 1)
+    dt = min(inputs.stable_dt(dr, nth, m, s, steps) for m in modes)
+    obs = [(500.0, math.pi / 2, 0.0), (500.0, math.pi / 2, math.pi / 3), (500.0, math.pi / 4, 0.0),
+           (300.0, 2.0, 1.0)]
+    W = ModeSet(a, s, modes, nr, nth, r0, r1, dt, obs)
+    for m in modes:
+        p, q = inputs.gaussian_pulse(nr, nth, r0, r1, 12.0, 4.0, "regular", m, s)
+        W.set_initial_data(m, torch.from_numpy(p).cuda(), torch.from_numpy(q).cuda())
+    W.evolve(4, sample_every)  # warm-up (captures the batch's graph)
+    stream = W.batch.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    samples = W.evolve(n_samples, sample_every)
+    ev[1].record(stream)
+    psi = W.assemble(samples)
+    ev[2].record(stream)
+    ev[3].record(stream)
+    W.batch.step(steps)  # the same steps without sampling
+    ev[4].record(stream)
+    torch.cuda.synchronize()
+    ms_evolve, ms_assemble, ms_plain = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[3].elapsed_time(ev[4])
+    assert bool(torch.isfinite(psi.real).all()) and bool(torch.isfinite(psi.imag).all()), "Psi became non-finite"
+    pts = W.batch.total_points()
+    W.close()
+    return {"modes": len(modes), "m": [modes[0], modes[-1]], "grid": f"{nr}x{nth}", "points_per_step": pts,
+            "steps": steps, "sample_every": sample_every, "observers": len(obs),
+            "value": pts * steps / (ms_evolve * 1e-3), "unit": "member grid-point updates/s",
+            "ms_per_step": ms_evolve / steps, "sampling_share": 1.0 - ms_plain / ms_evolve,
+            "assemble_ms": ms_assemble, "samples": n_samples}
+
+
 def batched_leg(steps=200, launch=None):
     """64 uneven evolutions in one persistent launch per step (autotuned
     unless `launch` = (rows, waves_per_block, blocks) is given)."""
@@ -238,7 +285,7 @@ def main():
     ap.add_argument("--workload", default="kerr_a0.99_25600x512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint legs")
-    ap.add_argument("--only", choices=["batched", "adjoint"],
+    ap.add_argument("--only", choices=["batched", "adjoint", "waveform"],
                     help="run only this leg and print its JSON object (for profiling)")
     ap.add_argument("--batch-launch", default=None,
                     help="rows,waves_per_block,blocks for the batched leg (default: autotune)")
@@ -262,6 +309,9 @@ def main():
     launch = tuple(int(x) for x in args.batch_launch.split(",")) if args.batch_launch else None
     if args.only == "batched":
         print(json.dumps(batched_leg(launch=launch)), flush=True)
+        return
+    if args.only == "waveform":
+        print(json.dumps(waveform_leg()), flush=True)
         return
     if args.only == "adjoint":
         print(json.dumps(adjoint_leg()), flush=True)
@@ -363,6 +413,9 @@ def main():
         bl = batched_leg(launch=launch)
         bl["ratio_to_single"] = bl["value"] / ups
         out["batched"] = bl
+        wl = waveform_leg()
+        wl["ratio_to_single"] = wl["value"] / ups
+        out["waveform"] = wl
         out["adjoint"] = adjoint_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
