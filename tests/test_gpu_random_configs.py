@@ -1,0 +1,92 @@
+"""Seeded random configurations through the C ABI against the oracle.
+
+Each case draws the grid size (Nr in [3, 700), Ntheta in [2, 80)), the spin,
+the spin weight, the mode, the launch shape, the number of steps and up to
+three extraction points from a fixed-seed generator, so that the sweep covers
+combinations the hand-written cases do not (ragged strips and chunks of every
+size, pole rows inside and at the edges of tiles, extraction points anywhere).
+
+Forward: one and two steps per pass bit-identical; state and series within
+1e-11 normwise of the oracle.  Adjoint: the spin path's cotangents within
+1e-11 of the oracle's transposed steps and dL/da within 1e-10; the
+cotangent-only paths (one and two steps per pass) bit-identical to the spin
+path's cotangents.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1010_3816_amd import inputs
+from parity import oracle_segment_adjoint, rel_err, run_gpu, run_oracle, small_case
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def _draw(seed, n_max, ext_min):
+    rng = np.random.default_rng(seed)
+    c = dict(nr=int(rng.integers(3, 700)), nth=int(rng.integers(2, 80)), a=float(rng.uniform(0, 0.99)),
+             s=int(rng.choice([-2, -1, 0, 1, 2])), m=int(rng.integers(-4, 5)))
+    c["rows"] = int(rng.integers(1, c["nth"] + 1))
+    c["wpb"] = int(rng.choice([1, 2, 4]))
+    c["n"] = int(rng.integers(1, n_max))
+    ne = int(rng.integers(ext_min, 4))
+    c["ext"] = tuple((float(rng.uniform(-30.0, 60.0)), float(rng.uniform(0, math.pi))) for _ in range(ne))
+    c["gser"] = rng.standard_normal((c["n"], max(ne, 1))) + 1j * rng.standard_normal((c["n"], max(ne, 1)))
+    return c
+
+
+@pytest.mark.parametrize("case", range(24))
+def test_random_forward(gpu, case):
+    c = _draw(5000 + case, 10, 0)
+    w = small_case(c["a"], c["s"], c["m"], c["nr"], c["nth"], ext=c["ext"])
+    phi0, pi0 = inputs.random_state(c["nr"], c["nth"], seed=6000 + case)
+    one = run_gpu(gpu, w, phi0, pi0, c["n"], tile=(c["rows"], c["wpb"]), steps_per_pass=1)
+    two = run_gpu(gpu, w, phi0, pi0, c["n"], tile=(c["rows"], c["wpb"]), steps_per_pass=2)
+    for k in range(3):
+        if one[k] is not None:
+            assert np.array_equal(one[k], two[k]), (c, k)
+    o = run_oracle(w, phi0, pi0, c["n"])
+    assert rel_err(two[0], o[0]) <= TOL and rel_err(two[1], o[1]) <= TOL, c
+    if c["ext"]:
+        assert rel_err(two[2], o[2]) <= TOL, c
+
+
+@pytest.mark.parametrize("case", range(16))
+def test_random_adjoint(gpu, case):
+    c = _draw(7000 + case, 8, 1)
+    nr, nth, n = c["nr"], c["nth"], c["n"]
+    w = small_case(c["a"], c["s"], c["m"], nr, nth, ext=c["ext"])
+    phi0, pi0 = inputs.random_state(nr, nth, seed=8000 + case)
+    lam0 = inputs.random_state(nr, nth, seed=9000 + case)
+    o = oracle.OracleGrid(c["a"], c["s"], c["m"], nr, nth, w["rstar_min"], w["rstar_max"], w["dt"])
+    p, q = o.project(phi0, pi0)
+    states = []
+    for _ in range(n):
+        states.append((p.copy(), q.copy()))
+        p, q = o.step(p, q, 1)
+    ref_p, ref_q, ref_dlda = oracle_segment_adjoint(o, states, lam0[0], lam0[1], c["gser"], w["extract_rstar"],
+                                                    w["extract_theta"])
+    g = gpu.TeukGrid(c["a"], c["s"], c["m"], nr, nth, w["rstar_min"], w["rstar_max"], w["dt"],
+                     extract_rstar=w["extract_rstar"], extract_theta=w["extract_theta"])
+    g.set_adjoint_tile(c["rows"], c["wpb"])
+    g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
+    win = g.new_window(n)
+    g.step_store(n, win)
+    gs = torch.from_numpy(c["gser"]).cuda()
+    outs = []
+    for spin, spp in ((True, 2), (False, 1), (False, 2)):
+        g.set_steps_per_pass(spp)
+        lp = torch.from_numpy(lam0[0].copy()).cuda()
+        lq = torch.from_numpy(lam0[1].copy()).cuda()
+        d = g.adjoint(n, lp, lq, gs, win if spin else None, spin=spin)
+        torch.cuda.synchronize()
+        outs.append((lp.cpu().numpy(), lq.cpu().numpy(), d))
+    g.close()
+    for k in (1, 2):
+        assert np.array_equal(outs[0][0], outs[k][0]) and np.array_equal(outs[0][1], outs[k][1]), (c, k)
+    assert rel_err(outs[0][0], ref_p) <= TOL and rel_err(outs[0][1], ref_q) <= TOL, c
+    assert abs(outs[0][2] - ref_dlda) <= 1e-10 * abs(ref_dlda), (c, outs[0][2], ref_dlda)
