@@ -10,7 +10,8 @@ Forward: one and two steps per pass bit-identical; state and series within
 1e-11 normwise of the oracle.  Adjoint: the spin path's cotangents within
 1e-11 of the oracle's transposed steps and dL/da within 1e-10; the
 cotangent-only paths (one and two steps per pass) bit-identical to the spin
-path's cotangents.
+path's cotangents.  Batch: random member sets and persistent launch shapes
+bit-identical to single-grid evolutions and extractions.
 """
 import math
 
@@ -90,3 +91,49 @@ def test_random_adjoint(gpu, case):
         assert np.array_equal(outs[0][0], outs[k][0]) and np.array_equal(outs[0][1], outs[k][1]), (c, k)
     assert rel_err(outs[0][0], ref_p) <= TOL and rel_err(outs[0][1], ref_q) <= TOL, c
     assert abs(outs[0][2] - ref_dlda) <= 1e-10 * abs(ref_dlda), (c, outs[0][2], ref_dlda)
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_random_batch(gpu, case):
+    """2-6 members of random size and physics, a random launch shape and
+    steps per pass, an odd or even step count: every member equals its
+    single-grid evolution bit for bit, and the batch's samples equal the
+    single grids' extraction."""
+    rng = np.random.default_rng(11000 + case)
+    members, data, ext = [], [], []
+    for k in range(int(rng.integers(2, 7))):
+        nr, nth = int(rng.integers(3, 500)), int(rng.integers(2, 70))
+        a, s, m = float(rng.uniform(0, 0.99)), int(rng.choice([-2, 0, 2])), int(rng.integers(-4, 5))
+        r0 = float(rng.uniform(-60.0, 0.0))
+        r1 = r0 + float(rng.uniform(20.0, 120.0))
+        dt = inputs.stable_dt((r1 - r0) / (nr - 1), nth, m, s, 50)
+        pts = [(float(rng.uniform(r0, r1)), float(rng.uniform(0, math.pi))) for _ in range(int(rng.integers(0, 3)))]
+        members.append(dict(a=a, s=s, m=m, nr=nr, ntheta=nth, rstar_min=r0, rstar_max=r1, dt=dt,
+                            extract_rstar=[p[0] for p in pts], extract_theta=[p[1] for p in pts]))
+        data.append(inputs.random_state(nr, nth, seed=12000 + 10 * case + k))
+        ext.append(pts)
+    rows, wpb = int(rng.integers(1, 80)), int(rng.choice([1, 2, 4]))
+    blocks = int(rng.integers(1, 2049))
+    spp, n = int(rng.choice([1, 2])), int(rng.integers(1, 9))
+    b = gpu.TeukBatch(members)
+    b.set_launch(rows, wpb, blocks)
+    b.set_steps_per_pass(spp)
+    for k, (p, q) in enumerate(data):
+        b.set_initial_data(k, torch.from_numpy(p).cuda(), torch.from_numpy(q).cuda())
+    b.step(n)
+    got = [[t.cpu().numpy() for t in b.state(k)] for k in range(len(members))]
+    samples = b.extract().cpu().numpy() if b.n_extract() else None
+    b.close()
+    off = 0
+    for k, mb in enumerate(members):
+        g = gpu.TeukGrid(mb["a"], mb["s"], mb["m"], mb["nr"], mb["ntheta"], mb["rstar_min"], mb["rstar_max"],
+                         mb["dt"])
+        g.set_initial_data(torch.from_numpy(data[k][0]).cuda(), torch.from_numpy(data[k][1]).cuda())
+        g.step(n)
+        ref = [t.cpu().numpy() for t in g.state()]
+        if ext[k]:
+            want = g.extract([p[0] for p in ext[k]], [p[1] for p in ext[k]]).cpu().numpy()
+            assert np.array_equal(samples[off:off + len(ext[k])], want), (case, k)
+            off += len(ext[k])
+        g.close()
+        assert np.array_equal(got[k][0], ref[0]) and np.array_equal(got[k][1], ref[1]), (case, k, rows, wpb, blocks)
