@@ -77,6 +77,32 @@ __device__ __forceinline__ Rad rad_from_lds(lds_cptr rs, int o) {
     return R;
 }
 
+// Tile of a wavefront.  Tiles are numbered strip-major (the theta chunks of
+// a strip consecutive) and workgroup b takes tiles b*wpb .. b*wpb + wpb - 1,
+// so the tile count need not be a multiple of wpb per strip and a launch can
+// fill every wavefront slot of the device.  A workgroup's tiles lie in at
+// most two consecutive strips when wpb <= n_chunks + 1 (the host keeps it
+// so); it holds the radial tables of both in LDS, as two slices.
+struct TileOf {
+    int strip, chunk;  // of this wavefront's tile
+    int s0, n_slices;  // the workgroup's first strip and its number of strips (1 or 2)
+    int slice;         // this wavefront's slice, strip - s0
+    bool valid;        // false for wavefronts past the last tile
+};
+
+__device__ __forceinline__ TileOf tile_of(int b, int wpb, int wave, int n_strips, int n_chunks) {
+    TileOf T;
+    const int n_tiles = n_strips * n_chunks;
+    const int first = b * wpb, tile = first + wave;
+    T.valid = tile < n_tiles;
+    T.s0 = first / n_chunks;
+    T.n_slices = min((min(first + wpb, n_tiles) - 1) / n_chunks - T.s0 + 1, 2);
+    T.strip = min(tile, n_tiles - 1) / n_chunks;
+    T.chunk = tile - T.strip * n_chunks;
+    T.slice = min(T.strip - T.s0, 1);
+    return T;
+}
+
 // complex helpers for the transposed operators
 __device__ __forceinline__ cd cadd3(cd a, cd b, cd c) { return {a.re + b.re + c.re, a.im + b.im + c.im}; }
 // (x + i y) * (re + i im)
@@ -135,30 +161,31 @@ __global__ void __launch_bounds__(256)
     constexpr int kRIF = SPIN ? kAdjRowsInFlight : TEUK_ADJ_ROWS_IN_FLIGHT_NOSPIN;
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
-    // a workgroup owns one strip and wpb consecutive theta chunks, so that it
-    // shares one LDS copy of the strip's radial tables
-    const int bid = xcd_block(blockIdx.x, gridDim.x);
-    const int strip = bid % A.n_strips;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int chunk = (bid / A.n_strips) * wpb + wave;
+    const TileOf T = tile_of(xcd_block(blockIdx.x, gridDim.x), wpb, wave, A.n_strips, A.n_chunks);
+    const int strip = T.strip, chunk = T.chunk;
     const int nr = A.nr, nth = A.nth, P = A.pitch;
     const int col = strip * kStripCols - 1 + lane;
     const unsigned long long interior = ((col >= 1) && (col < nr - 1)) ? ~0ull : 0ull;
     const int ci = min(max(col, 0), nr - 1);
-    const int hi = min(max(col, 0), nr - 2);
 
-    __shared__ double rad_s[4 * kNumRad * kWave];
-    for (int f = wave; f < (SPIN ? 4 : 2) * kNumRad; f += wpb) {
-        const int deriv = f / (2 * kNumRad), kind = (f / kNumRad) % 2, field = f % kNumRad;
+    // the radial tables of the workgroup's strips: [strip][value/derivative][integer/half][field][lane]
+    // (dynamic LDS, adjoint_lds_bytes)
+    constexpr int kF = (SPIN ? 4 : 2) * kNumRad;
+    extern __shared__ double rad_s[];
+    for (int f = wave; f < T.n_slices * kF; f += wpb) {
+        const int g = f % kF, deriv = g / (2 * kNumRad), kind = (g / kNumRad) % 2, field = g % kNumRad;
+        const int c = min(max((T.s0 + f / kF) * kStripCols - 1 + lane, 0), nr - 1);
         const double* src = deriv ? rad_da : rad;
-        rad_s[f * kWave + lane] = src[((size_t)field * 2 + kind) * P + (kind == 0 ? ci : hi)];
+        rad_s[f * kWave + lane] = src[((size_t)field * 2 + kind) * P + (kind == 0 ? c : min(c, nr - 2))];
     }
     __syncthreads();
-    if (chunk >= A.n_chunks) return;  // wavefront-uniform
-    lds_cptr rvi = (lds_cptr)(rad_s + 0 * kNumRad * kWave + lane);
-    lds_cptr rvh = (lds_cptr)(rad_s + 1 * kNumRad * kWave + lane);
-    lds_cptr rdi = (lds_cptr)(rad_s + 2 * kNumRad * kWave + lane);
-    lds_cptr rdh = (lds_cptr)(rad_s + 3 * kNumRad * kWave + lane);
+    if (!T.valid) return;  // wavefront-uniform
+    const double* slice = rad_s + T.slice * kF * kWave + lane;
+    lds_cptr rvi = (lds_cptr)(slice + 0 * kNumRad * kWave);
+    lds_cptr rvh = (lds_cptr)(slice + 1 * kNumRad * kWave);
+    lds_cptr rdi = (lds_cptr)(slice + 2 * kNumRad * kWave);
+    lds_cptr rdh = (lds_cptr)(slice + 3 * kNumRad * kWave);
 
     const bool own = (lane >= 1) && (lane <= kWave - 2) && (col < nr);  // columns and halves this tile owns
     const int j0 = chunk * A.rows;
@@ -441,25 +468,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
                        const double* __restrict__ gsample_b, AdjScalars A) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
-    const int bid = xcd_block(blockIdx.x, gridDim.x);
-    const int strip = bid % A.n_strips;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int chunk = (bid / A.n_strips) * wpb + wave;
+    const TileOf T = tile_of(xcd_block(blockIdx.x, gridDim.x), wpb, wave, A.n_strips, A.n_chunks);
+    const int strip = T.strip, chunk = T.chunk;
     const int nr = A.nr, nth = A.nth, P = A.pitch;
     const int col = strip * kStripCols2 - 2 + lane;
     const unsigned long long interior = ((col >= 1) && (col < nr - 1)) ? ~0ull : 0ull;
     const int ci = min(max(col, 0), nr - 1);
-    const int hi = min(max(col, 0), nr - 2);
 
-    __shared__ double rad_s[2 * kNumRad * kWave];
-    for (int f = wave; f < 2 * kNumRad; f += wpb) {
-        const int kind = f / kNumRad, field = f % kNumRad;
-        rad_s[f * kWave + lane] = rad[((size_t)field * 2 + kind) * P + (kind == 0 ? ci : hi)];
+    constexpr int kF = 2 * kNumRad;
+    extern __shared__ double rad_s[];  // as in lw_adjoint_kernel<false>
+    for (int f = wave; f < T.n_slices * kF; f += wpb) {
+        const int g = f % kF, kind = g / kNumRad, field = g % kNumRad;
+        const int c = min(max((T.s0 + f / kF) * kStripCols2 - 2 + lane, 0), nr - 1);
+        rad_s[f * kWave + lane] = rad[((size_t)field * 2 + kind) * P + (kind == 0 ? c : min(c, nr - 2))];
     }
     __syncthreads();
-    if (chunk >= A.n_chunks) return;  // wavefront-uniform
-    lds_cptr rvi = (lds_cptr)(rad_s + 0 * kNumRad * kWave + lane);
-    lds_cptr rvh = (lds_cptr)(rad_s + 1 * kNumRad * kWave + lane);
+    if (!T.valid) return;  // wavefront-uniform
+    const double* slice = rad_s + T.slice * kF * kWave + lane;
+    lds_cptr rvi = (lds_cptr)(slice + 0 * kNumRad * kWave);
+    lds_cptr rvh = (lds_cptr)(slice + 1 * kNumRad * kWave);
 
     const bool own = (lane >= 2) && (lane <= kWave - 3) && (col < nr);
     const int j0 = chunk * A.rows;
@@ -704,19 +732,36 @@ __global__ void zero_radial_boundary_kernel(double2* __restrict__ u, int nr, int
 
 }  // namespace
 
+// Workgroups of wpb consecutive tiles (strip-major), wpb at most n_chunks + 1
+// so that a workgroup spans at most two strips.  The LDS holds one strip's
+// tables (fields_per_strip doubles per lane) when no workgroup spans two,
+// i.e. when wpb divides the chunks of a strip or there is one strip, and two
+// otherwise.
+static void adjoint_launch_shape(const AdjScalars& k, int waves_per_block, int fields_per_strip, dim3* grid,
+                                 dim3* block, size_t* lds_bytes) {
+    const int w = std::min(waves_per_block, k.n_chunks + 1);
+    const int64_t tiles = (int64_t)k.n_strips * k.n_chunks;
+    const int slices = (k.n_chunks % w == 0 || k.n_strips == 1) ? 1 : 2;
+    *block = dim3(kWave * w);
+    *grid = dim3((unsigned)((tiles + w - 1) / w));
+    *lds_bytes = (size_t)slices * fields_per_strip * kWave * sizeof(double);
+}
+
 hipError_t launch_adjoint(const AdjArgs& a, int waves_per_block, bool spin, hipStream_t s) {
-    const int groups = (a.k.n_chunks + waves_per_block - 1) / waves_per_block;
-    const dim3 block(kWave * waves_per_block), grid(a.k.n_strips * groups);
+    dim3 grid, block;
+    size_t lds;
+    adjoint_launch_shape(a.k, waves_per_block, (spin ? 4 : 2) * kNumRad, &grid, &block, &lds);
     auto kern = spin ? lw_adjoint_kernel<true> : lw_adjoint_kernel<false>;
-    hipLaunchKernelGGL(kern, grid, block, 0, s, a.nu_in, a.u_in, a.lam_out, a.rad, a.rad_da, a.ang, a.slots, a.ext,
+    hipLaunchKernelGGL(kern, grid, block, lds, s, a.nu_in, a.u_in, a.lam_out, a.rad, a.rad_da, a.ang, a.slots, a.ext,
                        a.gsample, a.k);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint2(const AdjArgs& a, const double* gsample_b, int waves_per_block, hipStream_t s) {
-    const int groups = (a.k.n_chunks + waves_per_block - 1) / waves_per_block;
-    const dim3 block(kWave * waves_per_block), grid(a.k.n_strips * groups);
-    hipLaunchKernelGGL(lw_adjoint2_kernel, grid, block, 0, s, a.nu_in, a.lam_out, a.rad, a.ang, a.ext, a.gsample,
+    dim3 grid, block;
+    size_t lds;
+    adjoint_launch_shape(a.k, waves_per_block, 2 * kNumRad, &grid, &block, &lds);
+    hipLaunchKernelGGL(lw_adjoint2_kernel, grid, block, lds, s, a.nu_in, a.lam_out, a.rad, a.ang, a.ext, a.gsample,
                        gsample_b, a.k);
     return hipGetLastError();
 }

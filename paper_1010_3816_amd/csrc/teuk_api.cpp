@@ -255,14 +255,13 @@ void default_tile(int nr, int nth, int cus, int* rows, int* wpb) {
     *wpb = tiles < (int64_t)cus * 4 ? 1 : 4;
 }
 
-// Default tile of the adjoint kernels (four wavefronts per workgroup, each
-// workgroup taking four theta chunks of one strip): the shortest tiles whose
-// workgroups fit one round of two wavefronts per SIMD, at most 16 rows.
+// Default tile of the adjoint kernels: the shortest tiles of which one round
+// of two wavefronts per SIMD holds all (workgroups take consecutive tiles of
+// the strip-major list, so any tile count packs), at most 16 rows.
 int default_adjoint_rows(int nr, int nth, int cus) {
     const int64_t strips = (nr + kStripCols - 1) / kStripCols;
-    const int64_t groups = (int64_t)cus * 8 / 4 / strips;  // workgroups per strip in one round
-    if (groups < 1) return std::min(nth, 16);
-    const int64_t chunks = groups * 4;
+    const int64_t chunks = (int64_t)cus * 8 / strips;  // theta chunks per strip in one round
+    if (chunks < 1) return std::min(nth, 16);
     return (int)std::min<int64_t>(std::min<int64_t>((nth + chunks - 1) / chunks, 16), nth);
 }
 

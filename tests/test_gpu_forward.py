@@ -242,10 +242,10 @@ def _default_rows(nr, nth, cus):
 
 
 def _default_adjoint_rows(nr, nth, cus):
-    groups = cus * 8 // 4 // -(-nr // 62)
-    if groups < 1:
+    chunks = cus * 8 // -(-nr // 62)
+    if chunks < 1:
         return min(nth, 16)
-    return min(-(-nth // (4 * groups)), 16, nth)
+    return min(-(-nth // chunks), 16, nth)
 
 
 @pytest.mark.parametrize("nr,nth", [(25600, 512), (6400, 256), (400, 32), (12800, 128), (70000, 64)])
@@ -263,7 +263,7 @@ def test_default_tile_fills_whole_rounds(gpu, nr, nth):
     assert wpb == (1 if tiles < 4 * cus else 4)
     assert adj == (_default_adjoint_rows(nr, nth, cus), 4)
     if cus == 256:
-        expect = {(25600, 512): (57, 4, 16), (6400, 256): (14, 4, 16), (400, 32): (1, 1, 1)}.get((nr, nth))
+        expect = {(25600, 512): (57, 4, 16), (6400, 256): (14, 4, 14), (400, 32): (1, 1, 1)}.get((nr, nth))
         if expect:
             assert (rows, wpb, adj[0]) == expect
 
