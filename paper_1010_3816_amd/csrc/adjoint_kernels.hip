@@ -24,40 +24,41 @@
 namespace teuk {
 namespace {
 
-// d/da of kerr_coef: R, dR are the radial factors and their a-derivatives
-// at the position, s = (1/Sigma, 1/Sigma^2), c the coefficient values.
-__device__ __forceinline__ Coef kerr_coef_da(const Rad& R, const Rad& dR, const Ang& G, Sig s, const Coef& c) {
-    const double dsig2 = fma(-dR.a2d, G.sn2, dR.rho2);
-    const double dinv = -s.inv * s.inv * dsig2;
-    const double disig = -0.5 * s.isig * s.inv * dsig2;
-    Coef d;
-    d.b = fma(dR.rho, s.isig, R.rho * disig);
-    const double T = fma(-R.rb3, G.sn2, R.rb2);
-    const double dT = fma(-dR.rb3, G.sn2, dR.rb2);
-    const double Q = fma(-T, s.inv, R.rb1);
-    const double dQ = dR.rb1 - fma(dT, s.inv, T * dinv);
-    const double bp = s.isig * Q;
-    const double dbp = fma(disig, Q, s.isig * dQ);
-    d.ctr = fma(dR.ctr, s.inv, R.ctr * dinv);
-    const double CI = fma(R.cti1, G.cs, R.cti0);
-    const double dCI = fma(dR.cti1, G.cs, dR.cti0);
-    d.cti = fma(dCI, s.inv, CI * dinv);
-    const double db1 = fma(dR.b1n, s.inv, R.b1n * dinv);
-    d.cre = fma(d.b, bp - c.ctr, c.b * (dbp - d.ctr)) - db1;
-    d.cim = -fma(d.b, c.cti, c.b * d.cti);
-    d.a2s = fma(dR.dl2, s.inv, R.dl2 * dinv);
-    d.a1s = d.a2s * G.cotp;
-    const double V = fma(R.dl2, G.pd, R.v0r);
-    const double dV = fma(dR.dl2, G.pd, dR.v0r);
-    d.v0r = fma(dV, s.inv, V * dinv);
-    d.v0i = fma(dR.v0i, s.inv, R.v0i * dinv);
-    return d;
-}
-
 // LDS copy of a strip's radial tables: [value/derivative][integer/half][field][lane].
 // `o` is a row-dependent offset that is 0 at run time (row & zero): it keeps
 // the reads inside the row loop instead of in (scarce) registers.
 typedef const __attribute__((address_space(3))) double* lds_cptr;
+
+// d/da of kerr_coef at one position from the a-derivative tables rd, four
+// value fields (rv), the angular factors, s = (1/Sigma, 1/Sigma^2) and the
+// coefficient values c.  With w = d(Sigma^2)/Sigma^2, a coefficient
+// X/Sigma^2 has derivative dX/Sigma^2 - c w and rho/Sigma has
+// drho/Sigma - c w/2, so most value fields are not needed again.
+__device__ __forceinline__ Coef kerr_coef_da(lds_cptr rv, lds_cptr rd, int o, const Ang& G, Sig s, const Coef& c) {
+    auto d = [&](int f) { return rd[o + f * kWave]; };
+    auto v = [&](int f) { return rv[o + f * kWave]; };
+    const double w = s.inv * fma(-d(R_A2D), G.sn2, d(R_RHO2));
+    const double hw = 0.5 * w;
+    Coef r;
+    r.b = fma(s.isig, d(R_RHO), -c.b * hw);
+    const double T = fma(-v(R_RB3), G.sn2, v(R_RB2));
+    const double dT = fma(-d(R_RB3), G.sn2, d(R_RB2));
+    const double Q = fma(-T, s.inv, v(R_RB1));
+    const double dQ = fma(-s.inv, fma(-T, w, dT), d(R_RB1));
+    const double bp = s.isig * Q;
+    const double dbp = s.isig * fma(-Q, hw, dQ);
+    r.ctr = fma(s.inv, d(R_CTR), -c.ctr * w);
+    r.cti = fma(s.inv, fma(d(R_CTI1), G.cs, d(R_CTI0)), -c.cti * w);
+    const double b1 = v(R_B1N) * s.inv;
+    const double db1 = fma(s.inv, d(R_B1N), -b1 * w);
+    r.cre = fma(r.b, bp - c.ctr, c.b * (dbp - r.ctr)) - db1;
+    r.cim = -fma(r.b, c.cti, c.b * r.cti);
+    r.a2s = fma(s.inv, d(R_DL2), -c.a2s * w);
+    r.a1s = r.a2s * G.cotp;
+    r.v0r = fma(s.inv, fma(d(R_DL2), G.pd, d(R_V0R)), -c.v0r * w);
+    r.v0i = fma(s.inv, d(R_V0I), -c.v0i * w);
+    return r;
+}
 
 __device__ __forceinline__ Rad rad_from_lds(lds_cptr rs, int o) {
     Rad R;
@@ -101,6 +102,19 @@ __device__ __forceinline__ TileOf tile_of(int b, int wpb, int wave, int n_strips
     T.chunk = tile - T.strip * n_chunks;
     T.slice = min(T.strip - T.s0, 1);
     return T;
+}
+
+// Extraction points (of the first n) whose bilinear stencil touches output
+// rows r_lo .. r_hi of a tile and the columns c0 .. c0 + 63 of its lanes, as
+// bits: the transposed extraction is applied row by row only for these.
+__device__ __forceinline__ unsigned ext_mask(const ExtPoint* __restrict__ ext, int n, int r_lo, int r_hi, int c0) {
+    unsigned m = 0;
+    for (int e = 0; e < n; ++e) {
+        const ExtPoint E = ext[e];
+        const bool rows = (E.rowa >= r_lo && E.rowa <= r_hi) || (E.rowb >= r_lo && E.rowb <= r_hi);
+        if (rows && E.col + 1 >= c0 && E.col <= c0 + kWave - 1) m |= 1u << e;
+    }
+    return m;
 }
 
 // complex helpers for the transposed operators
@@ -152,7 +166,7 @@ struct AdjRow {
 // they do not need u^m: no state rows are read, nothing of the forward step
 // is recomputed and no spin gradient is accumulated.
 template <bool SPIN>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
     lw_adjoint_kernel(const double2* __restrict__ nu_in, const double2* __restrict__ u_in,
                       double2* __restrict__ lam_out, const double* __restrict__ rad,
                       const double* __restrict__ rad_da, const double* __restrict__ ang,
@@ -193,6 +207,7 @@ __global__ void __launch_bounds__(256)
     const double sg = (double)A.sigma;
     const int last = (j1 < nth) ? j1 : nth - 1;
     double acc = 0.0;  // spin-gradient partial sum of this lane
+    const unsigned emask = ext_mask(ext, gsample ? A.n_ext : 0, j0, j1 - 1, strip * kStripCols - 1);
 
     // angular factors of row t (clamped: rows past the last are loaded
     // ahead but never used)
@@ -377,8 +392,9 @@ __global__ void __launch_bounds__(256)
         // transposed extraction of the sample of the output state: each
         // stencil point of an extraction point receives its bilinear weight
         // times the sample's gradient (gsample[e], re/im interleaved)
-        if (gsample != nullptr) {
+        if (emask != 0) {
             for (int e = 0; e < A.n_ext; ++e) {
+                if (!((emask >> e) & 1u)) continue;
                 const ExtPoint E = ext[e];
                 if (t != E.rowa && t != E.rowb) continue;  // wavefront-uniform
                 const double wrow = (t == E.rowa) ? E.wa : E.wb;
@@ -403,8 +419,8 @@ __global__ void __launch_bounds__(256)
             const cd hbq = cavg(hq, hql);
             const cd dhq = csub(hq, hql);
             const int o = t & A.zero;
-            const Coef dkh = kerr_coef_da(rad_from_lds(rvh, o), rad_from_lds(rdh, o), G, sh, kh);
-            const Coef dki = kerr_coef_da(rad_from_lds(rvi, o), rad_from_lds(rdi, o), G, si, ki);
+            const Coef dkh = kerr_coef_da(rvh, rdh, o, G, sh, kh);
+            const Coef dki = kerr_coef_da(rvi, rdi, o, G, si, ki);
             // half: dh_Phi = -dt/2dr db delta_Phi;  dh_Pi = -dt/2dr (dc dP - db dQ) + dt/2 dS(ubar)
             const cd dhP = cscale(-A.hdt_dr * dkh.b, F.dp);
             const cd dd1 = d_pi(dkh, F.dp, F.dq);
@@ -495,6 +511,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     const int aE = min(j1, nth - 1);        // last row sweep A completes
     const int last = min(aE + 1, nth - 1);  // last row of lambda^{m+2} read
     const double sg = (double)A.sigma;
+    // both sweeps' output rows, j0-1 .. j1
+    const unsigned emask = ext_mask(ext, (gsample_a || gsample_b) ? A.n_ext : 0, j0 - 1, j1, strip * kStripCols2 - 2);
 
     auto ang_row = [&](int t) -> Ang { return load_ang(ang, nth, min(t, nth - 1)); };
     // arrival of a row (as fresh() of lw_adjoint_kernel<false>)
@@ -553,8 +571,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
         const cd dQ = {fma(0.5, lubq.re, -ldq.re), fma(0.5, lubq.im, -ldq.im)};
         outp = cadd3(cur.np, dP, from_left(cP));
         outq = cadd3(cur.nq, dQ, from_left(cQ));
-        if (gsample != nullptr) {
+        if (gsample != nullptr && emask != 0) {
             for (int e = 0; e < A.n_ext; ++e) {
+                if (!((emask >> e) & 1u)) continue;
                 const ExtPoint E = ext[e];
                 if (t != E.rowa && t != E.rowb) continue;  // wavefront-uniform
                 const double wrow = (t == E.rowa) ? E.wa : E.wb;
