@@ -192,13 +192,16 @@ size_t teuk_adjoint_workspace_bytes(teuk_grid* g);
  * adjoint workspace.  KERR mode only.  Synchronous. */
 int teuk_enable_adjoint(teuk_grid* g, void* d_adj_workspace, size_t bytes);
 
-/* Launch shape of the adjoint kernel: theta rows per wavefront tile (1 ..
+/* Launch shape of the adjoint kernels: theta rows per wavefront tile (1 ..
  * ntheta) and wavefronts per workgroup (1, 2 or 4, default 4; a workgroup
  * takes consecutive tiles of the strip-major tile list, and at most
- * 1 + the chunks per strip of them).  The default rows are the fewest whose
- * tiles fit one round of two wavefronts per SIMD, at most 16.  The
- * cotangents do not depend on it; dL/da is summed per tile, so its last bits
- * may.  TEUK_E_INVALID_ARG outside these ranges. */
+ * 1 + the chunks per strip of them).  Default rows, at most 16: for the
+ * spin-gradient (and one-step) kernel the fewest whose tiles fit 7/8 of one
+ * round of two wavefronts per SIMD, leaving the rest to a recompute running
+ * beside it; for the two-step cotangent kernel the fewest that fit the whole
+ * round.  Setting the tile sets both; get returns the spin-gradient kernel's.
+ * The cotangents do not depend on it; dL/da is summed per tile, so its last
+ * bits may.  TEUK_E_INVALID_ARG outside these ranges. */
 int teuk_set_adjoint_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per_block);
 int teuk_get_adjoint_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per_block);
 

@@ -171,7 +171,8 @@ struct teuk_grid {
     // adjoint (teuk_enable_adjoint)
     char* aws = nullptr;      // adjoint workspace
     size_t aoff_lam[2]{}, aoff_da = 0, aoff_slots = 0, aoff_sum = 0;
-    int adj_rows = 32, adj_wpb = 4, adj_chunks = 0, adj_strips = 0;
+    int adj_rows = 32, adj_wpb = 4, adj_chunks = 0, adj_strips = 0;  // spin-gradient and one-step kernels
+    int adj2_rows = 32, adj2_chunks = 0;                              // two-step cotangent kernel
 
     double2* u(int k) const { return reinterpret_cast<double2*>(ws + L.off_u[k]); }
     template <class T>
@@ -255,12 +256,12 @@ void default_tile(int nr, int nth, int cus, int* rows, int* wpb) {
     *wpb = tiles < (int64_t)cus * 4 ? 1 : 4;
 }
 
-// Default tile of the adjoint kernels: the shortest tiles of which one round
-// of two wavefronts per SIMD holds all (workgroups take consecutive tiles of
-// the strip-major list, so any tile count packs), at most 16 rows.
-int default_adjoint_rows(int nr, int nth, int cus) {
-    const int64_t strips = (nr + kStripCols - 1) / kStripCols;
-    const int64_t chunks = (int64_t)cus * 8 / strips;  // theta chunks per strip in one round
+// Default tile height of an adjoint kernel: the shortest tiles of which
+// `slots` wavefronts hold all (workgroups take consecutive tiles of the
+// strip-major list, so any tile count packs), at most 16 rows.
+int adjoint_rows(int nr, int nth, int64_t slots, int strip_cols) {
+    const int64_t strips = (nr + strip_cols - 1) / strip_cols;
+    const int64_t chunks = slots / strips;  // theta chunks per strip
     if (chunks < 1) return std::min(nth, 16);
     return (int)std::min<int64_t>(std::min<int64_t>((nth + chunks - 1) / chunks, 16), nth);
 }
@@ -388,8 +389,14 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
             cus = 256;
         default_tile(nr, nth, cus, &g->rows, &g->wpb);
     }
-    g->adj_rows = default_adjoint_rows(nr, nth, cus);
+    // a device holds two adjoint wavefronts per SIMD (8 per CU).  The
+    // spin-gradient kernel leaves one slot in eight to the recompute that
+    // the reverse pass runs beside it; the two-step cotangent kernel, which
+    // runs alone, fills the round.
+    g->adj_rows = adjoint_rows(nr, nth, (int64_t)cus * 7, kStripCols);
     g->adj_chunks = (nth + g->adj_rows - 1) / g->adj_rows;
+    g->adj2_rows = adjoint_rows(nr, nth, (int64_t)cus * 8, kStripCols2);
+    g->adj2_chunks = (nth + g->adj2_rows - 1) / g->adj2_rows;
     g->adj_strips = ((int)p->nr + kStripCols - 1) / kStripCols;
     g->ext_r.assign(p->extract_rstar, p->extract_rstar + p->n_extract);
     g->ext_t.assign(p->extract_theta, p->extract_theta + p->n_extract);
@@ -637,8 +644,8 @@ int teuk_set_adjoint_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per
         return fail(TEUK_E_INVALID_ARG, "rows_per_tile=%d outside [1, ntheta]", rows_per_tile);
     if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
         return fail(TEUK_E_INVALID_ARG, "waves_per_block=%d not in {1, 2, 4}", waves_per_block);
-    g->adj_rows = rows_per_tile;
-    g->adj_chunks = (int)((g->p.ntheta + rows_per_tile - 1) / rows_per_tile);
+    g->adj_rows = g->adj2_rows = rows_per_tile;
+    g->adj_chunks = g->adj2_chunks = (int)((g->p.ntheta + rows_per_tile - 1) / rows_per_tile);
     g->adj_wpb = waves_per_block;
     return TEUK_OK;
 }
@@ -774,6 +781,8 @@ int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi
         // cotangents only: two adjoint steps (k, then k-1) per pass
         AdjArgs a2 = a;
         a2.k.n_strips = (nr + kStripCols2 - 1) / kStripCols2;
+        a2.k.rows = g->adj2_rows;
+        a2.k.n_chunks = g->adj2_chunks;
         for (; k >= 1; k -= 2) {
             a2.nu_in = lam(c);
             a2.lam_out = lam(1 - c);

@@ -242,7 +242,7 @@ def _default_rows(nr, nth, cus):
 
 
 def _default_adjoint_rows(nr, nth, cus):
-    chunks = cus * 8 // -(-nr // 62)
+    chunks = cus * 7 // -(-nr // 62)
     if chunks < 1:
         return min(nth, 16)
     return min(-(-nth // chunks), 16, nth)
@@ -263,7 +263,7 @@ def test_default_tile_fills_whole_rounds(gpu, nr, nth):
     assert wpb == (1 if tiles < 4 * cus else 4)
     assert adj == (_default_adjoint_rows(nr, nth, cus), 4)
     if cus == 256:
-        expect = {(25600, 512): (57, 4, 16), (6400, 256): (14, 4, 14), (400, 32): (1, 1, 1)}.get((nr, nth))
+        expect = {(25600, 512): (57, 4, 16), (6400, 256): (14, 4, 16), (400, 32): (1, 1, 1)}.get((nr, nth))
         if expect:
             assert (rows, wpb, adj[0]) == expect
 
