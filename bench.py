@@ -106,9 +106,10 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     return 2 * nbytes / s / 1e9
 
 
-def cpu_baseline(w, target_seconds=10.0):
+def cpu_baseline(w, target_seconds=10.0, single_seconds=3.0):
     """The oracle as it stands, on the same grid, timed over whole steps
-    until at least `target_seconds` have passed."""
+    until at least `target_seconds` have passed on all host threads, then
+    `single_seconds` on one thread."""
     import numpy as np
 
     import oracle
@@ -117,21 +118,32 @@ def cpu_baseline(w, target_seconds=10.0):
     o = oracle.OracleGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"])
     phi, pi = inputs.initial_data(w)
     phi, pi = o.project(phi, pi)
-    t0 = time.perf_counter()
-    phi, pi = o.step(phi, pi, 1)
-    one = time.perf_counter() - t0
-    chunk = max(1, int(1.0 / max(one, 1e-6)))
-    n, el = 0, 0.0
-    t0 = time.perf_counter()
-    while el < target_seconds:
-        phi, pi = o.step(phi, pi, chunk)
-        n += chunk
-        el = time.perf_counter() - t0
-    assert np.isfinite(phi).all()
     pts = w["nr"] * w["ntheta"]
-    return {"value": pts * n / el, "unit": "grid-point updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{n} steps of the full {w['nr']}x{w['ntheta']} grid ({el:.1f} s), after 1 untimed step"}
+
+    def timed(seconds):
+        nonlocal phi, pi
+        t0 = time.perf_counter()
+        phi, pi = o.step(phi, pi, 1)
+        one = time.perf_counter() - t0
+        chunk = max(1, int(1.0 / max(one, 1e-6)))
+        n, el = 0, 0.0
+        t0 = time.perf_counter()
+        while el < seconds:
+            phi, pi = o.step(phi, pi, chunk)
+            n += chunk
+            el = time.perf_counter() - t0
+        assert np.isfinite(phi).all()
+        return pts * n / el, f"{n} steps of the full {w['nr']}x{w['ntheta']} grid ({el:.1f} s), after 1 untimed step"
+
+    threads = oracle.num_threads()
+    value, sample = timed(target_seconds)
+    oracle.set_num_threads(1)
+    try:
+        value1, sample1 = timed(single_seconds)
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": value, "unit": "grid-point updates/s", "cores": threads, "kind": "oracle", "sample": sample,
+            "single_thread": {"value": value1, "cores": 1, "sample": sample1}}
 
 
 def waveform_leg(n_samples=500, sample_every=2):

@@ -58,6 +58,7 @@ def _load():
     lib.orc_step.argtypes = [P, P, P]
     lib.orc_evolve.argtypes = [P, P, P, ctypes.c_int64, I, P, P, P]
     lib.orc_num_threads.restype = I
+    lib.orc_set_num_threads.argtypes = [I]
     for name, argt in _ADJOINT_SIGS.items():
         fn = getattr(lib, name, None)
         if fn is not None:
@@ -89,6 +90,12 @@ def _c128(arr, shape=None):
 
 def num_threads():
     return _load().orc_num_threads()
+
+
+def set_num_threads(n):
+    """Threads of later oracle calls (timing only: the results do not
+    depend on it)."""
+    _load().orc_set_num_threads(int(n))
 
 
 def tortoise_x(a, rstar):

@@ -535,6 +535,18 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads used by later calls (timing only; results do not depend on it:
+   every output point is written by one thread). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Adjoint (conjugate transpose) of the step and its spin derivative          */
 /* ------------------------------------------------------------------------ */
