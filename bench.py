@@ -305,6 +305,8 @@ def main():
                     help="rows,waves_per_block of the step kernel (default: autotune)")
     ap.add_argument("--steps-per-pass", type=int, choices=[1, 2], default=None,
                     help="force one or two steps per kernel pass (default: the library's, two)")
+    ap.add_argument("--adjoint-steps", type=int, default=None,
+                    help="steps of the adjoint leg (default: the workload's 8000; fewer for profiling)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB streaming kernel (for counter calibration)")
     args = ap.parse_args()
@@ -326,7 +328,7 @@ def main():
         print(json.dumps(waveform_leg()), flush=True)
         return
     if args.only == "adjoint":
-        print(json.dumps(adjoint_leg()), flush=True)
+        print(json.dumps(adjoint_leg(n_steps=args.adjoint_steps)), flush=True)
         return
     w = inputs.workload(args.workload)
     g = binding.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"],
