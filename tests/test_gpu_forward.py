@@ -228,6 +228,47 @@ def test_two_step_full_size(gpu, name):
         assert rel_err(g[2], o[2]) <= TOL
 
 
+@pytest.mark.parametrize("name", ["kerr_a0.9_6400x256", "kerr_a0.99_25600x512"])
+def test_full_length_run(gpu, name):
+    """The whole run of a full-size workload (all its steps, from its own
+    initial data) in the default launch configuration: one and two steps per
+    pass agree bit for bit in the final state and the whole extraction
+    series, and the last step equals one oracle step taken from the GPU's
+    own state before it."""
+    import torch
+
+    import oracle
+
+    w = inputs.workload(name)
+    n = w["steps"]
+    phi0, pi0 = inputs.initial_data(w)
+    runs = {}
+    for spp in (2, 1):
+        g = gpu.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"],
+                         extract_rstar=w.get("extract_rstar", []), extract_theta=w.get("extract_theta", []))
+        g.set_steps_per_pass(spp)
+        g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
+        s1 = g.step(n - 1)
+        before = [t.cpu().numpy() for t in g.state()]
+        s2 = g.step(1)
+        after = [t.cpu().numpy() for t in g.state()]
+        series = None if s1 is None else np.concatenate([s1.cpu().numpy(), s2.cpu().numpy()])
+        runs[spp] = (before, after, series)
+        g.close()
+    for k in range(2):
+        assert np.array_equal(runs[1][1][k], runs[2][1][k]), k
+    if runs[2][2] is not None:
+        assert runs[2][2].shape == (n, len(w["extract_rstar"]))
+        assert np.array_equal(runs[1][2], runs[2][2])
+        assert np.isfinite(runs[2][2]).all()
+    before, after = runs[2][0], runs[2][1]
+    assert np.isfinite(after[0]).all() and np.isfinite(after[1]).all()
+    o = oracle.OracleGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"])
+    p, q = o.step(before[0], before[1], 1)
+    assert rel_err(after[0], p) <= TOL
+    assert rel_err(after[1], q) <= TOL
+
+
 def _default_rows(nr, nth, cus):
     """The documented default tile height: fewest rounds k of two wavefronts
     per SIMD whose round-filling tiles have at most 64 rows."""
