@@ -132,3 +132,37 @@ def test_two_step_launches_identical(gpu):
         b.close()
     for k in range(len(mbs)):
         assert np.array_equal(res[0][k][0], res[1][k][0]) and np.array_equal(res[0][k][1], res[1][k][1]), k
+
+
+def test_batch64_full_length(gpu):
+    """The 64-member workload for all its 5000 steps in the default launch:
+    every member equals its single-grid evolution bit for bit, and the last
+    step of three members equals one oracle step taken from the batch's state
+    before it."""
+    mbs = inputs.batch_members()
+    n = mbs[0]["steps"]
+    b = gpu.TeukBatch(mbs)
+    for k, mb in enumerate(mbs):
+        p, q = inputs.initial_data(mb)
+        b.set_initial_data(k, torch.from_numpy(p).cuda(), torch.from_numpy(q).cuda())
+    b.step(n - 1)
+    sampled = (0, 37, 63)
+    before = {k: [t.cpu().numpy() for t in b.state(k)] for k in sampled}
+    b.step(1)
+    for k, mb in enumerate(mbs):
+        g = gpu.TeukGrid(mb["a"], mb["s"], mb["m"], mb["nr"], mb["ntheta"], mb["rstar_min"], mb["rstar_max"],
+                         mb["dt"])
+        p, q = inputs.initial_data(mb)
+        g.set_initial_data(torch.from_numpy(p).cuda(), torch.from_numpy(q).cuda())
+        g.step(n)
+        ref, got = g.state(), b.state(k)
+        assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), k
+        g.close()
+        if k in sampled:
+            o = oracle.OracleGrid(mb["a"], mb["s"], mb["m"], mb["nr"], mb["ntheta"], mb["rstar_min"],
+                                  mb["rstar_max"], mb["dt"])
+            op, oq = o.step(before[k][0], before[k][1], 1)
+            after = [t.cpu().numpy() for t in got]
+            assert np.isfinite(after[0]).all() and np.isfinite(after[1]).all()
+            assert rel_err(after[0], op) <= 1e-11 and rel_err(after[1], oq) <= 1e-11, k
+    b.close()
