@@ -113,7 +113,9 @@ int teuk_extract(teuk_grid* g, int32_t n, const double* h_rstar, const double* h
 int teuk_get_state(teuk_grid* g, void* d_phi, void* d_pi);
 
 /* Synchronous check of the current state: TEUK_OK if every value is finite,
- * TEUK_E_NONFINITE otherwise. */
+ * TEUK_E_NONFINITE otherwise; TEUK_E_HIP if a persistent launch (see
+ * teuk_set_persistent) gave up waiting at a grid barrier since the last
+ * check (the state is then not valid; the flag is cleared). */
 int teuk_check_finite(teuk_grid* g);
 
 /* Steps taken since the last teuk_set_initial_data, and the time step. */
@@ -143,6 +145,20 @@ int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per
  * TEUK_E_INVALID_ARG for other values. */
 int teuk_set_steps_per_pass(teuk_grid* g, int32_t steps_per_pass);
 int teuk_get_steps_per_pass(const teuk_grid* g, int32_t* steps_per_pass);
+
+/* Persistent launch of the step loop (Sec. 3.2's steps repeated, here with
+ * the time loop inside one kernel).  mode 1: with two steps per pass and no
+ * window, a run of at least two passes goes to one cooperative launch whose
+ * wavefronts keep their tiles and meet at a grid-wide barrier between
+ * passes, when every tile fits one round of resident wavefronts (otherwise,
+ * or without cooperative launches, one launch per pass).  mode 0 (default):
+ * one launch per pass, which measures faster on MI355X even on small grids
+ * (the barrier's cache write-back and invalidation cost more than a launch
+ * boundary).  Results are identical either way.  A barrier wait gives up
+ * after about a second (the launch then ends and teuk_check_finite reports
+ * it).  TEUK_E_INVALID_ARG for other modes. */
+int teuk_set_persistent(teuk_grid* g, int32_t mode);
+int teuk_get_persistent(const teuk_grid* g, int32_t* mode);
 
 /* Host-only: the Boyer-Lindquist radius r (M = 1) at tortoise coordinate
  * rstar for spin a (the inverse of r*(r) of Sec. 3.2 as read here: r* = r +

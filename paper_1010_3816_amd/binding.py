@@ -67,6 +67,8 @@ def _load():
         "teuk_get_tile": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "teuk_set_steps_per_pass": (ctypes.c_int, [V, I32]),
         "teuk_get_steps_per_pass": (ctypes.c_int, [V, ctypes.POINTER(I32)]),
+        "teuk_set_persistent": (ctypes.c_int, [V, I32]),
+        "teuk_get_persistent": (ctypes.c_int, [V, ctypes.POINTER(I32)]),
         "teuk_set_adjoint_tile": (ctypes.c_int, [V, I32, I32]),
         "teuk_get_adjoint_tile": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "teuk_suggest_dt": (ctypes.c_int, [P, I64, D, D, ctypes.POINTER(D)]),
@@ -110,7 +112,7 @@ EXPORTED = ("teuk_workspace_bytes", "teuk_init_grid", "teuk_set_coefficients", "
             "teuk_batch_set_initial_data", "teuk_batch_get_state", "teuk_batch_step_n", "teuk_batch_set_launch",
             "teuk_batch_get_launch", "teuk_batch_total_points", "teuk_batch_free",
             "teuk_batch_set_steps_per_pass", "teuk_batch_extract", "teuk_batch_n_extract", "teuk_radius",
-            "teuk_assemble_modes")
+            "teuk_assemble_modes", "teuk_set_persistent", "teuk_get_persistent")
 
 
 def _check(rc):
@@ -220,6 +222,16 @@ def teuk_set_steps_per_pass(h, steps_per_pass):
 def teuk_get_steps_per_pass(h):
     v = ctypes.c_int32()
     _check(_lib.teuk_get_steps_per_pass(h, ctypes.byref(v)))
+    return v.value
+
+
+def teuk_set_persistent(h, mode):
+    return _check(_lib.teuk_set_persistent(h, int(mode)))
+
+
+def teuk_get_persistent(h):
+    v = ctypes.c_int32()
+    _check(_lib.teuk_get_persistent(h, ctypes.byref(v)))
     return v.value
 
 
@@ -391,6 +403,14 @@ class TeukGrid:
 
     def steps_per_pass(self):
         return teuk_get_steps_per_pass(self.handle)
+
+    def set_persistent(self, mode):
+        """0 (default): one launch per pass; 1: one persistent launch for
+        a run of passes whenever the tiles fit one round."""
+        teuk_set_persistent(self.handle, mode)
+
+    def persistent(self):
+        return teuk_get_persistent(self.handle)
 
     def set_adjoint_tile(self, rows_per_tile, waves_per_block):
         teuk_set_adjoint_tile(self.handle, rows_per_tile, waves_per_block)

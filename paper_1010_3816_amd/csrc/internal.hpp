@@ -140,6 +140,27 @@ struct AdjArgs {
 hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s);
 // Two steps in one pass (k.n_strips counted in kStripCols2-column strips).
 hipError_t launch_step2(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s);
+// Several two-step passes in one cooperative launch (grids whose tiles all
+// fit one round of resident wavefronts), separated by a grid-wide barrier.
+struct PersistArgs {
+    double2* u[2];           // pass p reads u[p & 1] and writes u[1 - (p & 1)]
+    const double* rad;
+    const double* ang;
+    const double* uci;
+    const double* uch;
+    const ExtPoint* ext;
+    double2* series;         // the call's series (n_ext per row), or nullptr
+    int64_t k0;              // step count before the first pass (its input is state k0)
+    unsigned* bar;           // barrier counter, zero at launch
+    int* err;                // set to 1 when a barrier wait times out
+    int32_t passes, pad;
+    StepScalars k;           // k.n_strips counted in kStripCols2-column strips
+};
+// Workgroups one cooperative launch of the persistent kernel can hold on
+// the current device (0 if it cannot be launched cooperatively).
+int persist2_capacity(bool kerr, int waves_per_block);
+hipError_t launch_persist2(const PersistArgs& a, bool kerr, int waves_per_block, hipStream_t s);
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 // two = true: two steps per launch (work list of tile_begin2 / n_strips2).
 hipError_t launch_batch(const BatchMember* members, int n_members, int total_tiles, int parity, int n_blocks,
                         int waves_per_block, bool two, hipStream_t s);

@@ -643,6 +643,88 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
                       (lds_t)(rad_s + (threadIdx.x / kWave) * 2 * kNumRad * kWave), A, strip, chunk, lane);
 }
 
+// Polls of the barrier counter before a workgroup gives up (about a
+// second): the launch then ends with the error flag set instead of hanging.
+constexpr int kBarrierSpins = 1 << 21;
+
+// Grid-wide barrier number `target / gridDim.x` of a cooperative launch
+// (all workgroups resident).  Every wavefront first releases its stores at
+// agent scope (they reach memory past its XCD's L2), the workgroup counts
+// itself in, waits until all have, and acquires (its XCD's caches drop
+// stale lines).  Returns false when this or another workgroup timed out.
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int* err, int* leave) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(bar, 1u);
+        int ok = 1;
+        for (int spins = 0; __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++spins) {
+            if (spins >= kBarrierSpins || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (!ok) atomicOr(err, 1);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *leave = !ok;
+    }
+    __syncthreads();
+    return !*leave;
+}
+
+// `passes` two-step passes in one cooperative launch: each wavefront keeps
+// its tile (of the two-step kernel's tiling) from pass to pass, and a grid
+// barrier separates the passes.  For small grids, where a pass is a few
+// microseconds of latency and the boundary between two launches costs as
+// much.  Same sweep, same arithmetic: the states equal the two-step
+// kernel's bit for bit.
+// The launch arguments, read afresh from the kernel-argument segment at each
+// use: the pointer is passed through an empty asm statement, so the compiler
+// cannot keep earlier loads live across a pass (the sweep alone fills the
+// registers).
+typedef const __attribute__((address_space(4))) PersistArgs* cpersist_t;
+__device__ __forceinline__ const PersistArgs& persist_args() {
+    cpersist_t p = (cpersist_t)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return *(const PersistArgs*)p;
+}
+
+template <bool KERR>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4)))
+    lw_persist2_kernel(PersistArgs) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wpb = blockDim.x / kWave;
+    const int wave = threadIdx.x / kWave;
+    extern __shared__ double rad_s[];
+    __shared__ int leave;
+    for (int p = 0;; ++p) {
+        {
+            const PersistArgs& P = persist_args();
+            const int tile = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + wave);
+            const int strip = tile % P.k.n_strips;
+            const int chunk = tile / P.k.n_strips;
+            if (chunk < P.k.n_chunks) {  // the others only take part in the barriers
+                const int ne = P.k.n_ext;
+                const int64_t k = P.k0 + 2 * (int64_t)p;
+                double2* s_in = (P.series && k > 0) ? P.series + (k - 1) * ne : nullptr;
+                double2* s_mid = P.series ? P.series + k * ne : nullptr;
+                sweep_tile2<KERR>((gin_t)P.u[p & 1], (gout_t)P.u[1 - (p & 1)], (ctab_t)P.rad, (ctab_t)P.ang,
+                                  (ctab_t)P.uci, (ctab_t)P.uch, (cext_t)P.ext, s_in, s_mid, nullptr,
+                                  (lds_t)(rad_s + wave * 2 * kNumRad * kWave), P.k, strip, chunk, lane);
+            }
+        }
+        const PersistArgs& P = persist_args();
+        if (p + 1 >= P.passes) return;
+        if (!grid_barrier(P.bar, (unsigned)(p + 1) * gridDim.x, P.err, &leave)) return;
+    }
+}
+
+__global__ void zero_ints_kernel(int* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 template <bool KERR>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_WAVES_PER_SIMD, 8)))
     lw_step_kernel(const double2* __restrict__ u_in, double2* __restrict__ u_out, const double* __restrict__ rad,
@@ -848,6 +930,34 @@ hipError_t launch_step2(const StepArgs& a, bool kerr, int waves_per_block, hipSt
     auto kern = kerr ? lw_step2_kernel<true> : lw_step2_kernel<false>;
     hipLaunchKernelGGL(kern, grid, block, kerr ? waves_per_block * kRadSliceBytes : 0, s, a.u_in, a.u_out, a.rad, a.ang,
                        a.uci, a.uch, a.ext, a.series, a.series_mid, a.win, a.k);
+    return hipGetLastError();
+}
+
+int persist2_capacity(bool kerr, int waves_per_block) {
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const void* kern = kerr ? reinterpret_cast<const void*>(lw_persist2_kernel<true>)
+                            : reinterpret_cast<const void*>(lw_persist2_kernel<false>);
+    const size_t lds = kerr ? waves_per_block * kRadSliceBytes : 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave * waves_per_block, lds) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+hipError_t launch_persist2(const PersistArgs& a, bool kerr, int waves_per_block, hipStream_t s) {
+    const int nb = (a.k.n_strips * a.k.n_chunks + waves_per_block - 1) / waves_per_block;
+    const void* kern = kerr ? reinterpret_cast<const void*>(lw_persist2_kernel<true>)
+                            : reinterpret_cast<const void*>(lw_persist2_kernel<false>);
+    PersistArgs arg = a;
+    void* params[] = {&arg};
+    return hipLaunchCooperativeKernel(kern, dim3(nb), dim3(kWave * waves_per_block), params,
+                                      kerr ? waves_per_block * kRadSliceBytes : 0, s);
+}
+
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(zero_ints_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

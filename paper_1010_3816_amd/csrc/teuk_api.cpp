@@ -167,6 +167,8 @@ struct teuk_grid {
     bool fused_ext = true;
     int steps_per_pass = 2;  // 2: pairs of steps in one pass (temporal blocking)
     bool fused_ext2 = true;  // extraction fusable with the two-step strips
+    int persist_mode = 0;    // teuk_set_persistent: 1 = persistent launch whenever the tiles fit
+    int persist_cap = -1;    // workgroups a cooperative persistent launch can hold (-1: not yet queried)
     bool coef_set = false;
     // adjoint (teuk_enable_adjoint)
     char* aws = nullptr;      // adjoint workspace
@@ -415,6 +417,7 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
     if (e != hipSuccess) return bail(fail(TEUK_E_HIP, "hipGetDevice: %s", hipGetErrorString(e)));
     hipStream_t s = g->stream;
     e = hipMemsetAsync(g->ws, 0, L.off_rad, s);  // both state buffers
+    if (e == hipSuccess) e = hipMemsetAsync(g->ws + L.off_flag, 0, kAlign, s);  // status flags
     if (e == hipSuccess && !rad.empty())
         e = hipMemcpyAsync(g->ws + L.off_rad, rad.data(), rad.size() * sizeof(double), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -496,13 +499,43 @@ int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window) {
     // state); otherwise a separate pass samples each new state.
     const bool fused = g->fused_ext;
     int64_t sampled = 0;
+    // On request, runs of two-step passes go to one persistent launch
+    // (cooperative, grid barrier between passes) instead of one launch each.
+    int* flags = g->at<int>(g->L.off_flag);  // [0] non-finite, [1] barrier time-out, [2] barrier counter
+    bool persist = false;
+    if (two && !win && n >= 4 && g->persist_mode == 1) {
+        const int64_t blocks = ((int64_t)a2.k.n_strips * a2.k.n_chunks + wpb2 - 1) / wpb2;
+        if (g->persist_cap < 0) g->persist_cap = persist2_capacity(kerr, wpb2);
+        persist = blocks <= g->persist_cap;
+    }
     auto extract_state = [&](const double2* u, int64_t j) -> int {
         HIP_TRY(launch_extract(u, g->L.pitch, ext, ne, series + (j - 1) * ne, g->stream));
         sampled = j;
         return TEUK_OK;
     };
     for (int64_t k = 0; k < n;) {
-        if (two && k + 2 <= n && !(win && k == 0)) {
+        if (persist && k + 4 <= n) {
+            PersistArgs pa{};
+            pa.u[0] = in;
+            pa.u[1] = g->u(1 - cur);
+            pa.rad = a2.rad;
+            pa.ang = a2.ang;
+            pa.uci = a2.uci;
+            pa.uch = a2.uch;
+            pa.ext = a2.ext;
+            pa.series = series;
+            pa.k0 = k;
+            pa.bar = reinterpret_cast<unsigned*>(flags + 2);
+            pa.err = flags + 1;
+            pa.passes = (int)std::min<int64_t>((n - k) / 2, 1 << 30);
+            pa.k = a2.k;
+            HIP_TRY(launch_zero_ints(flags + 2, 1, g->stream));
+            HIP_TRY(launch_persist2(pa, kerr, wpb2, g->stream));
+            if (pa.passes & 1) advance(g->u(1 - cur));
+            k += 2 * (int64_t)pa.passes;
+            g->steps += 2 * (int64_t)pa.passes;
+            if (series) sampled = k - 1;
+        } else if (two && k + 2 <= n && !(win && k == 0)) {
             double2* out = next_buffer(k + 2);
             a2.u_in = in;
             a2.u_out = out;
@@ -594,10 +627,15 @@ int teuk_check_finite(teuk_grid* g) {
     int* flag = g->at<int>(g->L.off_flag);
     HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), g->stream));
     HIP_TRY(launch_nonfinite(g->u(g->cur), (int)g->p.nr, (int)g->p.ntheta, g->L.pitch, flag, g->stream));
-    int h = 0;
-    HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, g->stream));
+    int h[2] = {0, 0};  // non-finite flag, barrier time-out flag of the persistent launches
+    HIP_TRY(hipMemcpyAsync(h, flag, sizeof(h), hipMemcpyDeviceToHost, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
-    if (h) return fail(TEUK_E_NONFINITE, "state holds a non-finite value after %lld steps", (long long)g->steps);
+    if (h[1]) {
+        HIP_TRY(hipMemsetAsync(flag + 1, 0, sizeof(int), g->stream));
+        HIP_TRY(hipStreamSynchronize(g->stream));
+        return fail(TEUK_E_HIP, "a persistent launch timed out at a grid barrier: the state is not valid");
+    }
+    if (h[0]) return fail(TEUK_E_NONFINITE, "state holds a non-finite value after %lld steps", (long long)g->steps);
     return TEUK_OK;
 }
 
@@ -613,6 +651,7 @@ int teuk_set_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per_block) 
         return fail(TEUK_E_INVALID_ARG, "waves_per_block=%d not in {1, 2, 4, 8}", waves_per_block);
     g->rows = rows_per_tile;
     g->wpb = waves_per_block;
+    g->persist_cap = -1;  // depends on the workgroup size
     update_fusion(g);
     return TEUK_OK;
 }
@@ -622,6 +661,19 @@ int teuk_set_steps_per_pass(teuk_grid* g, int32_t steps_per_pass) {
     if (steps_per_pass != 1 && steps_per_pass != 2)
         return fail(TEUK_E_INVALID_ARG, "steps_per_pass=%d not in {1, 2}", steps_per_pass);
     g->steps_per_pass = steps_per_pass;
+    return TEUK_OK;
+}
+
+int teuk_set_persistent(teuk_grid* g, int32_t mode) {
+    if (int rc = check_grid(g)) return rc;
+    if (mode != 0 && mode != 1) return fail(TEUK_E_INVALID_ARG, "mode=%d not in {0, 1}", mode);
+    g->persist_mode = mode;
+    return TEUK_OK;
+}
+
+int teuk_get_persistent(const teuk_grid* g, int32_t* mode) {
+    if (int rc = check_grid(g)) return rc;
+    if (mode) *mode = g->persist_mode;
     return TEUK_OK;
 }
 
