@@ -151,10 +151,12 @@ int teuk_get_steps_per_pass(const teuk_grid* g, int32_t* steps_per_pass);
  * window, a run of at least two passes goes to one cooperative launch whose
  * wavefronts keep their tiles and meet at a grid-wide barrier between
  * passes, when every tile fits one round of resident wavefronts (otherwise,
- * or without cooperative launches, one launch per pass).  mode 0 (default):
- * one launch per pass, which measures faster on MI355X even on small grids
- * (the barrier's cache write-back and invalidation cost more than a launch
- * boundary).  Results are identical either way.  A barrier wait gives up
+ * or without cooperative launches, one launch per pass).  The state is
+ * then read and written with agent-scope coherent accesses, so the barrier
+ * needs no cache maintenance.  mode 0 (default): one launch per pass, which
+ * measures faster on MI355X even on small grids (a barrier on one counter
+ * shared by all workgroups costs more than a launch boundary).  Results are
+ * identical either way.  A barrier wait gives up
  * after about a second (the launch then ends and teuk_check_finite reports
  * it).  TEUK_E_INVALID_ARG for other modes. */
 int teuk_set_persistent(teuk_grid* g, int32_t mode);

@@ -290,7 +290,7 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
 // step n-1) and the intermediate state (sample of step n).
 typedef __attribute__((address_space(3))) double* lds_t;
 
-template <bool KERR>
+template <bool KERR, bool COH = false>
 __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __restrict__ u_out, ctab_t rad,
                                             ctab_t ang, ctab_t uci, ctab_t uch, cext_t ext,
                                             double2* __restrict__ series_in, double2* __restrict__ series_mid,
@@ -452,8 +452,20 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
 
     auto load_row = [&](int t, cd& p, cd& q) {
         const size_t o = (size_t)min(max(t, 0), lastA) * P + ci;
-        p = ld(u_in, o);
-        q = ld(u_in, o + A.plane);
+        if constexpr (COH) {
+            p = ld_coherent(u_in, o);
+            q = ld_coherent(u_in, o + A.plane);
+        } else {
+            p = ld(u_in, o);
+            q = ld(u_in, o + A.plane);
+        }
+    };
+    // the new state (COH: written through to memory, see ld_coherent)
+    auto put = [&](size_t o, cd v) {
+        if constexpr (COH)
+            st_coherent(u_out, o, v);
+        else
+            st(u_out, o, v);
     };
 
     // ---- prologue: step A completes rows j0-1 (if j0 > 0) and j0; step B
@@ -579,8 +591,8 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
         out_row(bc, kic, b_hbp_m, bn.ubp, bn.hbp, wp, wq);
         if (store_ok) {
             const size_t o = (size_t)(r - 1) * P + col;
-            st(u_out, o, wp);
-            st(u_out, o + A.plane, wq);
+            put(o, wp);
+            put(o + A.plane, wq);
         }
         b_hbp_m = bc.hbp;
     };
@@ -590,8 +602,8 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
         out_row(bc, kic, b_hbp_m, cscale(sg, bc.ubp), cscale(sg, bc.hbp), wp, wq);
         if (store_ok) {
             const size_t o = (size_t)(nth - 1) * P + col;
-            st(u_out, o, wp);
-            st(u_out, o + A.plane, wq);
+            put(o, wp);
+            put(o + A.plane, wq);
         }
     };
 
@@ -647,13 +659,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
 // second): the launch then ends with the error flag set instead of hanging.
 constexpr int kBarrierSpins = 1 << 21;
 
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima).
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 // Grid-wide barrier number `target / gridDim.x` of a cooperative launch
-// (all workgroups resident).  Every wavefront first releases its stores at
-// agent scope (they reach memory past its XCD's L2), the workgroup counts
-// itself in, waits until all have, and acquires (its XCD's caches drop
-// stale lines).  Returns false when this or another workgroup timed out.
+// (all workgroups resident).  The state is written and read with
+// agent-scope coherent accesses (ld_coherent, st_coherent), so a wavefront
+// only waits until its stores are complete; the workgroup then counts itself
+// in and waits until all have.  No L2 write-back or invalidation is needed,
+// and the cached coefficient tables stay in the L2.  Returns false when this
+// or another workgroup timed out.
 __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int* err, int* leave) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
     if (threadIdx.x == 0) {
         atomicAdd(bar, 1u);
@@ -666,7 +683,6 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int
             __builtin_amdgcn_s_sleep(2);
         }
         if (!ok) atomicOr(err, 1);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *leave = !ok;
     }
     __syncthreads();
@@ -709,7 +725,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
                 const int64_t k = P.k0 + 2 * (int64_t)p;
                 double2* s_in = (P.series && k > 0) ? P.series + (k - 1) * ne : nullptr;
                 double2* s_mid = P.series ? P.series + k * ne : nullptr;
-                sweep_tile2<KERR>((gin_t)P.u[p & 1], (gout_t)P.u[1 - (p & 1)], (ctab_t)P.rad, (ctab_t)P.ang,
+                sweep_tile2<KERR, true>((gin_t)P.u[p & 1], (gout_t)P.u[1 - (p & 1)], (ctab_t)P.rad, (ctab_t)P.ang,
                                   (ctab_t)P.uci, (ctab_t)P.uch, (cext_t)P.ext, s_in, s_mid, nullptr,
                                   (lds_t)(rad_s + wave * 2 * kNumRad * kWave), P.k, strip, chunk, lane);
             }
