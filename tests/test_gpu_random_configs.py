@@ -7,7 +7,8 @@ combinations the hand-written cases do not (ragged strips and chunks of every
 size, pole rows inside and at the edges of tiles, extraction points anywhere).
 
 Forward: one and two steps per pass bit-identical; state and series within
-1e-11 normwise of the oracle.  Adjoint: the spin path's cotangents within
+1e-11 normwise of the oracle; the persistent step loop bit-identical to one
+launch per pass over a longer run.  Adjoint: the spin path's cotangents within
 1e-11 of the oracle's transposed steps and dL/da within 1e-10; the
 cotangent-only paths (one and two steps per pass) bit-identical to the spin
 path's cotangents.  Batch: random member sets and persistent launch shapes
@@ -37,6 +38,7 @@ def _draw(seed, n_max, ext_min):
     ne = int(rng.integers(ext_min, 4))
     c["ext"] = tuple((float(rng.uniform(-30.0, 60.0)), float(rng.uniform(0, math.pi))) for _ in range(ne))
     c["gser"] = rng.standard_normal((c["n"], max(ne, 1))) + 1j * rng.standard_normal((c["n"], max(ne, 1)))
+    c["persistent_n"] = int(rng.integers(4, 24))  # drawn last: the earlier draws are unchanged
     return c
 
 
@@ -54,6 +56,14 @@ def test_random_forward(gpu, case):
     assert rel_err(two[0], o[0]) <= TOL and rel_err(two[1], o[1]) <= TOL, c
     if c["ext"]:
         assert rel_err(two[2], o[2]) <= TOL, c
+    # the persistent step loop (one cooperative launch for the run) against
+    # one launch per pass, over a longer run
+    m = c["persistent_n"]
+    per = run_gpu(gpu, w, phi0, pi0, m, tile=(c["rows"], c["wpb"]), steps_per_pass=2, persistent=1)
+    ref = run_gpu(gpu, w, phi0, pi0, m, tile=(c["rows"], c["wpb"]), steps_per_pass=2, persistent=0)
+    for k in range(3):
+        if ref[k] is not None:
+            assert np.array_equal(per[k], ref[k]), (c, k)
 
 
 @pytest.mark.parametrize("case", range(16))
