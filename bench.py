@@ -361,6 +361,17 @@ def main():
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     assert g.check_finite(), "state became non-finite"
+    # run-to-run spread: five more windows of steps/5 (outside the timed region)
+    n_rep = max(2, (args.steps // 5) // 2 * 2)
+    reps = []
+    for _ in range(5):
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        run(n_rep)
+        a1.record(stream)
+        torch.cuda.synchronize()
+        reps.append(w["nr"] * w["ntheta"] * n_rep / (a0.elapsed_time(a1) * 1e-3))
+    assert g.check_finite(), "state became non-finite"
 
     pts = w["nr"] * w["ntheta"]
     ms_step = ms / args.steps
@@ -421,6 +432,7 @@ def main():
                    "n_extract": g.n_extract, "steps_per_pass": spp, "tile_rows": rows, "waves_per_block": wpb},
         "roofline": roof,
         "wall_s_timed_region": wall,
+        "repeats": {"windows": 5, "steps_each": n_rep, "median": sorted(reps)[2], "min": min(reps), "max": max(reps)},
     }
     g.close()
     if not args.no_extras:
