@@ -46,6 +46,7 @@ extern "C" {
 #define TEUK_E_NONFINITE (-3)   /* the state holds a NaN or an infinity      */
 #define TEUK_E_WORKSPACE (-4)   /* workspace too small or misaligned         */
 #define TEUK_E_STATE (-5)       /* call not valid in the grid's current state */
+#define TEUK_E_UNSTABLE_DT (-6) /* strict mode: dt would let the run blow up  */
 
 #define TEUK_COEF_KERR 0 /* coefficients of Eq. (1) for (a, s, m)           */
 #define TEUK_COEF_USER 1 /* caller-supplied coefficient tables              */
@@ -66,12 +67,27 @@ typedef struct teuk_params {
     int64_t nr;                  /* radial points, 3 <= nr <= 2^24                */
     int64_t ntheta;              /* angular rows, 2 <= ntheta <= 2^20             */
     double rstar_min, rstar_max; /* r* range, rstar_min < rstar_max               */
-    double dt;                   /* time step, > 0 (see teuk_suggest_dt)          */
+    double dt;                   /* time step; <= 0: the policy step (below)      */
     int32_t coef_mode;           /* TEUK_COEF_KERR or TEUK_COEF_USER              */
     int32_t n_extract;           /* number of extraction points, 0..4096          */
     const double* extract_rstar; /* h_, n_extract entries, in [rstar_min, rstar_max] */
     const double* extract_theta; /* h_, n_extract entries, in [0, pi]             */
+    int64_t stable_steps;        /* horizon of the time-step policy and check     */
 } teuk_params;
+/* The time step (KERR mode; the explicit scheme's fastest angular mode grows
+ * by |g|^2 = 1 + (w dt)^4/4 per step, see teuk_suggest_dt):
+ *  - dt <= 0 selects the policy step teuk_suggest_dt(p, N, 10, 0.5): half the
+ *    r* spacing, or less so that the fastest angular mode grows at most 10x
+ *    over N = stable_steps steps (10,000 if stable_steps <= 0).  The grid's
+ *    step is then teuk_get_dt.  It depends on a; gradients with respect to a
+ *    treat the step as fixed.
+ *  - dt > 0 with stable_steps > 0 (strict mode): TEUK_E_UNSTABLE_DT if dt is
+ *    above teuk_suggest_dt(p, stable_steps, 10, 1.0), i.e. the fastest
+ *    angular mode would grow more than 10x over stable_steps steps or the r*
+ *    Courant number would exceed 1.  The check comes before any other use of
+ *    the arguments.
+ *  - dt > 0 with stable_steps <= 0: used as given.
+ * USER mode needs dt > 0 and ignores stable_steps. */
 
 /* Bytes of device workspace a grid with these parameters needs (0 and an
  * error message if the parameters are invalid).  The workspace must be

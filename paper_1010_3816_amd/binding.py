@@ -22,13 +22,14 @@ TEUK_E_HIP = -2
 TEUK_E_NONFINITE = -3
 TEUK_E_WORKSPACE = -4
 TEUK_E_STATE = -5
+TEUK_E_UNSTABLE_DT = -6
 TEUK_COEF_KERR = 0
 TEUK_COEF_USER = 1
 TEUK_NCOEF = 9
 TEUK_ADJ_PROJECT_INITIAL = 1
 
 _ERRNAMES = {-1: "TEUK_E_INVALID_ARG", -2: "TEUK_E_HIP", -3: "TEUK_E_NONFINITE",
-             -4: "TEUK_E_WORKSPACE", -5: "TEUK_E_STATE"}
+             -4: "TEUK_E_WORKSPACE", -5: "TEUK_E_STATE", -6: "TEUK_E_UNSTABLE_DT"}
 
 
 class TeukError(RuntimeError):
@@ -43,7 +44,8 @@ class teuk_params(ctypes.Structure):
                 ("rstar_min", ctypes.c_double), ("rstar_max", ctypes.c_double),
                 ("dt", ctypes.c_double), ("coef_mode", ctypes.c_int32), ("n_extract", ctypes.c_int32),
                 ("extract_rstar", ctypes.POINTER(ctypes.c_double)),
-                ("extract_theta", ctypes.POINTER(ctypes.c_double))]
+                ("extract_theta", ctypes.POINTER(ctypes.c_double)),
+                ("stable_steps", ctypes.c_int64)]
 
 
 def _load():
@@ -130,13 +132,13 @@ def teuk_last_error():
 
 
 def make_params(a, s, m, nr, ntheta, rstar_min, rstar_max, dt, coef_mode=TEUK_COEF_KERR,
-                extract_rstar=(), extract_theta=()):
+                extract_rstar=(), extract_theta=(), stable_steps=0):
     er = np.ascontiguousarray(extract_rstar, dtype=np.float64).ravel()
     et = np.ascontiguousarray(extract_theta, dtype=np.float64).ravel()
     if er.shape != et.shape:
         raise ValueError("extraction coordinate arrays differ in length")
     p = teuk_params(float(a), int(s), int(m), int(nr), int(ntheta), float(rstar_min), float(rstar_max),
-                    float(dt), int(coef_mode), int(er.size), None, None)
+                    float(dt), int(coef_mode), int(er.size), None, None, int(stable_steps))
     if er.size:
         p.extract_rstar = er.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         p.extract_theta = et.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
@@ -293,14 +295,14 @@ class TeukGrid:
     Field tensors are torch.complex128 of shape (ntheta, nr) on the device."""
 
     def __init__(self, a, s, m, nr, ntheta, rstar_min, rstar_max, dt, coef_mode=TEUK_COEF_KERR,
-                 extract_rstar=(), extract_theta=(), device=None, stream=None):
+                 extract_rstar=(), extract_theta=(), device=None, stream=None, stable_steps=0):
         import torch
 
         self.torch = torch
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.params = make_params(a, s, m, nr, ntheta, rstar_min, rstar_max, dt, coef_mode,
-                                  extract_rstar, extract_theta)
+                                  extract_rstar, extract_theta, stable_steps)
         self.nr, self.ntheta = int(nr), int(ntheta)
         self.n_extract = self.params.n_extract
         nbytes = teuk_workspace_bytes(self.params)
@@ -447,7 +449,8 @@ class TeukBatch:
         keep = []
         for k, m in enumerate(members):
             p = make_params(m["a"], m["s"], m["m"], m["nr"], m["ntheta"], m["rstar_min"], m["rstar_max"], m["dt"],
-                            extract_rstar=m.get("extract_rstar", ()), extract_theta=m.get("extract_theta", ()))
+                            extract_rstar=m.get("extract_rstar", ()), extract_theta=m.get("extract_theta", ()),
+                            stable_steps=m.get("stable_steps", 0))
             keep.append(p._keep)  # the extraction coordinate arrays the copied structs point to
             arr[k] = p
         self._arr, self._keep = arr, keep

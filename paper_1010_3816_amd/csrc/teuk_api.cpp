@@ -66,7 +66,9 @@ int validate(const teuk_params* p) {
         return fail(TEUK_E_INVALID_ARG, "ntheta=%lld outside [2, 2^20]", (long long)p->ntheta);
     if (!std::isfinite(p->rstar_min) || !std::isfinite(p->rstar_max) || !(p->rstar_min < p->rstar_max))
         return fail(TEUK_E_INVALID_ARG, "need finite rstar_min < rstar_max");
-    if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(TEUK_E_INVALID_ARG, "dt=%g must be > 0", p->dt);
+    if (!std::isfinite(p->dt)) return fail(TEUK_E_INVALID_ARG, "dt=%g is not finite", p->dt);
+    if (!(p->dt > 0.0) && p->coef_mode == TEUK_COEF_USER)
+        return fail(TEUK_E_INVALID_ARG, "dt=%g: USER mode needs dt > 0", p->dt);
     if (p->coef_mode != TEUK_COEF_KERR && p->coef_mode != TEUK_COEF_USER)
         return fail(TEUK_E_INVALID_ARG, "coef_mode=%d unknown", p->coef_mode);
     if (p->n_extract < 0 || p->n_extract > kMaxExtract)
@@ -337,9 +339,37 @@ int teuk_suggest_dt(const teuk_params* p, int64_t n_steps, double growth, double
     return TEUK_OK;
 }
 
+namespace {
+
+// The grid's time step: the policy step for dt <= 0, the strict-mode check
+// for dt > 0 with a horizon (see teuk_params in teuk.h).
+constexpr int64_t kPolicySteps = 10000;
+constexpr double kPolicyGrowth = 10.0;
+
+int resolve_dt(const teuk_params* p, double* dt) {
+    *dt = p->dt;
+    if (p->coef_mode != TEUK_COEF_KERR) return TEUK_OK;
+    const int64_t n = p->stable_steps > 0 ? p->stable_steps : kPolicySteps;
+    if (!(p->dt > 0.0)) return teuk_suggest_dt(p, n, kPolicyGrowth, 0.5, dt);
+    if (p->stable_steps > 0) {
+        double bound = 0.0;
+        if (int rc = teuk_suggest_dt(p, n, kPolicyGrowth, 1.0, &bound)) return rc;
+        if (p->dt > bound)
+            return fail(TEUK_E_UNSTABLE_DT,
+                        "dt=%g exceeds %g: the fastest angular mode would grow more than %gx over %lld steps "
+                        "(or the r* Courant number exceed 1)",
+                        p->dt, bound, kPolicyGrowth, (long long)n);
+    }
+    return TEUK_OK;
+}
+
+}  // namespace
+
 int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, size_t workspace_bytes,
                    teuk_grid** out) {
     if (int rc = validate(p)) return rc;
+    double dt = 0.0;
+    if (int rc = resolve_dt(p, &dt)) return rc;
     if (!out) return fail(TEUK_E_INVALID_ARG, "out is NULL");
     if (!d_workspace) return fail(TEUK_E_INVALID_ARG, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign)
@@ -377,6 +407,7 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
 
     teuk_grid* g = new teuk_grid();
     g->p = *p;
+    g->p.dt = dt;
     g->L = L;
     g->stream = reinterpret_cast<hipStream_t>(hip_stream);
     g->ws = reinterpret_cast<char*>(d_workspace);

@@ -338,3 +338,32 @@ def test_full_size_tile_independence(gpu):
             p, q = g.state()
             assert torch.equal(p, ref[0]) and torch.equal(q, ref[1]), (r, wpb)
     g.close()
+
+
+def test_policy_time_step(gpu):
+    """dt <= 0 takes the policy step (teuk_suggest_dt with a growth bound of
+    10 over stable_steps steps, 10,000 by default, Courant 0.5), reported by
+    teuk_get_dt and used by the steps (parity with the oracle at that dt);
+    strict mode accepts a dt below its bound."""
+    import torch
+
+    from paper_1010_3816_amd import binding
+
+    w = small_case(0.7, -2, 2, 150, 20)
+    geo = (w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"])
+    for horizon, n_pol in ((0, 10000), (200, 200)):
+        g = gpu.TeukGrid(*geo, 0.0, extract_rstar=w["extract_rstar"], extract_theta=w["extract_theta"],
+                         stable_steps=horizon)
+        dt = g.dt
+        assert dt == binding.suggest_dt(*geo, n_pol, 10.0, 0.5)
+        phi0, pi0 = inputs.random_state(w["nr"], w["ntheta"], seed=21)
+        g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
+        ser = g.step(9).cpu().numpy()
+        got = [t.cpu().numpy() for t in g.state()]
+        g.close()
+        o = run_oracle(dict(w, dt=dt), phi0, pi0, 9)
+        assert rel_err(got[0], o[0]) <= TOL and rel_err(got[1], o[1]) <= TOL and rel_err(ser, o[2]) <= TOL
+    ok = 0.99 * binding.suggest_dt(*geo, 500, 10.0, 1.0)
+    g = gpu.TeukGrid(*geo, ok, stable_steps=500)
+    assert g.dt == ok
+    g.close()
