@@ -534,10 +534,11 @@ int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window) {
     // (cooperative, grid barrier between passes) instead of one launch each.
     int* flags = g->at<int>(g->L.off_flag);  // [0] non-finite, [1] barrier time-out, [2] barrier counter
     bool persist = false;
+    int64_t persist_blocks = 1;
     if (two && !win && n >= 4 && g->persist_mode == 1) {
-        const int64_t blocks = ((int64_t)a2.k.n_strips * a2.k.n_chunks + wpb2 - 1) / wpb2;
+        persist_blocks = ((int64_t)a2.k.n_strips * a2.k.n_chunks + wpb2 - 1) / wpb2;
         if (g->persist_cap < 0) g->persist_cap = persist2_capacity(kerr, wpb2);
-        persist = blocks <= g->persist_cap;
+        persist = persist_blocks <= g->persist_cap;
     }
     auto extract_state = [&](const double2* u, int64_t j) -> int {
         HIP_TRY(launch_extract(u, g->L.pitch, ext, ne, series + (j - 1) * ne, g->stream));
@@ -558,7 +559,8 @@ int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window) {
             pa.k0 = k;
             pa.bar = reinterpret_cast<unsigned*>(flags + 2);
             pa.err = flags + 1;
-            pa.passes = (int)std::min<int64_t>((n - k) / 2, 1 << 30);
+            // the barrier counter reaches passes x blocks: kept below 2^31
+            pa.passes = (int)std::min<int64_t>((n - k) / 2, ((int64_t)1 << 31) / persist_blocks - 1);
             pa.k = a2.k;
             HIP_TRY(launch_zero_ints(flags + 2, 1, g->stream));
             HIP_TRY(launch_persist2(pa, kerr, wpb2, g->stream));
