@@ -689,12 +689,6 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int
     return !*leave;
 }
 
-// `passes` two-step passes in one cooperative launch: each wavefront keeps
-// its tile (of the two-step kernel's tiling) from pass to pass, and a grid
-// barrier separates the passes.  For small grids, where a pass is a few
-// microseconds of latency and the boundary between two launches costs as
-// much.  Same sweep, same arithmetic: the states equal the two-step
-// kernel's bit for bit.
 // The launch arguments, read afresh from the kernel-argument segment at each
 // use: the pointer is passed through an empty asm statement, so the compiler
 // cannot keep earlier loads live across a pass (the sweep alone fills the
@@ -706,6 +700,13 @@ __device__ __forceinline__ const PersistArgs& persist_args() {
     return *(const PersistArgs*)p;
 }
 
+// `passes` two-step passes in one cooperative launch: each wavefront keeps
+// its tile (of the two-step kernel's tiling) from pass to pass, and a grid
+// barrier separates the passes.  Same sweep, same arithmetic (the state
+// accessed coherently): the states equal the two-step kernel's bit for bit.
+// Not used by default: one launch per pass measures faster, even on small
+// grids, whose passes are bound by the latency of one short tile per
+// wavefront rather than by the launches.
 template <bool KERR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4)))
     lw_persist2_kernel(PersistArgs) {
@@ -725,9 +726,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
                 const int64_t k = P.k0 + 2 * (int64_t)p;
                 double2* s_in = (P.series && k > 0) ? P.series + (k - 1) * ne : nullptr;
                 double2* s_mid = P.series ? P.series + k * ne : nullptr;
-                sweep_tile2<KERR, true>((gin_t)P.u[p & 1], (gout_t)P.u[1 - (p & 1)], (ctab_t)P.rad, (ctab_t)P.ang,
-                                  (ctab_t)P.uci, (ctab_t)P.uch, (cext_t)P.ext, s_in, s_mid, nullptr,
-                                  (lds_t)(rad_s + wave * 2 * kNumRad * kWave), P.k, strip, chunk, lane);
+                sweep_tile2<KERR, true>((gin_t)P.u[p & 1], (gout_t)P.u[1 - (p & 1)], (ctab_t)P.rad,
+                                        (ctab_t)P.ang, (ctab_t)P.uci, (ctab_t)P.uch, (cext_t)P.ext, s_in, s_mid,
+                                        nullptr, (lds_t)(rad_s + wave * 2 * kNumRad * kWave), P.k, strip, chunk,
+                                        lane);
             }
         }
         const PersistArgs& P = persist_args();
