@@ -836,24 +836,29 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
 // The state is stored as two planes in one buffer: u[f * nth * pitch + j *
 // pitch + i], f = 0 for Phi and 1 for Pi.
 
+// The row-wise kernels below take rows blockIdx.y, blockIdx.y + gridDim.y,
+// ...: a launch's y dimension is capped (kMaxGridY) while ntheta may reach 2^20.
+constexpr int kMaxGridY = 65535;
+
 __global__ void import_kernel(const double2* __restrict__ src, double2* __restrict__ u, int f, int nr, int nth,
                               int pitch) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= pitch || j >= nth) return;
-    double2 v;
-    v.x = 0.0;
-    v.y = 0.0;
-    if (i > 0 && i < nr - 1) v = src[(size_t)j * nr + i];
-    u[(size_t)f * nth * pitch + (size_t)j * pitch + i] = v;
+    if (i >= pitch) return;
+    for (int j = blockIdx.y; j < nth; j += gridDim.y) {
+        double2 v;
+        v.x = 0.0;
+        v.y = 0.0;
+        if (i > 0 && i < nr - 1) v = src[(size_t)j * nr + i];
+        u[(size_t)f * nth * pitch + (size_t)j * pitch + i] = v;
+    }
 }
 
 __global__ void export_kernel(const double2* __restrict__ u, double2* __restrict__ dst, int f, int nr, int nth,
                               int pitch) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= nr || j >= nth) return;
-    dst[(size_t)j * nr + i] = u[(size_t)f * nth * pitch + (size_t)j * pitch + i];
+    if (i >= nr) return;
+    for (int j = blockIdx.y; j < nth; j += gridDim.y)
+        dst[(size_t)j * nr + i] = u[(size_t)f * nth * pitch + (size_t)j * pitch + i];
 }
 
 // Bilinear sample of Phi at one extraction point (rows rowa, rowb with the
@@ -916,19 +921,20 @@ __global__ void batch_extract_kernel(const BatchExtPoint* __restrict__ pts, int 
 
 __global__ void nonfinite_kernel(const double2* __restrict__ u, int nr, int nth, int pitch, int* flag) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= nr || j >= nth) return;
-    const size_t o = (size_t)j * pitch + i;
-    const double2 a = u[o], b = u[o + (size_t)nth * pitch];
-    if (!isfinite(a.x) || !isfinite(a.y) || !isfinite(b.x) || !isfinite(b.y)) *flag = 1;
+    if (i >= nr) return;
+    for (int j = blockIdx.y; j < nth; j += gridDim.y) {
+        const size_t o = (size_t)j * pitch + i;
+        const double2 a = u[o], b = u[o + (size_t)nth * pitch];
+        if (!isfinite(a.x) || !isfinite(a.y) || !isfinite(b.x) || !isfinite(b.y)) *flag = 1;
+    }
 }
 
 __global__ void pitch_copy_kernel(const double* __restrict__ src, double* __restrict__ dst, int rows, int cols,
                                   int pitch) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= pitch || j >= rows) return;
-    dst[(size_t)j * pitch + i] = (i < cols) ? src[(size_t)j * cols + i] : 0.0;
+    if (i >= pitch) return;
+    for (int j = blockIdx.y; j < rows; j += gridDim.y)
+        dst[(size_t)j * pitch + i] = (i < cols) ? src[(size_t)j * cols + i] : 0.0;
 }
 
 }  // namespace
@@ -993,13 +999,13 @@ hipError_t launch_batch(const BatchMember* members, int n_members, int total_til
 }
 
 hipError_t launch_import(const double2* src, double2* u, int f, int nr, int nth, int pitch, hipStream_t s) {
-    const dim3 block(256), grid((pitch + 255) / 256, nth);
+    const dim3 block(256), grid((pitch + 255) / 256, std::min(nth, kMaxGridY));
     hipLaunchKernelGGL(import_kernel, grid, block, 0, s, src, u, f, nr, nth, pitch);
     return hipGetLastError();
 }
 
 hipError_t launch_export(const double2* u, double2* dst, int f, int nr, int nth, int pitch, hipStream_t s) {
-    const dim3 block(256), grid((nr + 255) / 256, nth);
+    const dim3 block(256), grid((nr + 255) / 256, std::min(nth, kMaxGridY));
     hipLaunchKernelGGL(export_kernel, grid, block, 0, s, u, dst, f, nr, nth, pitch);
     return hipGetLastError();
 }
@@ -1028,13 +1034,13 @@ hipError_t launch_assemble(const AssembleArgs& a, int64_t n_samples, const doubl
 }
 
 hipError_t launch_nonfinite(const double2* u, int nr, int nth, int pitch, int* flag, hipStream_t s) {
-    const dim3 block(256), grid((nr + 255) / 256, nth);
+    const dim3 block(256), grid((nr + 255) / 256, std::min(nth, kMaxGridY));
     hipLaunchKernelGGL(nonfinite_kernel, grid, block, 0, s, u, nr, nth, pitch, flag);
     return hipGetLastError();
 }
 
 hipError_t launch_pitch_copy(const double* src, double* dst, int rows, int cols, int pitch, hipStream_t s) {
-    const dim3 block(256), grid((pitch + 255) / 256, rows);
+    const dim3 block(256), grid((pitch + 255) / 256, std::min(rows, kMaxGridY));
     hipLaunchKernelGGL(pitch_copy_kernel, grid, block, 0, s, src, dst, rows, cols, pitch);
     return hipGetLastError();
 }

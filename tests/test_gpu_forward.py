@@ -367,3 +367,47 @@ def test_policy_time_step(gpu):
     g = gpu.TeukGrid(*geo, ok, stable_steps=500)
     assert g.dt == ok
     g.close()
+
+
+def test_maximum_sizes(gpu):
+    """The largest grids the ABI accepts, one in each direction, a few steps
+    with one and two steps per pass (bit-identical).  Nr = 2^24 x Ntheta = 2
+    (both rows are pole rows): the oracle on windows of 2000 columns at both
+    radial ends and in the middle, compared where the window's own edges
+    (zeroed like radial boundaries) cannot have reached in n steps (one
+    column per step).  Nr = 3 x Ntheta = 2^20: the whole grid."""
+    import torch
+
+    import oracle
+
+    n = 3
+    for nr, nth in ((1 << 24, 2), (3, 1 << 20)):
+        w = small_case(0.6, -2, 1, nr, nth, rmin=-50.0, rmax=150.0, ext=())
+        phi0, pi0 = inputs.random_state(nr, nth, seed=31)
+        g = gpu.TeukGrid(w["a"], w["s"], w["m"], nr, nth, w["rstar_min"], w["rstar_max"], w["dt"])
+        states = []
+        for spp in (2, 1):
+            g.set_steps_per_pass(spp)
+            g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
+            g.step(n)
+            states.append([t.cpu().numpy() for t in g.state()])
+        assert g.check_finite()
+        g.close()
+        for k in range(2):
+            assert np.array_equal(states[0][k], states[1][k]), (nr, nth, k)
+        got = states[0]
+        if nr == 3:
+            o = run_oracle(w, phi0, pi0, n)
+            assert rel_err(got[0], o[0]) <= TOL and rel_err(got[1], o[1]) <= TOL
+            continue
+        dr = (w["rstar_max"] - w["rstar_min"]) / (nr - 1)
+        for i0 in (0, nr // 2 - 1000, nr - 2000):
+            i1 = i0 + 1999
+            o = oracle.OracleGrid(w["a"], w["s"], w["m"], 2000, nth, w["rstar_min"] + i0 * dr,
+                                  w["rstar_min"] + i1 * dr, w["dt"])
+            p, q = o.project(phi0[:, i0:i1 + 1], pi0[:, i0:i1 + 1])
+            p, q, _ = o.evolve(p, q, n, [], [])
+            lo = 0 if i0 == 0 else n + 1  # columns the window's artificial edges cannot have reached
+            hi = 2000 if i1 == nr - 1 else 2000 - n - 1
+            for a, b in ((got[0][:, i0:i1 + 1], p), (got[1][:, i0:i1 + 1], q)):
+                assert rel_err(a[:, lo:hi], b[:, lo:hi]) <= TOL, (i0, rel_err(a[:, lo:hi], b[:, lo:hi]))
