@@ -125,6 +125,18 @@ int teuk_step_n(teuk_grid* g, int64_t n, void* d_series);
  * centres the angular ghost rows are used) into d_out (complex128 [n]). */
 int teuk_extract(teuk_grid* g, int32_t n, const double* h_rstar, const double* h_theta, void* d_out);
 
+/* Allocation-free variant of teuk_extract, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): same arguments, same results bit for
+ * bit.  The point records are staged in a static device array of the
+ * library (192 KiB per device, held until the process ends) instead of the
+ * grid's workspace; the call allocates nothing.  n is at most 4096
+ * (TEUK_E_INVALID_ARG above).  The array is shared by every call on one
+ * device: the call synchronises the grid's stream before it returns, so
+ * calls from one thread follow each other, but calls that overlap on one
+ * device (other threads or streams) race for it. */
+int teuk_extract_noalloc(teuk_grid* g, int32_t n, const double* h_rstar, const double* h_theta, void* d_out);
+
 /* Copy the current state into caller arrays (complex128 [ntheta][nr]). */
 int teuk_get_state(teuk_grid* g, void* d_phi, void* d_pi);
 

@@ -61,6 +61,7 @@ def _load():
         "teuk_set_initial_data": (ctypes.c_int, [V, V, V]),
         "teuk_step_n": (ctypes.c_int, [V, I64, V]),
         "teuk_extract": (ctypes.c_int, [V, I32, V, V, V]),
+        "teuk_extract_noalloc": (ctypes.c_int, [V, I32, V, V, V]),
         "teuk_get_state": (ctypes.c_int, [V, V, V]),
         "teuk_check_finite": (ctypes.c_int, [V]),
         "teuk_steps_taken": (I64, [V]),
@@ -114,7 +115,7 @@ EXPORTED = ("teuk_workspace_bytes", "teuk_init_grid", "teuk_set_coefficients", "
             "teuk_batch_set_initial_data", "teuk_batch_get_state", "teuk_batch_step_n", "teuk_batch_set_launch",
             "teuk_batch_get_launch", "teuk_batch_total_points", "teuk_batch_free",
             "teuk_batch_set_steps_per_pass", "teuk_batch_extract", "teuk_batch_n_extract", "teuk_radius",
-            "teuk_assemble_modes", "teuk_set_persistent", "teuk_get_persistent")
+            "teuk_assemble_modes", "teuk_set_persistent", "teuk_get_persistent", "teuk_extract_noalloc")
 
 
 def _check(rc):
@@ -185,6 +186,15 @@ def teuk_extract(h, rstar, theta, out):
         raise ValueError("coordinate arrays differ in length")
     return _check(_lib.teuk_extract(h, int(r.size), r.ctypes.data_as(ctypes.c_void_p),
                                     t.ctypes.data_as(ctypes.c_void_p), _dptr(out)))
+
+
+def teuk_extract_noalloc(h, rstar, theta, out):
+    r = np.ascontiguousarray(rstar, dtype=np.float64).ravel()
+    t = np.ascontiguousarray(theta, dtype=np.float64).ravel()
+    if r.shape != t.shape:
+        raise ValueError("coordinate arrays differ in length")
+    return _check(_lib.teuk_extract_noalloc(h, int(r.size), r.ctypes.data_as(ctypes.c_void_p),
+                                            t.ctypes.data_as(ctypes.c_void_p), _dptr(out)))
 
 
 def teuk_get_state(h, phi, pi):

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -148,6 +149,40 @@ ExtPoint ext_point(double rstar, double theta, double rmin, double dr, int nr, i
         E.wb = wt;
     }
     return E;
+}
+
+// Device scratch of teuk_extract_noalloc: the point records of one call,
+// staged here instead of in a grid's workspace, so that the call needs no
+// device memory from the caller beyond its output.  Every device the
+// library runs on holds its own copy until the process ends.  Host code
+// reaches a device's copy only through the address hipGetSymbolAddress
+// returns for it with that device current (scratch_address), never through
+// the array's name, which on the host is only a stand-in for the symbol.
+constexpr int kNoAllocMaxPoints = kMaxExtract;
+constexpr size_t kScratchBytes = (size_t)kNoAllocMaxPoints * sizeof(ExtPoint);  // 192 KiB
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_addr;  // by device ordinal; nullptr until resolved
+
+// Resolve the scratch address of `device`, which must be the current device
+// (called once per device, from teuk_init_grid).
+int resolve_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0) return fail(TEUK_E_HIP, "invalid device %d", device);
+    if ((size_t)device < g_scratch_addr.size() && g_scratch_addr[device]) return TEUK_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(TEUK_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    if ((size_t)device >= g_scratch_addr.size()) g_scratch_addr.resize(device + 1, nullptr);
+    g_scratch_addr[device] = p;
+    return TEUK_OK;
+}
+
+void* scratch_address(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return (device >= 0 && (size_t)device < g_scratch_addr.size()) ? g_scratch_addr[device] : nullptr;
 }
 
 }  // namespace
@@ -446,6 +481,7 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
     };
     hipError_t e = hipGetDevice(&g->device);
     if (e != hipSuccess) return bail(fail(TEUK_E_HIP, "hipGetDevice: %s", hipGetErrorString(e)));
+    if (int rc = resolve_scratch(g->device)) return bail(rc);
     hipStream_t s = g->stream;
     e = hipMemsetAsync(g->ws, 0, L.off_rad, s);  // both state buffers
     if (e == hipSuccess) e = hipMemsetAsync(g->ws + L.off_flag, 0, kAlign, s);  // status flags
@@ -622,25 +658,64 @@ int teuk_step_n_store(teuk_grid* g, int64_t n, void* d_series, void* d_window) {
     return step_n_impl(g, n, d_series, d_window);
 }
 
-int teuk_extract(teuk_grid* g, int32_t n, const double* h_rstar, const double* h_theta, void* d_out) {
+namespace {
+
+// Host check of the extraction requests of teuk_extract / teuk_extract_noalloc.
+int check_extract_args(const teuk_grid* g, int32_t n, int32_t max_n, const double* h_rstar, const double* h_theta,
+                       const void* d_out) {
     if (int rc = check_grid(g)) return rc;
-    if (n < 0 || n > kMaxExtract) return fail(TEUK_E_INVALID_ARG, "n=%d outside [0, %d]", n, kMaxExtract);
+    if (n < 0 || n > max_n) return fail(TEUK_E_INVALID_ARG, "n=%d outside [0, %d]", n, max_n);
     if (n == 0) return TEUK_OK;
     if (!h_rstar || !h_theta || !d_out) return fail(TEUK_E_INVALID_ARG, "NULL pointer");
-    const int nr = (int)g->p.nr, nth = (int)g->p.ntheta;
-    std::vector<ExtPoint> pts(n);
     for (int e = 0; e < n; ++e) {
         if (!(h_rstar[e] >= g->p.rstar_min && h_rstar[e] <= g->p.rstar_max))
             return fail(TEUK_E_INVALID_ARG, "r*=%g outside the grid", h_rstar[e]);
         if (!(h_theta[e] >= 0.0 && h_theta[e] <= M_PI))
             return fail(TEUK_E_INVALID_ARG, "theta=%g outside [0, pi]", h_theta[e]);
-        pts[e] = ext_point(h_rstar[e], h_theta[e], g->p.rstar_min, g->dr, nr, nth, g->sigma);
     }
+    return TEUK_OK;
+}
+
+ExtPoint grid_ext_point(const teuk_grid* g, double rstar, double theta) {
+    return ext_point(rstar, theta, g->p.rstar_min, g->dr, (int)g->p.nr, (int)g->p.ntheta, g->sigma);
+}
+
+}  // namespace
+
+int teuk_extract(teuk_grid* g, int32_t n, const double* h_rstar, const double* h_theta, void* d_out) {
+    if (int rc = check_extract_args(g, n, kMaxExtract, h_rstar, h_theta, d_out)) return rc;
+    if (n == 0) return TEUK_OK;
+    std::vector<ExtPoint> pts(n);
+    for (int e = 0; e < n; ++e) pts[e] = grid_ext_point(g, h_rstar[e], h_theta[e]);
     if (int rc = set_device(g)) return rc;
     ExtPoint* dp = g->at<ExtPoint>(g->L.off_ext2);
     HIP_TRY(hipMemcpyAsync(dp, pts.data(), n * sizeof(ExtPoint), hipMemcpyHostToDevice, g->stream));
     HIP_TRY(launch_extract(g->u(g->cur), g->L.pitch, dp, n, static_cast<double2*>(d_out), g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));  // `pts` is released on return
+    return TEUK_OK;
+}
+
+int teuk_extract_noalloc(teuk_grid* g, int32_t n, const double* h_rstar, const double* h_theta, void* d_out) {
+    if (int rc = check_extract_args(g, n, kNoAllocMaxPoints, h_rstar, h_theta, d_out)) return rc;
+    if (n == 0) return TEUK_OK;
+    if (int rc = set_device(g)) return rc;
+    char* d_scratch = static_cast<char*>(scratch_address(g->device));
+    if (!d_scratch) return fail(TEUK_E_STATE, "no scratch address for device %d", g->device);
+    // The point records are built in stack chunks and staged into this
+    // device's scratch; a chunk buffer is reused only once its copy is done.
+    constexpr int kChunk = 256;
+    ExtPoint buf[kChunk];
+    for (int e0 = 0; e0 < n; e0 += kChunk) {
+        const int c = std::min(kChunk, n - e0);
+        for (int k = 0; k < c; ++k) buf[k] = grid_ext_point(g, h_rstar[e0 + k], h_theta[e0 + k]);
+        HIP_TRY(hipMemcpyAsync(d_scratch + (size_t)e0 * sizeof(ExtPoint), buf, c * sizeof(ExtPoint),
+                               hipMemcpyHostToDevice, g->stream));
+        HIP_TRY(hipStreamSynchronize(g->stream));
+    }
+    HIP_TRY(launch_extract(g->u(g->cur), g->L.pitch, reinterpret_cast<const ExtPoint*>(d_scratch), n,
+                           static_cast<double2*>(d_out), g->stream));
+    // the scratch is free for the next call once this one returns
+    HIP_TRY(hipStreamSynchronize(g->stream));
     return TEUK_OK;
 }
 
