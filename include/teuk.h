@@ -230,6 +230,8 @@ int teuk_step_n_store(teuk_grid* g, int64_t n, void* d_series, void* d_window);
 #define TEUK_ADJ_PROJECT_INITIAL 1 /* zero the radial boundary columns of the result,
                                       giving the gradient w.r.t. the arguments of
                                       teuk_set_initial_data */
+#define TEUK_ADJ_TANGENT_WINDOW 2  /* the window holds the step tangents T_k written by
+                                      teuk_step_n_tangent instead of the states u^k */
 
 /* Device bytes for teuk_enable_adjoint (256-byte aligned, caller-allocated). */
 size_t teuk_adjoint_workspace_bytes(teuk_grid* g);
@@ -251,14 +253,32 @@ int teuk_enable_adjoint(teuk_grid* g, void* d_adj_workspace, size_t bytes);
 int teuk_set_adjoint_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per_block);
 int teuk_get_adjoint_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per_block);
 
+/* Copy window slot k (a state of teuk_step_n_store, or a tangent of
+ * teuk_step_n_tangent) into caller arrays (complex128 [ntheta][nr]).  The
+ * caller keeps k below the window's slot count; the call cannot check it. */
+int teuk_get_window_slot(teuk_grid* g, const void* d_window, int64_t k, void* d_phi, void* d_pi);
+
+/* As teuk_step_n without extraction (n >= 0 steps), and also leave in window
+ * slot k (k = 0..n-1) the derivative of step k with respect to the spin at
+ * fixed input, T_k = (dA/da) u^{s0+k}, where s0 is the step count before the
+ * call: dA/da differentiates the coefficients of Eq. (1) (and r(r*; a)) in
+ * both stages of Eqs. (lw1)-(lw2), T_k is zero on the radial boundary
+ * columns.  Then dL/da = sum_k Re <lambda^{s0+k+1}, T_k>, which
+ * teuk_adjoint_step_n forms with TEUK_ADJ_TANGENT_WINDOW from cotangents it
+ * computes anyway, so the reverse sweep needs no forward state.  The states
+ * u^{s0+k} equal those of teuk_step_n bit for bit.  Needs teuk_enable_adjoint
+ * (TEUK_E_STATE otherwise); d_window as for teuk_step_n_store. */
+int teuk_step_n_tangent(teuk_grid* g, int64_t n, void* d_window);
+
 /* Reverse of one segment of n forward steps whose input states are in
- * d_window (as written by teuk_step_n_store; slot k = state s0+k).
+ * d_window (as written by teuk_step_n_store; slot k = state s0+k), or whose
+ * step tangents are (teuk_step_n_tangent, flag TEUK_ADJ_TANGENT_WINDOW).
  *   d_lam_phi, d_lam_pi  (complex128 [ntheta][nr], in/out): in, the
  *       cotangent of state s0+n from everything after the segment; out, the
  *       cotangent of state s0 including the segment's samples.
  *   d_dL_dseries (complex128 [n][n_extract], or NULL = 0): gradient of L
  *       with respect to the series written by the forward call.
- *   flags: 0 or TEUK_ADJ_PROJECT_INITIAL.
+ *   flags: TEUK_ADJ_PROJECT_INITIAL, TEUK_ADJ_TANGENT_WINDOW or both (or 0).
  *   h_dL_da_accum: += this segment's part of dL/da (the call synchronises).
  *       NULL: dL/da is not computed; the cotangents of the linear step do
  *       not depend on the forward states, so d_window may then be NULL (it

@@ -4,10 +4,14 @@ data (Phi0, Pi0) and of the spin a, with checkpoint/recompute.
 Forward: the state is copied to a checkpoint every K steps while the
 library advances the grid (teuk_step_n).  Backward, for each segment from the
 last to the first: restore its checkpoint, recompute its K steps while the
-library keeps their input states in a window (teuk_step_n_store), and run the
+library keeps, for each step k, its derivative with respect to the spin at
+fixed input, T_k = (dA/da) u^k, in a window (teuk_step_n_tangent), and run the
 library's adjoint over the segment (teuk_adjoint_step_n), which carries the
-cotangent of the state and accumulates dL/da.  Device memory: the
-checkpoints (one state per K steps) plus one window of K states.
+cotangent of the state and accumulates dL/da = sum_k Re <lambda^{k+1}, T_k>
+from the cotangents it computes anyway.  Device memory: the checkpoints (one
+state per K steps) plus one window of K states.  tangent=False keeps the
+input states in the window instead (teuk_step_n_store) and lets the adjoint
+recompute the spin term from them: the same gradient, by another route.
 
 With overlap (the default) the recompute of the next segment runs on a
 second grid and stream while the adjoint of the current one runs, into the
@@ -36,18 +40,26 @@ def _make_grid(a, cfg, stream=None):
                             extract_theta=cfg.get("extract_theta", ()), stream=stream)
 
 
-def _reverse_sequential(grid, ckpts, segs, K, gseries, lam_phi, lam_pi):
+def _recompute(grid, m, window, tangent):
+    if tangent:
+        grid.step_tangent(m, window)
+    else:
+        grid.step_store(m, window, series=False)
+
+
+def _reverse_sequential(grid, ckpts, segs, K, gseries, lam_phi, lam_pi, tangent):
     window = grid.new_window(K)
     dlda = 0.0
     for idx in range(len(segs) - 1, -1, -1):
         k, m = segs[idx]
         grid.set_initial_data(*ckpts[idx])
-        grid.step_store(m, window, series=False)
-        dlda += grid.adjoint(m, lam_phi, lam_pi, gseries[k:k + m], window, project_initial=(idx == 0))
+        _recompute(grid, m, window, tangent)
+        dlda += grid.adjoint(m, lam_phi, lam_pi, gseries[k:k + m], window, project_initial=(idx == 0),
+                             tangent=tangent)
     return dlda
 
 
-def _reverse_overlapped(grid, a, cfg, ckpts, segs, K, gseries, lam_phi, lam_pi):
+def _reverse_overlapped(grid, a, cfg, ckpts, segs, K, gseries, lam_phi, lam_pi, tangent):
     """Segments in reverse; the recompute of segment idx-1 (second grid, own
     stream, window (idx-1) % 2) is queued before the adjoint of segment idx
     (this grid's stream, window idx % 2), which waits for its own recompute
@@ -63,7 +75,7 @@ def _reverse_overlapped(grid, a, cfg, ckpts, segs, K, gseries, lam_phi, lam_pi):
     def recompute(idx):
         m = segs[idx][1]
         rec.set_initial_data(*ckpts[idx])
-        rec.step_store(m, windows[idx % 2], series=False)
+        _recompute(rec, m, windows[idx % 2], tangent)
         done[idx % 2].record(rs)
 
     dlda = 0.0
@@ -74,23 +86,25 @@ def _reverse_overlapped(grid, a, cfg, ckpts, segs, K, gseries, lam_phi, lam_pi):
             recompute(idx - 1)
         grid.stream.wait_event(done[idx % 2])
         k, m = segs[idx]
-        dlda += grid.adjoint(m, lam_phi, lam_pi, gseries[k:k + m], windows[idx % 2], project_initial=(idx == 0))
+        dlda += grid.adjoint(m, lam_phi, lam_pi, gseries[k:k + m], windows[idx % 2], project_initial=(idx == 0),
+                             tangent=tangent)
     rs.synchronize()
     rec.close()
     return dlda
 
 
 class TeukEvolve(torch.autograd.Function):
-    """series = TeukEvolve.apply(phi0, pi0, a, cfg, n_steps, checkpoint_every, overlap)
+    """series = TeukEvolve.apply(phi0, pi0, a, cfg, n_steps, checkpoint_every, overlap, tangent)
 
     phi0, pi0: complex128 (ntheta, nr) on the GPU; a: 0-dim float64 tensor;
     cfg: dict with s, m, nr, ntheta, rstar_min, rstar_max, dt, extract_rstar,
     extract_theta.  Returns the extraction series, complex128 (n_steps, n_extract).
     overlap: run the recompute of the next segment beside the adjoint of the
-    current one (same results)."""
+    current one (same results).  tangent: the recompute stores the step
+    tangents (default) or the states (the same gradient, by another route)."""
 
     @staticmethod
-    def forward(ctx, phi0, pi0, a, cfg, n_steps, checkpoint_every, overlap=True):
+    def forward(ctx, phi0, pi0, a, cfg, n_steps, checkpoint_every, overlap=True, tangent=True):
         n, K = int(n_steps), int(checkpoint_every)
         if n < 1 or K < 1:
             raise ValueError("need n_steps >= 1 and checkpoint_every >= 1")
@@ -109,7 +123,7 @@ class TeukEvolve(torch.autograd.Function):
         else:
             binding.teuk_step_n(grid.handle, n, series)
         ctx.grid, ctx.ckpts, ctx.n, ctx.K, ctx.need_a = grid, ckpts, n, K, need_a
-        ctx.cfg, ctx.overlap, ctx.a_val = cfg, bool(overlap), float(a)
+        ctx.cfg, ctx.overlap, ctx.a_val, ctx.tangent = cfg, bool(overlap), float(a), bool(tangent)
         ctx.a_meta = (a.dtype, a.device, a.shape)
         return series
 
@@ -125,9 +139,9 @@ class TeukEvolve(torch.autograd.Function):
             segs = [(k, min(K, n - k)) for k in range(0, n, K)]
             if ctx.overlap and len(segs) > 1:
                 dlda = _reverse_overlapped(grid, ctx.a_val, ctx.cfg, ctx.ckpts, segs, min(K, n), gseries, lam_phi,
-                                           lam_pi)
+                                           lam_pi, ctx.tangent)
             else:
-                dlda = _reverse_sequential(grid, ctx.ckpts, segs, min(K, n), gseries, lam_phi, lam_pi)
+                dlda = _reverse_sequential(grid, ctx.ckpts, segs, min(K, n), gseries, lam_phi, lam_pi, ctx.tangent)
             dtype, device, shape = ctx.a_meta
             grad_a = torch.full(shape, dlda, dtype=dtype, device=device)
         else:
@@ -135,11 +149,11 @@ class TeukEvolve(torch.autograd.Function):
         ctx.grid = None
         ctx.ckpts = None
         grid.close()
-        return lam_phi, lam_pi, grad_a, None, None, None, None
+        return lam_phi, lam_pi, grad_a, None, None, None, None, None
 
 
-def evolve(phi0, pi0, a, cfg, n_steps, checkpoint_every=100, overlap=True):
+def evolve(phi0, pi0, a, cfg, n_steps, checkpoint_every=100, overlap=True, tangent=True):
     """Extraction series of an n-step evolution, differentiable in phi0, pi0 and a."""
     if not torch.is_tensor(a):
         a = torch.tensor(float(a), dtype=torch.float64, device=phi0.device)
-    return TeukEvolve.apply(phi0, pi0, a, cfg, n_steps, checkpoint_every, overlap)
+    return TeukEvolve.apply(phi0, pi0, a, cfg, n_steps, checkpoint_every, overlap, tangent)

@@ -27,6 +27,7 @@ TEUK_COEF_KERR = 0
 TEUK_COEF_USER = 1
 TEUK_NCOEF = 9
 TEUK_ADJ_PROJECT_INITIAL = 1
+TEUK_ADJ_TANGENT_WINDOW = 2
 
 _ERRNAMES = {-1: "TEUK_E_INVALID_ARG", -2: "TEUK_E_HIP", -3: "TEUK_E_NONFINITE",
              -4: "TEUK_E_WORKSPACE", -5: "TEUK_E_STATE", -6: "TEUK_E_UNSTABLE_DT"}
@@ -79,6 +80,8 @@ def _load():
         "teuk_last_error": (ctypes.c_char_p, []),
         "teuk_window_bytes": (ctypes.c_size_t, [V, I64]),
         "teuk_step_n_store": (ctypes.c_int, [V, I64, V, V]),
+        "teuk_step_n_tangent": (ctypes.c_int, [V, I64, V]),
+        "teuk_get_window_slot": (ctypes.c_int, [V, V, I64, V, V]),
         "teuk_adjoint_workspace_bytes": (ctypes.c_size_t, [V]),
         "teuk_enable_adjoint": (ctypes.c_int, [V, V, ctypes.c_size_t]),
         "teuk_adjoint_step_n": (ctypes.c_int, [V, I64, V, V, V, V, I32, ctypes.POINTER(D)]),
@@ -115,7 +118,8 @@ EXPORTED = ("teuk_workspace_bytes", "teuk_init_grid", "teuk_set_coefficients", "
             "teuk_batch_set_initial_data", "teuk_batch_get_state", "teuk_batch_step_n", "teuk_batch_set_launch",
             "teuk_batch_get_launch", "teuk_batch_total_points", "teuk_batch_free",
             "teuk_batch_set_steps_per_pass", "teuk_batch_extract", "teuk_batch_n_extract", "teuk_radius",
-            "teuk_assemble_modes", "teuk_set_persistent", "teuk_get_persistent", "teuk_extract_noalloc")
+            "teuk_assemble_modes", "teuk_set_persistent", "teuk_get_persistent", "teuk_extract_noalloc",
+            "teuk_step_n_tangent", "teuk_get_window_slot")
 
 
 def _check(rc):
@@ -272,6 +276,14 @@ def teuk_step_n_store(h, n, series, window):
     return _check(_lib.teuk_step_n_store(h, int(n), _dptr(series), _dptr(window)))
 
 
+def teuk_step_n_tangent(h, n, window):
+    return _check(_lib.teuk_step_n_tangent(h, int(n), _dptr(window)))
+
+
+def teuk_get_window_slot(h, window, k, phi, pi):
+    return _check(_lib.teuk_get_window_slot(h, _dptr(window), int(k), _dptr(phi), _dptr(pi)))
+
+
 def teuk_adjoint_workspace_bytes(h):
     nb = _lib.teuk_adjoint_workspace_bytes(h)
     if nb == 0:
@@ -390,15 +402,28 @@ class TeukGrid:
         teuk_step_n_store(self.handle, n, out, window)
         return out
 
-    def adjoint(self, n, lam_phi, lam_pi, dseries, window, project_initial=False, spin=True):
+    def step_tangent(self, n, window):
+        """n steps, leaving T_k = (dA/da) u^k in window slot k (teuk_step_n_tangent)."""
+        self.enable_adjoint()
+        teuk_step_n_tangent(self.handle, n, window)
+
+    def window_slot(self, window, k):
+        """Slot k of a window as (phi, pi) tensors of shape (ntheta, nr)."""
+        phi = self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
+        pi = self.torch.empty_like(phi)
+        teuk_get_window_slot(self.handle, window, k, phi, pi)
+        return phi, pi
+
+    def adjoint(self, n, lam_phi, lam_pi, dseries, window, project_initial=False, spin=True, tangent=False):
         """Reverse of n stored steps; updates (lam_phi, lam_pi) in place, returns the dL/da part
-        (spin=False: cotangents only, window may be None, returns None)."""
+        (spin=False: cotangents only, window may be None, returns None).  tangent: the window
+        holds step tangents (step_tangent) instead of states (step_store)."""
         self.enable_adjoint()
         if dseries is not None:
             dseries = self.torch.as_tensor(dseries, dtype=self.torch.complex128, device=self.device).contiguous()
             if tuple(dseries.shape) != (int(n), self.n_extract):
                 raise ValueError("dseries must have shape (n, n_extract)")
-        flags = TEUK_ADJ_PROJECT_INITIAL if project_initial else 0
+        flags = (TEUK_ADJ_PROJECT_INITIAL if project_initial else 0) | (TEUK_ADJ_TANGENT_WINDOW if tangent else 0)
         return teuk_adjoint_step_n(self.handle, n, lam_phi, lam_pi, dseries, window, flags, spin)
 
     def check_finite(self):

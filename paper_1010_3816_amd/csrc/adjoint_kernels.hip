@@ -150,9 +150,18 @@ struct AdjFwd {
 template <>
 struct AdjFwd<false> {};
 
-template <bool SPIN>
+// Tangent rows of the spin gradient's dot product (DOT kernels only).
+template <bool DOT>
+struct AdjTan {
+    cd tp, tq;            // T_m = (dA/da) u^m at (i, t)
+};
+template <>
+struct AdjTan<false> {};
+
+template <bool SPIN, bool DOT = false>
 struct AdjRow {
     AdjFwd<SPIN> f;       // forward recompute of step m at this row
+    AdjTan<DOT> tan;      // tangent row, for the dot product with nu
     // adjoint
     cd np, nq;            // nu at (i, t), radial boundary columns zeroed
     cd lhq;               // cotangent of the stage-1 Pi value at the half
@@ -165,7 +174,10 @@ struct AdjRow {
 // SPIN = false: the cotangents only.  The step is linear in the state, so
 // they do not need u^m: no state rows are read, nothing of the forward step
 // is recomputed and no spin gradient is accumulated.
-template <bool SPIN>
+// DOT (with SPIN = false): u_in holds T_m = (dA/da) u^m (lw_tangent_kernel)
+// instead of u^m, and the spin gradient's term of this step is the dot
+// product Re <lambda^{m+1}, T_m> over the owned points.
+template <bool SPIN, bool DOT = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
     lw_adjoint_kernel(const double2* __restrict__ nu_in, const double2* __restrict__ u_in,
                       double2* __restrict__ lam_out, const double* __restrict__ rad,
@@ -173,6 +185,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
                       double* __restrict__ dlda_slots, const ExtPoint* __restrict__ ext,
                       const double* __restrict__ gsample, AdjScalars A) {
     constexpr int kRIF = SPIN ? kAdjRowsInFlight : TEUK_ADJ_ROWS_IN_FLIGHT_NOSPIN;
+    static_assert(!(SPIN && DOT), "the stored-tangent dot product replaces the spin recompute");
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -223,8 +236,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
 
     // Arrival of row t: forward stage-1 pieces of u^m and the same-row part
     // of the transposed step applied to nu.
-    auto fresh = [&](int t, cd p, cd q, cd np, cd nq, cd ubp_prev, const Ang& G) -> AdjRow<SPIN> {
-        AdjRow<SPIN> R;
+    auto fresh = [&](int t, cd p, cd q, cd np, cd nq, cd ubp_prev, const Ang& G) -> AdjRow<SPIN, DOT> {
+        AdjRow<SPIN, DOT> R;
+        if constexpr (DOT) {
+            R.tan.tp = p;
+            R.tan.tq = q;
+        }
         Coef ki, kh;
         Sig si, sh;
         coefs(t, G, ki, kh, si, sh);
@@ -275,20 +292,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
         return R;
     };
 
-    // rows of u^m are read only for the spin gradient
+    // rows of u^m (or T_m) are read only for the spin gradient
     auto ldu = [&](size_t o) -> cd {
-        if constexpr (SPIN) return ld(u_in, o);
+        if constexpr (SPIN || DOT) return ld(u_in, o);
         return cd{0.0, 0.0};
     };
 
     // ---- prologue ----------------------------------------------------------
-    AdjRow<SPIN> cur;
+    AdjRow<SPIN, DOT> cur;
     cd ubp_m, hbp_m, below, below_h;
     {
         cd ubp_prev = {0.0, 0.0};
         if (j0 > 0) {
             const size_t o = (size_t)(j0 - 1) * P + ci;
-            const AdjRow<SPIN> rm = fresh(j0 - 1, ldu(o), ldu(o + A.plane), ld(nu_in, o), ld(nu_in, o + A.plane),
+            const AdjRow<SPIN, DOT> rm = fresh(j0 - 1, ldu(o), ldu(o + A.plane), ld(nu_in, o), ld(nu_in, o + A.plane),
                                           ubp_prev, ang_row(j0 - 1));
             if constexpr (SPIN) {
                 ubp_prev = rm.f.ubp;
@@ -322,7 +339,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
 
     // Row t is in cur; row t+1 arrives into nxt (the two alternate roles
     // from row to row, so no row state is copied).
-    auto finish_row = [&](int t, AdjRow<SPIN>& cur, AdjRow<SPIN>& nxt, cd* ru, cd* rn) {
+    auto finish_row = [&](int t, AdjRow<SPIN, DOT>& cur, AdjRow<SPIN, DOT>& nxt, cd* ru, cd* rn) {
         cd ubp_p, hbp_p, above, above_h;
         const Ang g1 = g_next;
         g_next = ang_row(t + 2);
@@ -438,6 +455,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
             if (own) acc += c;
         }
 
+        // spin gradient from the stored tangent: Re <nu, T_m> (T_m is zero on
+        // the radial boundary columns, where nu is masked)
+        if constexpr (DOT) {
+            double c = cur.np.re * cur.tan.tp.re + cur.np.im * cur.tan.tp.im;
+            c = fma(cur.nq.re, cur.tan.tq.re, fma(cur.nq.im, cur.tan.tq.im, c));
+            if (own) acc += c;
+        }
+
         below = cur.up;
         below_h = cur.uph;
         if constexpr (SPIN) {
@@ -447,7 +472,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     };
 
     // rows in pairs (the ring slot of row t+1 is (t - j0) mod kRIF)
-    AdjRow<SPIN> other;
+    AdjRow<SPIN, DOT> other;
     int t0 = j0;
     for (; t0 + 2 <= j1; t0 += 2) {
         finish_row(t0, cur, other, bu[0], bn[0]);
@@ -456,7 +481,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     if (t0 < j1) finish_row(t0, cur, other, bu[0], bn[0]);
 
     // fixed-order reduction over the wavefront, one slot per tile
-    if constexpr (SPIN) {
+    if constexpr (SPIN || DOT) {
         for (int off = kWave / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, kWave);
         if (lane == 0) dlda_slots[(size_t)chunk * A.n_strips + strip] += acc;
     }
@@ -478,10 +503,16 @@ struct AdjCot {
     Ang g;              // angular factors of the row (wavefront-uniform)
 };
 
+// DOT: also the spin gradient's terms of both steps from stored tangents,
+// Re <lambda^{m+2}, T_{m+1}> (tan_a, with the input rows as sweep A
+// completes them) and Re <lambda^{m+1}, T_m> (tan_b, with sweep B's rows),
+// over the owned points, summed per tile into slots.
+template <bool DOT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
     lw_adjoint2_kernel(const double2* __restrict__ nu_in, double2* __restrict__ lam_out, const double* __restrict__ rad, const double* __restrict__ ang,
                        const ExtPoint* __restrict__ ext, const double* __restrict__ gsample_a,
-                       const double* __restrict__ gsample_b, AdjScalars A) {
+                       const double* __restrict__ gsample_b, const double2* __restrict__ tan_a,
+                       const double2* __restrict__ tan_b, double* __restrict__ dlda_slots, AdjScalars A) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -516,14 +547,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
 
     auto ang_row = [&](int t) -> Ang { return load_ang(ang, nth, min(t, nth - 1)); };
     // arrival of a row (as fresh() of lw_adjoint_kernel<false>)
-    auto fresh = [&](int t, cd np, cd nq, const Ang& G) -> AdjCot {
+    // The row's coefficients come with it: sweep B's rows are the rows sweep
+    // A has just completed, whose coefficients A's finish() built (same
+    // expressions, same values), so B takes them instead of rebuilding them.
+    auto fresh_k = [&](cd np, cd nq, const Ang& G, Sig si, Sig sh, const Coef& ki, const Coef& kh) -> AdjCot {
         AdjCot R;
-        const int o = t & A.zero;
-        const Rad Ri = rad_from_lds(rvi, o), Rh = rad_from_lds(rvh, o);
-        R.si = kerr_sigma(Ri, G);
-        R.sh = kerr_sigma(Rh, G);
-        const Coef ki = kerr_coef(Ri, G, R.si);
-        const Coef kh = kerr_coef(Rh, G, R.sh);
+        R.si = si;
+        R.sh = sh;
         R.g = G;
         R.np = masked(np, interior);
         R.nq = masked(nq, interior);
@@ -540,11 +570,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
         R.dnh = cscale(kh.a2s - kh.a1s, tq);
         return R;
     };
+    auto fresh = [&](int t, cd np, cd nq, const Ang& G) -> AdjCot {
+        const int o = t & A.zero;
+        const Rad Ri = rad_from_lds(rvi, o), Rh = rad_from_lds(rvh, o);
+        const Sig si = kerr_sigma(Ri, G), sh = kerr_sigma(Rh, G);
+        return fresh_k(np, nq, G, si, sh, kerr_coef(Ri, G, si), kerr_coef(Rh, G, sh));
+    };
     // completion of row t (as in lw_adjoint_kernel<false>): the new
-    // cotangent, plus E^T g of the output state's sample
+    // cotangent, plus E^T g of the output state's sample; ki, kh receive the
+    // row's coefficients
     auto finish = [&](int t, const AdjCot& cur, cd below, cd below_h, cd above, cd above_h, const double* gsample,
-                      cd& outp, cd& outq) {
-        Coef ki, kh;
+                      cd& outp, cd& outq, Coef& ki, Coef& kh) {
         {
             const int o = t & A.zero;
             ki = kerr_coef(rad_from_lds(rvi, o), cur.g, cur.si);
@@ -588,6 +624,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
         p = ld(nu_in, o);
         q = ld(nu_in, o + A.plane);
     };
+    // a tangent row (DOT), clamped to the grid
+    struct TRow {
+        cd p, q;
+    };
+    auto load_tan = [&](const double2* tan, int t, TRow& r) {
+        if constexpr (DOT) {
+            const size_t o = (size_t)min(max(t, 0), nth - 1) * P + ci;
+            r.p = ld(tan, o);
+            r.q = ld(tan, o + A.plane);
+        }
+    };
+    double acc = 0.0;  // spin-gradient partial sum of this lane (DOT)
+    // Re <cotangent row, tangent row> of an owned row
+    auto dot = [&](const AdjCot& c, const TRow& t) {
+        if constexpr (DOT) {
+            double v = c.np.re * t.p.re + c.np.im * t.p.im;
+            v = fma(c.nq.re, t.q.re, fma(c.nq.im, t.q.im, v));
+            if (own) acc += v;
+        }
+    };
 
     // ---- prologue: A completes rows j0-1 (if j0 > 0) and j0; B takes them
     // as its halo row and its first row -------------------------------------
@@ -622,17 +678,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
                 a_nxt = a_cur;
             }
             cd vp, vq;
-            finish(r, a_cur, a_below, a_below_h, above, above_h, gsample_a, vp, vq);
+            Coef ki, kh;
+            finish(r, a_cur, a_below, a_below_h, above, above_h, gsample_a, vp, vq, ki, kh);
+            if (DOT && r == j0) {  // the one owned row the prologue completes
+                TRow tr;
+                load_tan(tan_a, r, tr);
+                dot(a_cur, tr);
+            }
             a_below = a_cur.up;
             a_below_h = a_cur.uph;
-            const Ang gr = a_cur.g;
+            const AdjCot ar = a_cur;
             a_cur = a_nxt;
             if (r < j0) {  // B's halo row j0-1
-                const AdjCot h = fresh(r, vp, vq, gr);
+                const AdjCot h = fresh_k(vp, vq, ar.g, ar.si, ar.sh, ki, kh);
                 b_below = h.up;
                 b_below_h = h.uph;
             } else {
-                b_cur = fresh(r, vp, vq, gr);
+                b_cur = fresh_k(vp, vq, ar.g, ar.si, ar.sh, ki, kh);
                 if (r == 0) {
                     b_below = cscale(sg, b_cur.dn);
                     b_below_h = cscale(sg, b_cur.dnh);
@@ -646,8 +708,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     cd rp[2], rq[2];
     load_row(j0 + 2, rp[0], rq[0]);
     load_row(j0 + 3, rp[1], rq[1]);
+    // tangent rows (DOT): step_row(r) finds T_{m+1} row r in ta and T_m row
+    // r-1 in tb, and loads the next rows into them once used
+    TRow ta, tb;
+    load_tan(tan_a, j0 + 1, ta);
+    load_tan(tan_b, j0, tb);
     Ang g_next = ang_row(j0 + 2);
-    auto step_row = [&](int r, cd& lp, cd& lq, AdjCot& ac, AdjCot& an, AdjCot& bc, AdjCot& bn) {
+    auto step_row = [&](int r, cd& lp, cd& lq, AdjCot& ac, AdjCot& an, AdjCot& bc, AdjCot& bn, TRow& tar,
+                        TRow& tbr) {
         cd above, above_h;
         const Ang g1 = g_next;
         g_next = ang_row(r + 2);
@@ -662,13 +730,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
         }
         load_row(r + 3, lp, lq);
         cd vp, vq;
-        finish(r, ac, a_below, a_below_h, above, above_h, gsample_a, vp, vq);
+        Coef ki, kh;
+        finish(r, ac, a_below, a_below_h, above, above_h, gsample_a, vp, vq, ki, kh);
+        if (r < j1) dot(ac, tar);  // wavefront-uniform: row j1 is a halo row of sweep A
+        load_tan(tan_a, r + 1, tar);
         a_below = ac.up;
         a_below_h = ac.uph;
 
-        bn = fresh(r, vp, vq, ac.g);
+        bn = fresh_k(vp, vq, ac.g, ac.si, ac.sh, ki, kh);
         cd wp, wq;
-        finish(r - 1, bc, b_below, b_below_h, bn.dn, bn.dnh, gsample_b, wp, wq);
+        finish(r - 1, bc, b_below, b_below_h, bn.dn, bn.dnh, gsample_b, wp, wq, ki, kh);
+        dot(bc, tbr);
+        load_tan(tan_b, r, tbr);
         if (own) {
             const size_t o = (size_t)(r - 1) * P + col;
             st(lam_out, o, wp);
@@ -677,9 +750,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
         b_below = bc.up;
         b_below_h = bc.uph;
     };
-    auto last_row = [&](const AdjCot& bc) {  // the grid's last row: B with the pole ghost row
+    auto last_row = [&](const AdjCot& bc, const TRow& tbr) {  // the grid's last row: B with the pole ghost row
         cd wp, wq;
-        finish(nth - 1, bc, b_below, b_below_h, cscale(sg, bc.up), cscale(sg, bc.uph), gsample_b, wp, wq);
+        Coef ki, kh;
+        finish(nth - 1, bc, b_below, b_below_h, cscale(sg, bc.up), cscale(sg, bc.uph), gsample_b, wp, wq, ki, kh);
+        dot(bc, tbr);
         if (own) {
             const size_t o = (size_t)(nth - 1) * P + col;
             st(lam_out, o, wp);
@@ -689,15 +764,256 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     AdjCot a_oth, b_oth;
     int r0 = j0 + 1;
     for (; r0 + 1 <= aE; r0 += 2) {
-        step_row(r0, rp[0], rq[0], a_cur, a_oth, b_cur, b_oth);
-        step_row(r0 + 1, rp[1], rq[1], a_oth, a_cur, b_oth, b_cur);
+        step_row(r0, rp[0], rq[0], a_cur, a_oth, b_cur, b_oth, ta, tb);
+        step_row(r0 + 1, rp[1], rq[1], a_oth, a_cur, b_oth, b_cur, ta, tb);
     }
     if (r0 <= aE) {
-        step_row(r0, rp[0], rq[0], a_cur, a_oth, b_cur, b_oth);
-        if (j1 == nth) last_row(b_oth);
+        step_row(r0, rp[0], rq[0], a_cur, a_oth, b_cur, b_oth, ta, tb);
+        if (j1 == nth) last_row(b_oth, tb);
     } else if (j1 == nth) {
-        last_row(b_cur);
+        last_row(b_cur, tb);
     }
+
+    // fixed-order reduction over the wavefront, one slot per tile
+    if constexpr (DOT) {
+        for (int off = kWave / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+        if (lane == 0) dlda_slots[(size_t)chunk * A.n_strips + strip] += acc;
+    }
+}
+
+// One Lax-Wendroff step, u^{m+1} = A u^m, that also writes the derivative of
+// the step with respect to the spin at fixed input, T_m = (dA/da) u^m: the
+// spin gradient is then dL/da = sum_m Re <lambda^{m+1}, T_m>, a dot product
+// the reverse sweep forms from the cotangents it computes anyway.  With
+// stage 1 h = ubar - dt/2 [D delta/dr - S(ubar)] at the halves and stage 2
+// u' = u - dt [D dh/dr - S(hbar)],
+//   dh = -dt/2 [D' delta/dr - S'(ubar)]                       (halves)
+//   T  = -dt [D' dh/dr + D d(dh)/dr - S'(hbar) - S(d(h)bar)]   (columns)
+// with D', S' the operators of the a-derivatives of the coefficients (the
+// Phi row of S' vanishes) and T = 0 on the radial boundary columns.  The
+// sweep is that of the one-step forward kernel (64-column strips numbered
+// strip-fastest, theta rows in order, the same expressions, so u^{m+1} equals
+// its result bit for bit); each lane holds the radial factors of its column
+// and half point in registers for the whole tile and their a-derivatives in
+// its own part of the wavefront's LDS slice (written and read by the same
+// lane: no barrier).
+// d/da of kerr_coef from the radial factors V (registers) and their
+// a-derivatives D (as kerr_coef_da).
+__device__ __forceinline__ Coef kerr_coef_da_reg(const Rad& V, const Rad& D, const Ang& G, Sig s, const Coef& c) {
+    const double w = s.inv * fma(-D.a2d, G.sn2, D.rho2);
+    const double hw = 0.5 * w;
+    Coef r;
+    r.b = fma(s.isig, D.rho, -c.b * hw);
+    const double T = fma(-V.rb3, G.sn2, V.rb2);
+    const double dT = fma(-D.rb3, G.sn2, D.rb2);
+    const double Q = fma(-T, s.inv, V.rb1);
+    const double dQ = fma(-s.inv, fma(-T, w, dT), D.rb1);
+    const double bp = s.isig * Q;
+    const double dbp = s.isig * fma(-Q, hw, dQ);
+    r.ctr = fma(s.inv, D.ctr, -c.ctr * w);
+    r.cti = fma(s.inv, fma(D.cti1, G.cs, D.cti0), -c.cti * w);
+    const double b1 = V.b1n * s.inv;
+    const double db1 = fma(s.inv, D.b1n, -b1 * w);
+    r.cre = fma(r.b, bp - c.ctr, c.b * (dbp - r.ctr)) - db1;
+    r.cim = -fma(r.b, c.cti, c.b * r.cti);
+    r.a2s = fma(s.inv, D.dl2, -c.a2s * w);
+    r.a1s = r.a2s * G.cotp;
+    r.v0r = fma(s.inv, fma(D.dl2, G.pd, D.v0r), -c.v0r * w);
+    r.v0i = fma(s.inv, D.v0i, -c.v0i * w);
+    return r;
+}
+
+struct TanRow {
+    cd p, q;      // u^m at (i, t)
+    cd ubp;       // stage-1 average of Phi at the half point i+1/2
+    cd hbp, dhp;  // mean and difference of stage-1 Phi at i-1/2, i+1/2
+    cd x;         // stage-1 Pi at i+1/2 except its row-(t+1) term: h_Pi = x + wp ubp(t+1)
+    double wp;
+    cd tbp, tdp;  // the same mean and difference of the a-derivative of stage-1 Phi
+    cd tx;        // a-derivative of x
+    double twp;   // a-derivative of wp
+    Ang g;        // angular factors of row t (wavefront-uniform)
+};
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+    lw_tangent_kernel(const double2* __restrict__ u_in, double2* __restrict__ u_out, double2* __restrict__ t_out,
+                      const double* __restrict__ rad, const double* __restrict__ rad_da,
+                      const double* __restrict__ ang, AdjScalars A) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wpb = blockDim.x / kWave;
+    const int tile = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x / kWave));
+    const int strip = tile % A.n_strips;
+    const int chunk = tile / A.n_strips;
+    if (chunk >= A.n_chunks) return;  // tiles beyond the last
+    const int nr = A.nr, nth = A.nth, P = A.pitch;
+    const int col = strip * kStripCols - 1 + lane;
+    // Lanes outside the grid read the clamped edge column; their values
+    // reach only the radial boundary columns of both outputs, which are zero.
+    const int ci = min(max(col, 0), nr - 1);
+    const int hi = min(max(col, 0), nr - 2);
+    // radial factors of this lane's column and half point; their
+    // a-derivatives go to the wavefront's LDS slice [integer/half][field][lane]
+    const Rad Vi = load_rad(rad, P, 0, ci), Vh = load_rad(rad, P, 1, hi);
+    extern __shared__ double rad_s[];
+    double* ds = rad_s + (threadIdx.x / kWave) * 2 * kNumRad * kWave + lane;
+#pragma unroll
+    for (int f = 0; f < kNumRad; ++f) {
+        ds[f * kWave] = rad_da[((size_t)f * 2 + 0) * P + ci];
+        ds[(kNumRad + f) * kWave] = rad_da[((size_t)f * 2 + 1) * P + hi];
+    }
+    lds_cptr rdi = (lds_cptr)ds, rdh = (lds_cptr)(ds + kNumRad * kWave);
+
+    const bool store_ok = (lane >= 1) && (lane <= kWave - 2) && (col < nr);
+    const bool boundary = (col == 0) || (col == nr - 1);
+    const int j0 = chunk * A.rows;
+    const int j1 = min(j0 + A.rows, nth);
+    const double sg = (double)A.sigma;
+    const int last = (j1 < nth) ? j1 : nth - 1;  // last row this tile reads
+
+    auto ang_row = [&](int t) -> Ang { return load_ang(ang, nth, min(t, nth - 1)); };
+
+    // Arrival of row t: stage-1 pieces (the forward kernel's expressions)
+    // and their a-derivatives.  A halo row needs only ubp, hbp and tbp.
+    auto fresh = [&](int t, cd p, cd q, cd ubp_prev, const Ang& G) -> TanRow {
+        TanRow R;
+        R.p = p;
+        R.q = q;
+        R.g = G;
+        const Sig sh = kerr_sigma(Vh, G);
+        const Coef kh = kerr_coef(Vh, G, sh);
+        const Coef dkh = kerr_coef_da_reg(Vh, rad_from_lds(rdh, t & A.zero), G, sh, kh);
+        const cd pr = from_right(p), qr = from_right(q);
+        R.ubp = cavg(p, pr);
+        const cd ubq = cavg(q, qr);
+        const cd dp = csub(pr, p);
+        const double tb = A.hdt_dr * kh.b;
+        const cd hp = {fma(-tb, dp.re, fma(A.hdt, ubq.re, R.ubp.re)), fma(-tb, dp.im, fma(A.hdt, ubq.im, R.ubp.im))};
+        const cd hpl = from_left(hp);
+        R.hbp = cavg(hp, hpl);
+        R.dhp = csub(hp, hpl);
+        // d/da h_Phi = -dt/2 db delta_Phi / dr
+        const double ttb = A.hdt_dr * dkh.b;
+        const cd thp = {-ttb * dp.re, -ttb * dp.im};
+        const cd thpl = from_left(thp);
+        R.tbp = cavg(thp, thpl);
+        R.tdp = csub(thp, thpl);
+        const cd dq = csub(qr, q);
+        const cd um = (t == 0) ? cscale(sg, R.ubp) : ubp_prev;
+        const cd dq1 = d_pi(kh, dp, dq);
+        const cd s1 = s_pi(kh, um, R.ubp, cd{0.0, 0.0}, ubq);
+        R.x = {fma(A.hdt, s1.re, fma(-A.hdt_dr, dq1.re, ubq.re)), fma(A.hdt, s1.im, fma(-A.hdt_dr, dq1.im, ubq.im))};
+        R.wp = A.hdt * (kh.a2s + kh.a1s);
+        // d/da h_Pi = -dt/2 [ (dc delta_Phi - db delta_Pi)/dr - S'(ubar) ]
+        const cd tq1 = d_pi(dkh, dp, dq);
+        const cd ts1 = s_pi(dkh, um, R.ubp, cd{0.0, 0.0}, ubq);
+        R.tx = {fma(A.hdt, ts1.re, -A.hdt_dr * tq1.re), fma(A.hdt, ts1.im, -A.hdt_dr * tq1.im)};
+        R.twp = A.hdt * (dkh.a2s + dkh.a1s);
+        return R;
+    };
+
+    // ---- prologue: rows j0-1 (halo or ghost) and j0 ---------------------
+    cd hbp_m, tbp_m;  // hbar_Phi and its a-derivative at row t-1
+    TanRow cur;
+    {
+        cd ubp_prev = {0.0, 0.0};
+        if (j0 > 0) {
+            const size_t o = (size_t)(j0 - 1) * P + ci;
+            const TanRow rm = fresh(j0 - 1, ld(u_in, o), ld(u_in, o + A.plane), ubp_prev, ang_row(j0 - 1));
+            ubp_prev = rm.ubp;
+            hbp_m = rm.hbp;
+            tbp_m = rm.tbp;
+        }
+        const size_t o = (size_t)j0 * P + ci;
+        cur = fresh(j0, ld(u_in, o), ld(u_in, o + A.plane), ubp_prev, ang_row(j0));
+        if (j0 == 0) {
+            hbp_m = cscale(sg, cur.hbp);
+            tbp_m = cscale(sg, cur.tbp);
+        }
+    }
+    Ang g_next = ang_row(j0 + 1);  // angular factors one row ahead
+    cd bp[2], bq[2];               // rows j0+1, j0+2 in flight
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const size_t o = (size_t)min(j0 + 1 + k, last) * P + ci;
+        bp[k] = ld(u_in, o);
+        bq[k] = ld(u_in, o + A.plane);
+    }
+
+    // Row t is in cur; row t+1 arrives into nxt (roles alternate from row to
+    // row, so no row state is copied); rp, rq: ring slot of row t+1, refilled
+    // with row t+3.
+    auto finish_row = [&](int t, TanRow& cur, TanRow& nxt, cd& rp, cd& rq) {
+        cd ubp_p, hbp_p, tbp_p;
+        const Ang g1 = g_next;
+        g_next = ang_row(t + 2);
+        if (t + 1 < nth) {
+            nxt = fresh(t + 1, rp, rq, cur.ubp, g1);
+            ubp_p = nxt.ubp;
+            hbp_p = nxt.hbp;
+            tbp_p = nxt.tbp;
+        } else {  // pole ghost row
+            ubp_p = cscale(sg, cur.ubp);
+            hbp_p = cscale(sg, cur.hbp);
+            tbp_p = cscale(sg, cur.tbp);
+            nxt = cur;  // unused: the sweep ends with this row
+        }
+        {
+            const size_t o = (size_t)min(t + 3, last) * P + ci;
+            rp = ld(u_in, o);
+            rq = ld(u_in, o + A.plane);
+        }
+        const Sig si = kerr_sigma(Vi, cur.g);
+        const Coef ki = kerr_coef(Vi, cur.g, si);
+        const Coef dki = kerr_coef_da_reg(Vi, rad_from_lds(rdi, t & A.zero), cur.g, si, ki);
+
+        // stage 1, Pi component at the halves, and its a-derivative
+        const cd hq = {fma(cur.wp, ubp_p.re, cur.x.re), fma(cur.wp, ubp_p.im, cur.x.im)};
+        const cd hql = from_left(hq);
+        const cd hbq = cavg(hq, hql);
+        const cd dhq = csub(hq, hql);
+        const cd thq = {fma(cur.twp, ubp_p.re, cur.tx.re), fma(cur.twp, ubp_p.im, cur.tx.im)};
+        const cd thql = from_left(thq);
+        const cd tbq = cavg(thq, thql);
+        const cd tdq = csub(thq, thql);
+
+        // stage 2 (the forward kernel's expressions)
+        const double tb = A.dt_dr * ki.b;
+        cd np = {fma(-tb, cur.dhp.re, fma(A.dt, hbq.re, cur.p.re)), fma(-tb, cur.dhp.im, fma(A.dt, hbq.im, cur.p.im))};
+        const cd dq2 = d_pi(ki, cur.dhp, dhq);
+        const cd s2 = s_pi(ki, hbp_m, cur.hbp, hbp_p, hbq);
+        cd nq = {fma(A.dt, s2.re, fma(-A.dt_dr, dq2.re, cur.q.re)), fma(A.dt, s2.im, fma(-A.dt_dr, dq2.im, cur.q.im))};
+        // T_Phi = -dt/dr (db dh_Phi + b d(dh)_Phi) + dt d(h)bar_Pi
+        cd tp = {fma(-A.dt_dr, fma(dki.b, cur.dhp.re, ki.b * cur.tdp.re), A.dt * tbq.re),
+                 fma(-A.dt_dr, fma(dki.b, cur.dhp.im, ki.b * cur.tdp.im), A.dt * tbq.im)};
+        // T_Pi = -dt/dr [D'(dh) + D(d(dh))]_Pi + dt [S'(hbar) + S(d(h)bar)]
+        const cd e1 = d_pi(dki, cur.dhp, dhq), e2 = d_pi(ki, cur.tdp, tdq);
+        const cd f1 = s_pi(dki, hbp_m, cur.hbp, hbp_p, hbq), f2 = s_pi(ki, tbp_m, cur.tbp, tbp_p, tbq);
+        cd tq = {fma(A.dt, f1.re + f2.re, -A.dt_dr * (e1.re + e2.re)),
+                 fma(A.dt, f1.im + f2.im, -A.dt_dr * (e1.im + e2.im))};
+        if (boundary) {
+            np = {0.0, 0.0};
+            nq = {0.0, 0.0};
+            tp = {0.0, 0.0};
+            tq = {0.0, 0.0};
+        }
+        if (store_ok) {
+            const size_t so = (size_t)t * P + col;
+            st(u_out, so, np);
+            st(u_out, so + A.plane, nq);
+            st(t_out, so, tp);
+            st(t_out, so + A.plane, tq);
+        }
+        hbp_m = cur.hbp;
+        tbp_m = cur.tbp;
+    };
+
+    TanRow other;
+    int t0 = j0;
+    for (; t0 + 2 <= j1; t0 += 2) {
+        finish_row(t0, cur, other, bp[0], bq[0]);
+        finish_row(t0 + 1, other, cur, bp[1], bq[1]);
+    }
+    if (t0 < j1) finish_row(t0, cur, other, bp[0], bq[0]);
 }
 
 // lam_Phi += E^T g for every extraction point, in point order (one thread).
@@ -766,22 +1082,35 @@ static void adjoint_launch_shape(const AdjScalars& k, int waves_per_block, int f
     *lds_bytes = (size_t)slices * fields_per_strip * kWave * sizeof(double);
 }
 
-hipError_t launch_adjoint(const AdjArgs& a, int waves_per_block, bool spin, hipStream_t s) {
+hipError_t launch_adjoint(const AdjArgs& a, int waves_per_block, AdjMode mode, hipStream_t s) {
     dim3 grid, block;
     size_t lds;
+    const bool spin = mode == AdjMode::kSpin;
     adjoint_launch_shape(a.k, waves_per_block, (spin ? 4 : 2) * kNumRad, &grid, &block, &lds);
-    auto kern = spin ? lw_adjoint_kernel<true> : lw_adjoint_kernel<false>;
+    auto kern = spin ? lw_adjoint_kernel<true, false>
+                     : (mode == AdjMode::kTangentDot ? lw_adjoint_kernel<false, true> : lw_adjoint_kernel<false, false>);
     hipLaunchKernelGGL(kern, grid, block, lds, s, a.nu_in, a.u_in, a.lam_out, a.rad, a.rad_da, a.ang, a.slots, a.ext,
                        a.gsample, a.k);
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint2(const AdjArgs& a, const double* gsample_b, int waves_per_block, hipStream_t s) {
+hipError_t launch_adjoint2(const AdjArgs& a, const double* gsample_b, const double2* tan_b, int waves_per_block,
+                           hipStream_t s) {
     dim3 grid, block;
     size_t lds;
     adjoint_launch_shape(a.k, waves_per_block, 2 * kNumRad, &grid, &block, &lds);
-    hipLaunchKernelGGL(lw_adjoint2_kernel, grid, block, lds, s, a.nu_in, a.lam_out, a.rad, a.ang, a.ext, a.gsample,
-                       gsample_b, a.k);
+    auto kern = a.u_in ? lw_adjoint2_kernel<true> : lw_adjoint2_kernel<false>;
+    hipLaunchKernelGGL(kern, grid, block, lds, s, a.nu_in, a.lam_out, a.rad, a.ang, a.ext, a.gsample, gsample_b,
+                       a.u_in, tan_b, a.slots, a.k);
+    return hipGetLastError();
+}
+
+hipError_t launch_tangent(const double2* u_in, double2* u_out, double2* t_out, const AdjArgs& a, int waves_per_block,
+                          hipStream_t s) {
+    const int64_t tiles = (int64_t)a.k.n_strips * a.k.n_chunks;
+    const dim3 block(kWave * waves_per_block), grid((unsigned)((tiles + waves_per_block - 1) / waves_per_block));
+    const size_t lds = (size_t)waves_per_block * 2 * kNumRad * kWave * sizeof(double);
+    hipLaunchKernelGGL(lw_tangent_kernel, grid, block, lds, s, u_in, u_out, t_out, a.rad, a.rad_da, a.ang, a.k);
     return hipGetLastError();
 }
 

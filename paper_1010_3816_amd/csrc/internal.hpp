@@ -171,12 +171,22 @@ hipError_t launch_batch_extract(const BatchExtPoint* pts, int n, int parity, dou
 hipError_t launch_assemble(const AssembleArgs& a, int64_t n_samples, const double2* samples, double2* psi,
                            hipStream_t s);
 hipError_t launch_nonfinite(const double2* u, int nr, int nth, int pitch, int* flag, hipStream_t s);
-// spin = false: cotangents only (u_in, rad_da and slots are not read).
-hipError_t launch_adjoint(const AdjArgs& a, int waves_per_block, bool spin, hipStream_t s);
-// Two cotangent-only adjoint steps: nu_in = lambda^{m+2} -> lam_out = lambda^m
+// Adjoint kernel variants: cotangents only (u_in, rad_da and slots are not
+// read); with the spin gradient recomputed from u^m = u_in; with the spin
+// gradient as the dot product of nu with T_m = u_in, the stored tangent.
+enum class AdjMode { kCotangent, kSpin, kTangentDot };
+hipError_t launch_adjoint(const AdjArgs& a, int waves_per_block, AdjMode mode, hipStream_t s);
+// Two cotangent adjoint steps: nu_in = lambda^{m+2} -> lam_out = lambda^m
 // (k.n_strips counted in kStripCols2-column strips); a.gsample is the sample
-// gradient added to lambda^{m+1}, gsample_b the one added to lambda^m.
-hipError_t launch_adjoint2(const AdjArgs& a, const double* gsample_b, int waves_per_block, hipStream_t s);
+// gradient added to lambda^{m+1}, gsample_b the one added to lambda^m.  With
+// a.u_in = T_{m+1} and tan_b = T_m (stored tangents) the kernel also adds the
+// spin gradient's dot products of both steps to a.slots.
+hipError_t launch_adjoint2(const AdjArgs& a, const double* gsample_b, const double2* tan_b, int waves_per_block,
+                           hipStream_t s);
+// One step u_in -> u_out that also writes T = (dA/da) u_in to t_out (tiles of
+// a.k: kStripCols-column strips, a.k.rows rows; a.rad_da the a-derivative tables).
+hipError_t launch_tangent(const double2* u_in, double2* u_out, double2* t_out, const AdjArgs& a, int waves_per_block,
+                          hipStream_t s);
 hipError_t launch_extract_adjoint(double2* lam, int pitch, const ExtPoint* pts, int n, const double2* g,
                                   hipStream_t s);
 hipError_t launch_reduce_slots(const double* slots, int n, double* out, hipStream_t s);

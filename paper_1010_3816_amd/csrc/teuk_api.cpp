@@ -212,6 +212,7 @@ struct teuk_grid {
     size_t aoff_lam[2]{}, aoff_da = 0, aoff_slots = 0, aoff_sum = 0;
     int adj_rows = 32, adj_wpb = 4, adj_chunks = 0, adj_strips = 0;  // spin-gradient and one-step kernels
     int adj2_rows = 32, adj2_chunks = 0;                              // two-step cotangent kernel
+    int tan_rows = 32, tan_chunks = 0;                                // step-with-tangent kernel
 
     double2* u(int k) const { return reinterpret_cast<double2*>(ws + L.off_u[k]); }
     template <class T>
@@ -465,6 +466,8 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
     g->adj_chunks = (nth + g->adj_rows - 1) / g->adj_rows;
     g->adj2_rows = adjoint_rows(nr, nth, (int64_t)cus * 8, kStripCols2);
     g->adj2_chunks = (nth + g->adj2_rows - 1) / g->adj2_rows;
+    g->tan_rows = adjoint_rows(nr, nth, (int64_t)cus * 8, kStripCols);
+    g->tan_chunks = (nth + g->tan_rows - 1) / g->tan_rows;
     g->adj_strips = ((int)p->nr + kStripCols - 1) / kStripCols;
     g->ext_r.assign(p->extract_rstar, p->extract_rstar + p->n_extract);
     g->ext_t.assign(p->extract_theta, p->extract_theta + p->n_extract);
@@ -682,6 +685,18 @@ ExtPoint grid_ext_point(const teuk_grid* g, double rstar, double theta) {
 
 }  // namespace
 
+int teuk_get_window_slot(teuk_grid* g, const void* d_window, int64_t k, void* d_phi, void* d_pi) {
+    if (int rc = check_grid(g)) return rc;
+    if (!d_window || !d_phi || !d_pi) return fail(TEUK_E_INVALID_ARG, "NULL pointer");
+    if (k < 0) return fail(TEUK_E_INVALID_ARG, "slot %lld < 0", (long long)k);
+    if (int rc = set_device(g)) return rc;
+    const int nr = (int)g->p.nr, nth = (int)g->p.ntheta;
+    const double2* u = reinterpret_cast<const double2*>(static_cast<const char*>(d_window) + (size_t)k * g->L.state);
+    HIP_TRY(launch_export(u, static_cast<double2*>(d_phi), 0, nr, nth, g->L.pitch, g->stream));
+    HIP_TRY(launch_export(u, static_cast<double2*>(d_pi), 1, nr, nth, g->L.pitch, g->stream));
+    return TEUK_OK;
+}
+
 int teuk_extract(teuk_grid* g, int32_t n, const double* h_rstar, const double* h_theta, void* d_out) {
     if (int rc = check_extract_args(g, n, kMaxExtract, h_rstar, h_theta, d_out)) return rc;
     if (n == 0) return TEUK_OK;
@@ -804,8 +819,8 @@ int teuk_set_adjoint_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per
         return fail(TEUK_E_INVALID_ARG, "rows_per_tile=%d outside [1, ntheta]", rows_per_tile);
     if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
         return fail(TEUK_E_INVALID_ARG, "waves_per_block=%d not in {1, 2, 4}", waves_per_block);
-    g->adj_rows = g->adj2_rows = rows_per_tile;
-    g->adj_chunks = g->adj2_chunks = (int)((g->p.ntheta + rows_per_tile - 1) / rows_per_tile);
+    g->adj_rows = g->adj2_rows = g->tan_rows = rows_per_tile;
+    g->adj_chunks = g->adj2_chunks = g->tan_chunks = (int)((g->p.ntheta + rows_per_tile - 1) / rows_per_tile);
     g->adj_wpb = waves_per_block;
     return TEUK_OK;
 }
@@ -829,7 +844,9 @@ void adjoint_layout(teuk_grid* g, size_t* total) {
     g->aoff_da = o;
     o += align_up((size_t)kNumRad * 2 * g->L.pitch * sizeof(double));
     g->aoff_slots = o;
-    o += align_up((size_t)g->adj_strips * nth * sizeof(double));  // room for any tile rows
+    // one slot per tile of either adjoint tiling, for any tile rows
+    const size_t strips2 = ((size_t)g->p.nr + kStripCols2 - 1) / kStripCols2;
+    o += align_up(std::max<size_t>(g->adj_strips, strips2) * nth * sizeof(double));
     g->aoff_sum = o;
     o += kAlign;
     *total = o;
@@ -881,6 +898,57 @@ int teuk_enable_adjoint(teuk_grid* g, void* d_adj_workspace, size_t bytes) {
     return TEUK_OK;
 }
 
+namespace {
+
+// Launch arguments of the adjoint-side kernels (tiles of the one-step
+// adjoint kernel; callers adjust rows, strips and chunks for the others).
+AdjArgs adjoint_args(const teuk_grid* g) {
+    AdjArgs a{};
+    const int nth = (int)g->p.ntheta;
+    a.k.nr = (int)g->p.nr;
+    a.k.nth = nth;
+    a.k.pitch = g->L.pitch;
+    a.k.sigma = g->sigma;
+    a.k.rows = g->adj_rows;
+    a.k.n_strips = g->adj_strips;
+    a.k.n_chunks = g->adj_chunks;
+    a.k.zero = 0;
+    a.k.plane = (int64_t)nth * g->L.pitch;
+    a.k.dt = g->p.dt;
+    a.k.hdt = 0.5 * g->p.dt;
+    a.k.dt_dr = g->p.dt / g->dr;
+    a.k.hdt_dr = 0.5 * g->p.dt / g->dr;
+    a.rad = g->at<double>(g->L.off_rad);
+    a.rad_da = reinterpret_cast<const double*>(g->aws + g->aoff_da);
+    a.ang = g->at<double>(g->L.off_ang);
+    a.ext = g->at<ExtPoint>(g->L.off_ext);
+    return a;
+}
+
+}  // namespace
+
+int teuk_step_n_tangent(teuk_grid* g, int64_t n, void* d_window) {
+    if (int rc = check_grid(g)) return rc;
+    if (n < 0) return fail(TEUK_E_INVALID_ARG, "n=%lld < 0", (long long)n);
+    if (!g->aws) return fail(TEUK_E_STATE, "teuk_enable_adjoint has not been called");
+    if (n > 0 && !d_window) return fail(TEUK_E_INVALID_ARG, "window is NULL");
+    if (d_window && reinterpret_cast<uintptr_t>(d_window) % kAlign)
+        return fail(TEUK_E_WORKSPACE, "window not %zu-byte aligned", kAlign);
+    if (n == 0) return TEUK_OK;
+    if (int rc = set_device(g)) return rc;
+    AdjArgs a = adjoint_args(g);
+    a.k.rows = g->tan_rows;
+    a.k.n_chunks = g->tan_chunks;
+    char* win = static_cast<char*>(d_window);
+    for (int64_t k = 0; k < n; ++k) {
+        double2* t_out = reinterpret_cast<double2*>(win + (size_t)k * g->L.state);
+        HIP_TRY(launch_tangent(g->u(g->cur), g->u(1 - g->cur), t_out, a, g->adj_wpb, g->stream));
+        g->cur = 1 - g->cur;
+        g->steps += 1;
+    }
+    return TEUK_OK;
+}
+
 int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi, const void* d_dL_dseries,
                         const void* d_window, int32_t flags, double* h_dL_da_accum) {
     if (int rc = check_grid(g)) return rc;
@@ -891,7 +959,10 @@ int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi
     // do not depend on the forward states (the step is linear)
     const bool spin = h_dL_da_accum != nullptr;
     if (n > 0 && spin && !d_window) return fail(TEUK_E_INVALID_ARG, "window is NULL");
-    if (flags & ~TEUK_ADJ_PROJECT_INITIAL) return fail(TEUK_E_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (flags & ~(TEUK_ADJ_PROJECT_INITIAL | TEUK_ADJ_TANGENT_WINDOW))
+        return fail(TEUK_E_INVALID_ARG, "unknown flags 0x%x", flags);
+    // the window holds T_k = (dA/da) u^k (teuk_step_n_tangent) instead of u^k
+    const bool tangent = spin && (flags & TEUK_ADJ_TANGENT_WINDOW);
     if (int rc = set_device(g)) return rc;
     const int nr = (int)g->p.nr, nth = (int)g->p.ntheta, P = g->L.pitch;
     const int ne = g->p.n_extract;
@@ -901,7 +972,8 @@ int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi
     auto lam = [&](int k) { return reinterpret_cast<double2*>(g->aws + g->aoff_lam[k]); };
     double* slots = reinterpret_cast<double*>(g->aws + g->aoff_slots);
     double* sum = reinterpret_cast<double*>(g->aws + g->aoff_sum);
-    const int nslots = g->adj_strips * g->adj_chunks;
+    const int strips2 = (nr + kStripCols2 - 1) / kStripCols2;
+    const int nslots = std::max(g->adj_strips * g->adj_chunks, strips2 * g->adj2_chunks);
 
     int c = 0;
     HIP_TRY(launch_import(static_cast<const double2*>(d_lam_phi), lam(c), 0, nr, nth, P, s));
@@ -912,52 +984,39 @@ int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi
     }
     // the sample of the segment's last state
     if (gs && n > 0) HIP_TRY(launch_extract_adjoint(lam(c), P, ext, ne, gs + (n - 1) * ne, s));
-    AdjArgs a{};
-    a.k.nr = nr;
-    a.k.nth = nth;
-    a.k.pitch = P;
-    a.k.sigma = g->sigma;
-    a.k.rows = g->adj_rows;
-    a.k.n_strips = g->adj_strips;
-    a.k.n_chunks = g->adj_chunks;
-    a.k.zero = 0;
-    a.k.plane = (int64_t)nth * P;
-    a.k.dt = g->p.dt;
-    a.k.hdt = 0.5 * g->p.dt;
-    a.k.dt_dr = g->p.dt / g->dr;
-    a.k.hdt_dr = 0.5 * g->p.dt / g->dr;
-    a.rad = g->at<double>(g->L.off_rad);
-    a.rad_da = reinterpret_cast<const double*>(g->aws + g->aoff_da);
-    a.ang = g->at<double>(g->L.off_ang);
+    AdjArgs a = adjoint_args(g);
     a.slots = slots;
-    a.ext = ext;
     // the sample of the state an adjoint step produces is added by the
     // adjoint kernel itself for a few points, by a separate pass otherwise
     const bool fused = ne <= kMaxFusedAdjointExtract;
     a.k.n_ext = fused ? ne : 0;
     const char* win = static_cast<const char*>(d_window);
+    auto slot = [&](int64_t k) { return reinterpret_cast<const double2*>(win + (size_t)k * g->L.state); };
     int64_t k = n - 1;
-    if (!spin && fused && g->steps_per_pass == 2) {
-        // cotangents only: two adjoint steps (k, then k-1) per pass
+    if ((!spin || tangent) && fused && g->steps_per_pass == 2) {
+        // cotangents (and the tangents' dot products): two adjoint steps
+        // (k, then k-1) per pass
         AdjArgs a2 = a;
-        a2.k.n_strips = (nr + kStripCols2 - 1) / kStripCols2;
+        a2.k.n_strips = strips2;
         a2.k.rows = g->adj2_rows;
         a2.k.n_chunks = g->adj2_chunks;
         for (; k >= 1; k -= 2) {
             a2.nu_in = lam(c);
             a2.lam_out = lam(1 - c);
+            a2.u_in = tangent ? slot(k) : nullptr;
             a2.gsample = gs ? reinterpret_cast<const double*>(gs + (k - 1) * ne) : nullptr;
             const double* gb = (gs && k >= 2) ? reinterpret_cast<const double*>(gs + (k - 2) * ne) : nullptr;
-            HIP_TRY(launch_adjoint2(a2, gb, g->adj_wpb, s));
+            HIP_TRY(launch_adjoint2(a2, gb, tangent ? slot(k - 1) : nullptr, g->adj_wpb, s));
             c = 1 - c;
         }
     }
+    const AdjMode mode = tangent ? AdjMode::kTangentDot : spin ? AdjMode::kSpin : AdjMode::kCotangent;
     for (; k >= 0; --k) {
         a.nu_in = lam(c);
-        a.u_in = spin ? reinterpret_cast<const double2*>(win + (size_t)k * g->L.state) : nullptr;
+        a.u_in = spin ? slot(k) : nullptr;
         a.lam_out = lam(1 - c);
         a.gsample = (gs && k >= 1 && fused) ? reinterpret_cast<const double*>(gs + (k - 1) * ne) : nullptr;
-        HIP_TRY(launch_adjoint(a, g->adj_wpb, spin, s));
+        HIP_TRY(launch_adjoint(a, g->adj_wpb, mode, s));
         c = 1 - c;
         if (gs && k >= 1 && !fused) HIP_TRY(launch_extract_adjoint(lam(c), P, ext, ne, gs + (k - 1) * ne, s));
     }
