@@ -59,6 +59,10 @@ def _load():
     lib.orc_evolve.argtypes = [P, P, P, ctypes.c_int64, I, P, P, P]
     lib.orc_num_threads.restype = I
     lib.orc_set_num_threads.argtypes = [I]
+    lib.orc_set_source.argtypes = [P, P, P]
+    lib.orc_evolve_source.argtypes = [P, P, P, ctypes.c_int64, P, I, P, P, P]
+    lib.orc_mode_sum.restype = I
+    lib.orc_mode_sum.argtypes = [D, ctypes.c_int64, I, P, I, P, P, P, P]
     for name, argt in _ADJOINT_SIGS.items():
         fn = getattr(lib, name, None)
         if fn is not None:
@@ -119,6 +123,23 @@ def coefficients(a, s, m, rstar, theta):
     if rc:
         raise ValueError("tortoise inversion failed")
     return val, dval
+
+
+def mode_sum(a, modes, rstar, phi, samples):
+    """Psi at observers (r*_o, phi_o) from mode samples (Sec. 3.2: Psi = sum_m
+    e^{i m phi} r^3 Phi_m): samples [n_samples][n_modes][n_obs] -> psi
+    [n_samples][n_obs], r from the tortoise inversion for spin a."""
+    m = np.ascontiguousarray(modes, dtype=np.int32)
+    rs = np.ascontiguousarray(rstar, dtype=np.float64)
+    ph = np.ascontiguousarray(phi, dtype=np.float64)
+    smp = np.ascontiguousarray(samples, dtype=np.complex128)
+    ns, nm, no = smp.shape
+    if nm != m.size or no != rs.size or no != ph.size:
+        raise ValueError("samples must have shape (n_samples, len(modes), len(observers))")
+    psi = np.zeros((ns, no), dtype=np.complex128)
+    if _load().orc_mode_sum(float(a), ns, nm, _ptr(m), no, _ptr(rs), _ptr(ph), _ptr(smp), _ptr(psi)):
+        raise ValueError("tortoise inversion failed")
+    return psi
 
 
 class OracleGrid:
@@ -213,6 +234,34 @@ class OracleGrid:
         self._lib.orc_evolve(self._h, _ptr(phi), _ptr(pi), int(n), ne,
                              _ptr(er) if ne else None, _ptr(et) if ne else None,
                              _ptr(series) if ne else None)
+        return phi, pi, series
+
+    def set_source(self, gi, gh):
+        """Source profile g of the inhomogeneous variant at integer (ntheta, nr)
+        and half (ntheta, nr-1) positions; None removes it."""
+        if gi is None or gh is None:
+            self._lib.orc_set_source(self._h, None, None)
+            return
+        gi = _c128(gi, self.shape)
+        gh = _c128(gh, (self.shape[0], self.shape[1] - 1))
+        self._lib.orc_set_source(self._h, _ptr(gi), _ptr(gh))
+
+    def evolve_source(self, phi, pi, f, ext_rstar=(), ext_theta=()):
+        """n = len(f) steps of the inhomogeneous variant; f[k] = (f(t_k),
+        f(t_k + dt/2)) for step k.  Returns (phi, pi, series[n, n_ext])."""
+        phi = _c128(phi, self.shape).copy()
+        pi = _c128(pi, self.shape).copy()
+        f = np.ascontiguousarray(f, dtype=np.complex128)
+        n = f.shape[0]
+        if f.shape != (n, 2):
+            raise ValueError("f must have shape (n, 2)")
+        er = np.ascontiguousarray(ext_rstar, dtype=np.float64).ravel()
+        et = np.ascontiguousarray(ext_theta, dtype=np.float64).ravel()
+        ne = er.size
+        series = np.zeros((n, ne), dtype=np.complex128)
+        self._lib.orc_evolve_source(self._h, _ptr(phi), _ptr(pi), n, _ptr(f), ne,
+                                    _ptr(er) if ne else None, _ptr(et) if ne else None,
+                                    _ptr(series) if ne else None)
         return phi, pi, series
 
     def extract(self, phi, rstar, theta):

@@ -36,6 +36,10 @@
  *                        Schwarzschild l = 2 ringdown frequency
  *   adjoint           -> dot-product identity, finite differences,
  *                        forward-mode tangent for d/da
+ *   mode sum          -> discrete Fourier transform over equally spaced
+ *                        azimuths recovers r^3 Phi_m (numpy's FFT); a
+ *                        single m = 0 mode gives r^3 with r from the
+ *                        closed-form tortoise coordinate
  * The size of the a*m terms is pinned only by the symbolic derivation.
  */
 #include <complex.h>
@@ -199,6 +203,8 @@ typedef struct {
     double* dch;    /* d/da of ch (Kerr mode)                             */
     double* xi;     /* r - r_+ at r*_i      */
     double* xh;     /* r - r_+ at r*_{i+1/2} */
+    cplx* gsi;      /* source profile g at r*_i      [nth][nr]   (NULL: none) */
+    cplx* gsh;      /* source profile g at r*_{i+1/2} [nth][nr-1] (NULL: none) */
 } orc_grid;
 
 static size_t tab_i(const orc_grid* g, int c, int j, int i) { return ((size_t)c * g->nth + j) * g->nr + i; }
@@ -208,6 +214,7 @@ void orc_destroy(orc_grid* g)
 {
     if (!g) return;
     free(g->ci); free(g->ch); free(g->dci); free(g->dch); free(g->xi); free(g->xh);
+    free(g->gsi); free(g->gsh);
     free(g);
 }
 
@@ -306,6 +313,29 @@ int orc_tortoise_x(double a, double rstar, double* x)
 
 double orc_rstar_of_x(double a, double x) { return creal(rstar_of_x(a, x)); }
 
+/* The field at observers from its azimuthal modes (Sec. 3.2): the solution
+ * is Psi = sum over m of exp(i m phi) r^3 Phi_m, so for sample k and observer
+ * o, at Boyer-Lindquist radius r_o = r_+ + x(r*_o) and azimuth phi_o,
+ *   psi[k][o] = sum_j exp(i m_j phi_o) r_o^3 samples[k][j][o].
+ * samples: [n_samples][n_modes][n_obs], psi: [n_samples][n_obs].  Returns
+ * nonzero if a tortoise inversion fails. */
+int orc_mode_sum(double a, int64_t n_samples, int n_modes, const int* m, int n_obs, const double* rstar,
+                 const double* phi, const cplx* samples, cplx* psi)
+{
+    for (int o = 0; o < n_obs; ++o) {
+        cplx x;
+        if (solve_x(a, rstar[o], &x)) return 1;
+        double r = creal(r_plus(a) + x);
+        for (int64_t k = 0; k < n_samples; ++k) {
+            cplx sum = 0.0;
+            for (int j = 0; j < n_modes; ++j)
+                sum += cexp(I * (double)m[j] * phi[o]) * (r * r * r) * samples[((size_t)k * n_modes + j) * n_obs + o];
+            psi[(size_t)k * n_obs + o] = sum;
+        }
+    }
+    return 0;
+}
+
 /* value[9] and d/da[9] at (r*, theta); returns the tortoise status. */
 int orc_coefficients(double a, int s, int m, double rstar, double th, double* val, double* dval)
 {
@@ -386,7 +416,7 @@ static void work_free(work* w)
  * Reading: D and S are evaluated with the coefficients at r*_{i+1/2} itself,
  * and S acts on the averaged state (average first, then the right-hand
  * side, as the printed kernel order implies). */
-static void stage1(const orc_grid* g, const cplx* phi, const cplx* pi, work* w)
+static void stage1(const orc_grid* g, const cplx* phi, const cplx* pi, work* w, const cplx* J)
 {
     const int nr = g->nr, nth = g->nth, nh = nr - 1;
     const size_t plane = (size_t)nth * nh;
@@ -400,6 +430,8 @@ static void stage1(const orc_grid* g, const cplx* phi, const cplx* pi, work* w)
             w->dQ[k] = pi[u + 1] - pi[u];
         }
     apply_S(g, g->ch, nh, w->ubP, w->ubQ, w->sP, w->sQ);
+    if (J)  /* inhomogeneous variant: the source is part of S's Pi row */
+        for (size_t k = 0; k < (size_t)nth * nh; ++k) w->sQ[k] += J[k];
     const double dt = g->dt, dr = g->dr;
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < nth; ++j)
@@ -420,7 +452,7 @@ static void stage1(const orc_grid* g, const cplx* phi, const cplx* pi, work* w)
  * Reading: the half-time state at the integer point, needed by S_i, is the
  * average of the two neighbouring stage-1 values (a second averaging pass).
  * Radial boundary condition: Phi = Pi = 0 at i = 0 and i = nr-1. */
-static void stage2(const orc_grid* g, cplx* phi, cplx* pi, work* w)
+static void stage2(const orc_grid* g, cplx* phi, cplx* pi, work* w, const cplx* J)
 {
     const int nr = g->nr, nth = g->nth, nh = nr - 1;
     const size_t plane = (size_t)nth * nr;
@@ -439,6 +471,8 @@ static void stage2(const orc_grid* g, cplx* phi, cplx* pi, work* w)
             w->dhQ[u] = w->hQ[kr] - w->hQ[kl];
         }
     apply_S(g, g->ci, nr, w->hbP, w->hbQ, w->tP, w->tQ);
+    if (J)
+        for (size_t u = 0; u < (size_t)nth * nr; ++u) w->tQ[u] += J[u];
     const double dt = g->dt, dr = g->dr;
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < nth; ++j)
@@ -503,9 +537,54 @@ void orc_step(const orc_grid* g, cplx* phi, cplx* pi)
 {
     work w;
     work_alloc(g, &w);
-    stage1(g, phi, pi, &w);
-    stage2(g, phi, pi, &w);
+    stage1(g, phi, pi, &w, NULL);
+    stage2(g, phi, pi, &w, NULL);
     work_free(&w);
+}
+
+/* Inhomogeneous variant (a source term J in the Pi equation, as the
+ * particle-driven form of Eq. (1) has; the paper does not give the source
+ * model, so J(t, r*, theta) = f(t) g(r*, theta) is supplied by the caller).
+ * Reading: J is part of S's Pi row and is evaluated where and when S is in
+ * each stage: at (t_n, r*_{i+1/2}) in Eq. (lw1) and at (t_n + dt/2, r*_i) in
+ * Eq. (lw2).  g is given at both positions: gi [nth][nr], gh [nth][nr-1]
+ * (NULL pointers remove the source). */
+void orc_set_source(orc_grid* g, const cplx* gi, const cplx* gh)
+{
+    free(g->gsi);
+    free(g->gsh);
+    g->gsi = g->gsh = NULL;
+    if (!gi || !gh) return;
+    size_t ni = (size_t)g->nth * g->nr, nh = (size_t)g->nth * (g->nr - 1);
+    g->gsi = malloc(ni * sizeof(cplx));
+    g->gsh = malloc(nh * sizeof(cplx));
+    memcpy(g->gsi, gi, ni * sizeof(cplx));
+    memcpy(g->gsh, gh, nh * sizeof(cplx));
+}
+
+/* n steps of the inhomogeneous variant: f[2k] = f(t_k) and f[2k+1] =
+ * f(t_k + dt/2) for step k of the call (t_k its start).  Samples as
+ * orc_evolve. */
+void orc_evolve_source(const orc_grid* g, cplx* phi, cplx* pi, int64_t n, const cplx* f, int n_ext,
+                       const double* ext_r, const double* ext_th, cplx* series)
+{
+    size_t ni = (size_t)g->nth * g->nr, nh = (size_t)g->nth * (g->nr - 1);
+    cplx* J1 = malloc(nh * sizeof(cplx));
+    cplx* J2 = malloc(ni * sizeof(cplx));
+    work w;
+    work_alloc(g, &w);
+    for (int64_t k = 0; k < n; ++k) {
+        for (size_t u = 0; u < nh; ++u) J1[u] = g->gsh ? f[2 * k] * g->gsh[u] : 0.0;
+        for (size_t u = 0; u < ni; ++u) J2[u] = g->gsi ? f[2 * k + 1] * g->gsi[u] : 0.0;
+        stage1(g, phi, pi, &w, J1);
+        stage2(g, phi, pi, &w, J2);
+        if (series)
+            for (int e = 0; e < n_ext; ++e)
+                series[k * n_ext + e] = extract(g, phi, ext_r[e], ext_th[e]);
+    }
+    work_free(&w);
+    free(J1);
+    free(J2);
 }
 
 /* n steps; after step k (k = 1..n) the n_ext extraction samples of Phi are
@@ -516,8 +595,8 @@ void orc_evolve(const orc_grid* g, cplx* phi, cplx* pi, int64_t n, int n_ext,
     work w;
     work_alloc(g, &w);
     for (int64_t k = 0; k < n; ++k) {
-        stage1(g, phi, pi, &w);
-        stage2(g, phi, pi, &w);
+        stage1(g, phi, pi, &w, NULL);
+        stage2(g, phi, pi, &w, NULL);
         if (series)
             for (int e = 0; e < n_ext; ++e)
                 series[k * n_ext + e] = extract(g, phi, ext_r[e], ext_th[e]);
@@ -678,7 +757,7 @@ void orc_tangent_a(const orc_grid* g, const cplx* phi, const cplx* pi, cplx* tp,
     cplx *s2P = calloc(ni, sizeof(cplx)), *s2Q = calloc(ni, sizeof(cplx));
     cplx *d2P = calloc(ni, sizeof(cplx)), *d2Q = calloc(ni, sizeof(cplx));
     /* values of stage 1 (h) and its tangent th = -dt/2 [ dD delta/dr - dS(ubar) ] */
-    stage1(g, phi, pi, &w);
+    stage1(g, phi, pi, &w, NULL);
     apply_S(g, g->dch, nh, w.ubP, w.ubQ, dsP, dsQ);   /* coefficient part only: */
     for (size_t k = 0; k < nhs; ++k) dsP[k] = 0.0;    /* the Phi row of S has no coefficient */
     for (int j = 0; j < nth; ++j)
