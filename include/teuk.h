@@ -120,6 +120,33 @@ int teuk_set_initial_data(teuk_grid* g, const void* d_phi, const void* d_pi);
  * extraction point e after step k+1 of this call. */
 int teuk_step_n(teuk_grid* g, int64_t n, void* d_series);
 
+/* ---- Inhomogeneous variant (a source term) ----------------------------
+ * The Teukolsky equation of a particle-driven problem (an extreme-mass-ratio
+ * inspiral, Sec. 1) has a source on its right-hand side; the paper does not
+ * give the source model.  Here the source of the first-order system is a
+ * caller-supplied separable term in the Pi equation,
+ *   d_t Pi - b Pi' + c Phi' = -Ct Pi + A2 Phi_thth + A1 Phi_th - V0 Phi + f(t) g(r*, theta),
+ * taken as part of S and evaluated where and when S is in each stage: with
+ * f(t_n) and g at r*_{i+1/2} in Eq. (lw1), with f(t_n + dt/2) and g at r*_i
+ * in Eq. (lw2).  (Several separable terms add: the evolution is affine.) */
+
+/* Device bytes for teuk_set_source (256-byte aligned, caller-allocated). */
+size_t teuk_source_workspace_bytes(const teuk_grid* g);
+
+/* Attach the source profile g: d_gi complex128 [ntheta][nr] at r*_i and
+ * d_gh complex128 [ntheta][nr-1] at r*_{i+1/2} (copied into d_src_workspace
+ * on the grid's stream; the arrays may be freed once the stream has passed
+ * this call; the workspace must stay allocated while the source is used).
+ * Both NULL: detach the source.  TEUK_E_INVALID_ARG if only one is NULL,
+ * TEUK_E_WORKSPACE if the workspace is missing, misaligned or too small. */
+int teuk_set_source(teuk_grid* g, void* d_src_workspace, size_t bytes, const void* d_gi, const void* d_gh);
+
+/* As teuk_step_n with the source term: h_f holds 4n doubles, for step k of
+ * the call (t_k its start) Re f(t_k), Im f(t_k), Re f(t_k + dt/2),
+ * Im f(t_k + dt/2); the caller keeps the absolute time.  TEUK_E_STATE
+ * without teuk_set_source; TEUK_E_INVALID_ARG for a NULL or non-finite h_f. */
+int teuk_step_n_source(teuk_grid* g, int64_t n, void* d_series, const double* h_f);
+
 /* Bilinear interpolation of the current Phi at n points (h_rstar, h_theta:
  * host arrays, r* in range, theta in [0, pi]; outside the first and last row
  * centres the angular ghost rows are used) into d_out (complex128 [n]). */
@@ -141,10 +168,22 @@ int teuk_extract_noalloc(teuk_grid* g, int32_t n, const double* h_rstar, const d
 int teuk_get_state(teuk_grid* g, void* d_phi, void* d_pi);
 
 /* Synchronous check of the current state: TEUK_OK if every value is finite,
- * TEUK_E_NONFINITE otherwise; TEUK_E_HIP if a persistent launch (see
- * teuk_set_persistent) gave up waiting at a grid barrier since the last
- * check (the state is then not valid; the flag is cleared). */
+ * TEUK_E_NONFINITE otherwise. */
 int teuk_check_finite(teuk_grid* g);
+
+/* Failure detection inside the step loop (the explicit scheme of Eqs.
+ * (lw1)-(lw2) blows up when dt is too large for the angular terms; a blown-up
+ * state is all the paper's boundary updates would carry forward).  every >= 1:
+ * teuk_step_n and teuk_step_n_store check the state on the device after
+ * every `every` steps (at the first pass boundary at or after each multiple,
+ * counted from the call's start) and after the call's last step; the first
+ * check that finds a NaN or an infinity records its step count on the
+ * device, and the call, which then synchronises the grid's stream once at
+ * its end, returns TEUK_E_NONFINITE naming that step (the steps are taken
+ * regardless; teuk_steps_taken counts them).  Each check reads the state
+ * once (32 bytes per point).  every = 0 (default): no checks, the calls stay
+ * asynchronous.  TEUK_E_INVALID_ARG for every < 0. */
+int teuk_set_finite_check(teuk_grid* g, int64_t every);
 
 /* Steps taken since the last teuk_set_initial_data, and the time step. */
 int64_t teuk_steps_taken(const teuk_grid* g);
@@ -173,22 +212,6 @@ int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per
  * TEUK_E_INVALID_ARG for other values. */
 int teuk_set_steps_per_pass(teuk_grid* g, int32_t steps_per_pass);
 int teuk_get_steps_per_pass(const teuk_grid* g, int32_t* steps_per_pass);
-
-/* Persistent launch of the step loop (Sec. 3.2's steps repeated, here with
- * the time loop inside one kernel).  mode 1: with two steps per pass and no
- * window, a run of at least two passes goes to one cooperative launch whose
- * wavefronts keep their tiles and meet at a grid-wide barrier between
- * passes, when every tile fits one round of resident wavefronts (otherwise,
- * or without cooperative launches, one launch per pass).  The state is
- * then read and written with agent-scope coherent accesses, so the barrier
- * needs no cache maintenance.  mode 0 (default): one launch per pass, which
- * measures faster on MI355X even on small grids (a barrier on one counter
- * shared by all workgroups costs more than a launch boundary).  Results are
- * identical either way.  A barrier wait gives up
- * after about a second (the launch then ends and teuk_check_finite reports
- * it).  TEUK_E_INVALID_ARG for other modes. */
-int teuk_set_persistent(teuk_grid* g, int32_t mode);
-int teuk_get_persistent(const teuk_grid* g, int32_t* mode);
 
 /* Host-only: the Boyer-Lindquist radius r (M = 1) at tortoise coordinate
  * rstar for spin a (the inverse of r*(r) of Sec. 3.2 as read here: r* = r +

@@ -71,8 +71,7 @@ def _load():
         "teuk_get_tile": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "teuk_set_steps_per_pass": (ctypes.c_int, [V, I32]),
         "teuk_get_steps_per_pass": (ctypes.c_int, [V, ctypes.POINTER(I32)]),
-        "teuk_set_persistent": (ctypes.c_int, [V, I32]),
-        "teuk_get_persistent": (ctypes.c_int, [V, ctypes.POINTER(I32)]),
+        "teuk_set_finite_check": (ctypes.c_int, [V, I64]),
         "teuk_set_adjoint_tile": (ctypes.c_int, [V, I32, I32]),
         "teuk_get_adjoint_tile": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "teuk_suggest_dt": (ctypes.c_int, [P, I64, D, D, ctypes.POINTER(D)]),
@@ -82,6 +81,9 @@ def _load():
         "teuk_step_n_store": (ctypes.c_int, [V, I64, V, V]),
         "teuk_step_n_tangent": (ctypes.c_int, [V, I64, V]),
         "teuk_get_window_slot": (ctypes.c_int, [V, V, I64, V, V]),
+        "teuk_source_workspace_bytes": (ctypes.c_size_t, [V]),
+        "teuk_set_source": (ctypes.c_int, [V, V, ctypes.c_size_t, V, V]),
+        "teuk_step_n_source": (ctypes.c_int, [V, I64, V, V]),
         "teuk_adjoint_workspace_bytes": (ctypes.c_size_t, [V]),
         "teuk_enable_adjoint": (ctypes.c_int, [V, V, ctypes.c_size_t]),
         "teuk_adjoint_step_n": (ctypes.c_int, [V, I64, V, V, V, V, I32, ctypes.POINTER(D)]),
@@ -118,8 +120,9 @@ EXPORTED = ("teuk_workspace_bytes", "teuk_init_grid", "teuk_set_coefficients", "
             "teuk_batch_set_initial_data", "teuk_batch_get_state", "teuk_batch_step_n", "teuk_batch_set_launch",
             "teuk_batch_get_launch", "teuk_batch_total_points", "teuk_batch_free",
             "teuk_batch_set_steps_per_pass", "teuk_batch_extract", "teuk_batch_n_extract", "teuk_radius",
-            "teuk_assemble_modes", "teuk_set_persistent", "teuk_get_persistent", "teuk_extract_noalloc",
-            "teuk_step_n_tangent", "teuk_get_window_slot")
+            "teuk_assemble_modes", "teuk_set_finite_check", "teuk_extract_noalloc",
+            "teuk_step_n_tangent", "teuk_get_window_slot", "teuk_source_workspace_bytes", "teuk_set_source",
+            "teuk_step_n_source")
 
 
 def _check(rc):
@@ -241,14 +244,8 @@ def teuk_get_steps_per_pass(h):
     return v.value
 
 
-def teuk_set_persistent(h, mode):
-    return _check(_lib.teuk_set_persistent(h, int(mode)))
-
-
-def teuk_get_persistent(h):
-    v = ctypes.c_int32()
-    _check(_lib.teuk_get_persistent(h, ctypes.byref(v)))
-    return v.value
+def teuk_set_finite_check(h, every):
+    return _check(_lib.teuk_set_finite_check(h, int(every)))
 
 
 def teuk_set_adjoint_tile(h, rows_per_tile, waves_per_block):
@@ -282,6 +279,24 @@ def teuk_step_n_tangent(h, n, window):
 
 def teuk_get_window_slot(h, window, k, phi, pi):
     return _check(_lib.teuk_get_window_slot(h, _dptr(window), int(k), _dptr(phi), _dptr(pi)))
+
+
+def teuk_source_workspace_bytes(h):
+    nb = _lib.teuk_source_workspace_bytes(h)
+    if nb == 0:
+        raise TeukError(TEUK_E_INVALID_ARG, teuk_last_error())
+    return nb
+
+
+def teuk_set_source(h, workspace, gi, gh):
+    nb = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    return _check(_lib.teuk_set_source(h, _dptr(workspace), nb, _dptr(gi), _dptr(gh)))
+
+
+def teuk_step_n_source(h, n, series, f):
+    """f: host array of n x 2 complex time factors (f(t_k), f(t_k + dt/2))."""
+    fa = np.ascontiguousarray(np.asarray(f, dtype=np.complex128).reshape(int(n), 2)).view(np.float64)
+    return _check(_lib.teuk_step_n_source(h, int(n), _dptr(series), fa.ctypes.data_as(ctypes.c_void_p)))
 
 
 def teuk_adjoint_workspace_bytes(h):
@@ -407,6 +422,31 @@ class TeukGrid:
         self.enable_adjoint()
         teuk_step_n_tangent(self.handle, n, window)
 
+    def set_source(self, gi, gh):
+        """Source profile g of the inhomogeneous variant, at integer (ntheta, nr)
+        and half (ntheta, nr-1) positions (complex128); None, None detaches."""
+        if gi is None and gh is None:
+            teuk_set_source(self.handle, None, None, None)
+            return
+        gi = self.torch.as_tensor(gi, dtype=self.torch.complex128, device=self.device).contiguous()
+        gh = self.torch.as_tensor(gh, dtype=self.torch.complex128, device=self.device).contiguous()
+        if tuple(gi.shape) != self.shape or tuple(gh.shape) != (self.ntheta, self.nr - 1):
+            raise ValueError("source profiles must have shapes (ntheta, nr) and (ntheta, nr - 1)")
+        if getattr(self, "source_workspace", None) is None:
+            self.source_workspace = _aligned_bytes(self.torch, teuk_source_workspace_bytes(self.handle), self.device)
+        self._source_keep = (gi, gh)  # until the stream has passed the copy
+        teuk_set_source(self.handle, self.source_workspace, gi, gh)
+
+    def step_source(self, f, series=True):
+        """len(f) steps with the source; f[k] = (f(t_k), f(t_k + dt/2)).  Returns the series or None."""
+        f = np.asarray(f, dtype=np.complex128)
+        n = int(f.shape[0])
+        out = None
+        if series and self.n_extract > 0 and n > 0:
+            out = self.torch.empty((n, self.n_extract), dtype=self.torch.complex128, device=self.device)
+        teuk_step_n_source(self.handle, n, out, f)
+        return out
+
     def window_slot(self, window, k):
         """Slot k of a window as (phi, pi) tensors of shape (ntheta, nr)."""
         phi = self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
@@ -441,13 +481,9 @@ class TeukGrid:
     def steps_per_pass(self):
         return teuk_get_steps_per_pass(self.handle)
 
-    def set_persistent(self, mode):
-        """0 (default): one launch per pass; 1: one persistent launch for
-        a run of passes whenever the tiles fit one round."""
-        teuk_set_persistent(self.handle, mode)
-
-    def persistent(self):
-        return teuk_get_persistent(self.handle)
+    def set_finite_check(self, every):
+        """Device check of the state every `every` steps inside step(); 0: off."""
+        teuk_set_finite_check(self.handle, every)
 
     def set_adjoint_tile(self, rows_per_tile, waves_per_block):
         teuk_set_adjoint_tile(self.handle, rows_per_tile, waves_per_block)

@@ -269,25 +269,6 @@ __device__ __forceinline__ void st(gout_t p, size_t o, cd v) {
     __builtin_nontemporal_store(w, p + o);
 }
 
-// Agent-scope coherent access to the state, for a launch whose workgroups
-// exchange it through memory between passes (the persistent step loop):
-// these loads and stores (global_load/store ... sc1) see and reach memory
-// past the XCD-local L2, so the grid barrier needs no L2 write-back or
-// invalidation.  Two 8-byte accesses per complex value.
-typedef __attribute__((address_space(1))) double* gdbl_t;
-
-__device__ __forceinline__ cd ld_coherent(gin_t p, size_t o) {
-    const gdbl_t q = (gdbl_t)(p + o);
-    return {__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-            __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
-}
-
-__device__ __forceinline__ void st_coherent(gout_t p, size_t o, cd v) {
-    const gdbl_t q = (gdbl_t)(p + o);
-    __hip_atomic_store(q, v.re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(q + 1, v.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // All pointers are distinct allocations (restrict): the uniform reads of
 // the angular tables and extraction descriptors become scalar loads.
 }  // namespace

@@ -68,6 +68,9 @@ struct StepScalars {
     int64_t plane;              // nth * pitch: offset of the Pi plane in a state
     double dt, hdt, dt_dr, hdt_dr;
     double inv_dth2, inv_2dth;  // USER mode scalings
+    // source term (inhomogeneous variant): time factors of the pass's steps,
+    // sf[4s .. 4s+3] = f(t_n), f(t_n + dt/2) (re, im) of its step s = 0, 1
+    double sf[8];
 };
 
 struct StepArgs {
@@ -81,6 +84,8 @@ struct StepArgs {
     double2* series;         // n_ext samples of the input Phi, or nullptr
     double2* win;            // copy of the input state (two-step kernel: the intermediate state), or nullptr
     double2* series_mid;     // two-step kernel: samples of Phi after the first step, or nullptr
+    const double2* src_i;    // source profile at the integer positions, [nth][pitch], or nullptr
+    const double2* src_h;    // source profile at the half positions, [nth][pitch]
     StepScalars k;
 };
 
@@ -140,26 +145,7 @@ struct AdjArgs {
 hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s);
 // Two steps in one pass (k.n_strips counted in kStripCols2-column strips).
 hipError_t launch_step2(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s);
-// Several two-step passes in one cooperative launch (grids whose tiles all
-// fit one round of resident wavefronts), separated by a grid-wide barrier.
-struct PersistArgs {
-    double2* u[2];           // pass p reads u[p & 1] and writes u[1 - (p & 1)]
-    const double* rad;
-    const double* ang;
-    const double* uci;
-    const double* uch;
-    const ExtPoint* ext;
-    double2* series;         // the call's series (n_ext per row), or nullptr
-    int64_t k0;              // step count before the first pass (its input is state k0)
-    unsigned* bar;           // barrier counter, zero at launch
-    int* err;                // set to 1 when a barrier wait times out
-    int32_t passes, pad;
-    StepScalars k;           // k.n_strips counted in kStripCols2-column strips
-};
-// Workgroups one cooperative launch of the persistent kernel can hold on
-// the current device (0 if it cannot be launched cooperatively).
-int persist2_capacity(bool kerr, int waves_per_block);
-hipError_t launch_persist2(const PersistArgs& a, bool kerr, int waves_per_block, hipStream_t s);
+// Zero n ints (a fill kernel: usable where a memset node is not).
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 // two = true: two steps per launch (work list of tile_begin2 / n_strips2).
 hipError_t launch_batch(const BatchMember* members, int n_members, int total_tiles, int parity, int n_blocks,
@@ -171,6 +157,9 @@ hipError_t launch_batch_extract(const BatchExtPoint* pts, int n, int parity, dou
 hipError_t launch_assemble(const AssembleArgs& a, int64_t n_samples, const double2* samples, double2* psi,
                            hipStream_t s);
 hipError_t launch_nonfinite(const double2* u, int nr, int nth, int pitch, int* flag, hipStream_t s);
+// Records `step` in *first (if still 0) when the state holds a non-finite value.
+hipError_t launch_nonfinite_step(const double2* u, int nr, int nth, int pitch, long long* first, int64_t step,
+                                 hipStream_t s);
 // Adjoint kernel variants: cotangents only (u_in, rad_da and slots are not
 // read); with the spin gradient recomputed from u^m = u_in; with the spin
 // gradient as the dot product of nu with T_m = u_in, the stored tangent.

@@ -28,6 +28,13 @@
 
 namespace teuk {
 namespace {
+// The source term of the inhomogeneous variant at one point: f g, with the
+// time factor f = (fr, fi) of the stage and the profile g at the position.
+__device__ __forceinline__ cd source(gin_t g, size_t o, double fr, double fi) {
+    const cd v = ld(g, o);
+    return {fma(fr, v.re, -fi * v.im), fma(fr, v.im, fi * v.re)};
+}
+
 // Row-sweep of one tile.  Per row t the sweep keeps:
 //   p, q      Phi, Pi at (i, t)
 //   ubp       stage-1 average of Phi at the half point i+1/2
@@ -43,11 +50,12 @@ struct Row {
 
 // One tile (strip of 64 columns x theta chunk) of one grid.  Inlined into
 // the single-grid kernel and into the batched kernel.
-template <bool KERR>
+template <bool KERR, bool SRC = false>
 __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __restrict__ u_out, ctab_t rad, ctab_t ang,
                                            ctab_t uci, ctab_t uch, cext_t ext, double2* __restrict__ series,
                                            gout_t __restrict__ win, const StepScalars& A, int strip, int chunk,
-                                           int lane) {
+                                           int lane, gin_t __restrict__ src_i = nullptr,
+                                           gin_t __restrict__ src_h = nullptr) {
     const int nr = A.nr, nth = A.nth, P = A.pitch;
     const int col = strip * kStripCols - 1 + lane;
     // Lanes outside the grid read the clamped edge column.  Their values
@@ -166,7 +174,8 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
             const cd dq = csub(qr, q);
             const cd um = (t == 0) ? cscale(sg, R.ubp) : ubp_prev;
             const cd dq1 = d_pi(kh, dp, dq);
-            const cd s1 = s_pi(kh, um, R.ubp, cd{0.0, 0.0}, ubq);
+            cd s1 = s_pi(kh, um, R.ubp, cd{0.0, 0.0}, ubq);
+            if constexpr (SRC) s1 = cadd(s1, source(src_h, (size_t)t * P + hi, A.sf[0], A.sf[1]));
             R.x = {fma(A.hdt, s1.re, fma(-A.hdt_dr, dq1.re, ubq.re)), fma(A.hdt, s1.im, fma(-A.hdt_dr, dq1.im, ubq.im))};
             R.wp = A.hdt * (kh.a2s + kh.a1s);
         }
@@ -234,7 +243,8 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
         const double tb = A.dt_dr * ki.b;
         cd np = {fma(-tb, cur.dhp.re, fma(A.dt, hbq.re, cur.p.re)), fma(-tb, cur.dhp.im, fma(A.dt, hbq.im, cur.p.im))};
         const cd dq2 = d_pi(ki, cur.dhp, dhq);
-        const cd s2 = s_pi(ki, hbp_m, cur.hbp, hbp_p, hbq);
+        cd s2 = s_pi(ki, hbp_m, cur.hbp, hbp_p, hbq);
+        if constexpr (SRC) s2 = cadd(s2, source(src_i, (size_t)t * P + ci, A.sf[2], A.sf[3]));
         cd nq = {fma(A.dt, s2.re, fma(-A.dt_dr, dq2.re, cur.q.re)), fma(A.dt, s2.im, fma(-A.dt_dr, dq2.im, cur.q.im))};
         if (boundary) {
             np = {0.0, 0.0};
@@ -290,12 +300,13 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
 // step n-1) and the intermediate state (sample of step n).
 typedef __attribute__((address_space(3))) double* lds_t;
 
-template <bool KERR, bool COH = false>
+template <bool KERR, bool SRC = false>
 __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __restrict__ u_out, ctab_t rad,
                                             ctab_t ang, ctab_t uci, ctab_t uch, cext_t ext,
                                             double2* __restrict__ series_in, double2* __restrict__ series_mid,
                                             gout_t __restrict__ u_mid, lds_t rs, const StepScalars& A, int strip,
-                                            int chunk, int lane) {
+                                            int chunk, int lane, gin_t __restrict__ src_i = nullptr,
+                                            gin_t __restrict__ src_h = nullptr) {
     const int nr = A.nr, nth = A.nth, P = A.pitch;
     const int col = strip * kStripCols2 - 2 + lane;
     // Lanes outside the grid need no masking (as in sweep_tile): what they
@@ -397,7 +408,8 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
     // Stage-1 pieces of row t (as in sweep_tile) with the half-point
     // coefficients kh of the row.  FULL = false: only the averages needed
     // from a halo row.
-    auto fresh = [&](int t, cd p, cd q, cd ubp_prev, bool full, const Ang& G, const Coef& kh) -> Row {
+    // stp: the step of the pass (0: sweep A, 1: sweep B), for the source term
+    auto fresh = [&](int t, cd p, cd q, cd ubp_prev, bool full, const Ang& G, const Coef& kh, int stp) -> Row {
         Row R;
         R.p = p;
         R.q = q;
@@ -415,7 +427,8 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
             const cd dq = csub(qr, q);
             const cd um = (t == 0) ? cscale(sg, R.ubp) : ubp_prev;
             const cd dq1 = d_pi(kh, dp, dq);
-            const cd s1 = s_pi(kh, um, R.ubp, cd{0.0, 0.0}, ubq);
+            cd s1 = s_pi(kh, um, R.ubp, cd{0.0, 0.0}, ubq);
+            if constexpr (SRC) s1 = cadd(s1, source(src_h, (size_t)t * P + hi, A.sf[4 * stp], A.sf[4 * stp + 1]));
             R.x = {fma(A.hdt, s1.re, fma(-A.hdt_dr, dq1.re, ubq.re)), fma(A.hdt, s1.im, fma(-A.hdt_dr, dq1.im, ubq.im))};
             R.wp = A.hdt * (kh.a2s + kh.a1s);
         }
@@ -425,7 +438,7 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
     // Stage 2 at (i, t) with the integer-point coefficients ki of row t: the
     // new (Phi, Pi) of row t from its stage-1 state c, hbar_Phi of row t-1
     // and (ubar_Phi, hbar_Phi) of row t+1.
-    auto out_row = [&](const Row& c, const Coef& ki, cd hbp_m, cd ubp_p, cd hbp_p, cd& np, cd& nq) {
+    auto out_row = [&](int t, const Row& c, const Coef& ki, cd hbp_m, cd ubp_p, cd hbp_p, cd& np, cd& nq, int stp) {
         const cd hq = {fma(c.wp, ubp_p.re, c.x.re), fma(c.wp, ubp_p.im, c.x.im)};
         const cd hql = from_left(hq);
         const cd hbq = cavg(hq, hql);
@@ -433,7 +446,8 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
         const double tb = A.dt_dr * ki.b;
         np = {fma(-tb, c.dhp.re, fma(A.dt, hbq.re, c.p.re)), fma(-tb, c.dhp.im, fma(A.dt, hbq.im, c.p.im))};
         const cd dq2 = d_pi(ki, c.dhp, dhq);
-        const cd s2 = s_pi(ki, hbp_m, c.hbp, hbp_p, hbq);
+        cd s2 = s_pi(ki, hbp_m, c.hbp, hbp_p, hbq);
+        if constexpr (SRC) s2 = cadd(s2, source(src_i, (size_t)t * P + ci, A.sf[4 * stp + 2], A.sf[4 * stp + 3]));
         nq = {fma(A.dt, s2.re, fma(-A.dt_dr, dq2.re, c.q.re)), fma(A.dt, s2.im, fma(-A.dt_dr, dq2.im, c.q.im))};
         if (boundary) {
             np = {0.0, 0.0};
@@ -452,21 +466,10 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
 
     auto load_row = [&](int t, cd& p, cd& q) {
         const size_t o = (size_t)min(max(t, 0), lastA) * P + ci;
-        if constexpr (COH) {
-            p = ld_coherent(u_in, o);
-            q = ld_coherent(u_in, o + A.plane);
-        } else {
-            p = ld(u_in, o);
-            q = ld(u_in, o + A.plane);
-        }
+        p = ld(u_in, o);
+        q = ld(u_in, o + A.plane);
     };
-    // the new state (COH: written through to memory, see ld_coherent)
-    auto put = [&](size_t o, cd v) {
-        if constexpr (COH)
-            st_coherent(u_out, o, v);
-        else
-            st(u_out, o, v);
-    };
+    auto put = [&](size_t o, cd v) { st(u_out, o, v); };
 
     // ---- prologue: step A completes rows j0-1 (if j0 > 0) and j0; step B
     // takes them as its halo row and its first row ------------------------
@@ -497,7 +500,7 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
         cd ubp_m = {0.0, 0.0};
         if (aS > 0) {
             const Ang G = ang_row(aS - 1);
-            const Row h = fresh(aS - 1, pp[0], pq[0], ubp_m, false, G, coef_h(aS - 1, G));
+            const Row h = fresh(aS - 1, pp[0], pq[0], ubp_m, false, G, coef_h(aS - 1, G), 0);
             sample(aS - 1, h.p, acc_in);
             ubp_m = h.ubp;
             a_hbp_m = h.hbp;
@@ -505,7 +508,7 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
         {
             const Ang G = ang_row(aS);
             kh_a = coef_h(aS, G);
-            a_cur = fresh(aS, pp[1], pq[1], ubp_m, true, G, kh_a);
+            a_cur = fresh(aS, pp[1], pq[1], ubp_m, true, G, kh_a, 0);
         }
         sample(aS, a_cur.p, acc_in);
         if (aS == 0) a_hbp_m = cscale(sg, a_cur.hbp);
@@ -518,7 +521,7 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
             if (r + 1 < nth) {
                 const Ang G = ang_row(r + 1);
                 kh_n = coef_h(r + 1, G);
-                a_nxt = fresh(r + 1, p1, q1, a_cur.ubp, true, G, kh_n);
+                a_nxt = fresh(r + 1, p1, q1, a_cur.ubp, true, G, kh_n, 0);
                 sample(r + 1, a_nxt.p, acc_in);
                 ubp_p = a_nxt.ubp;
                 hbp_p = a_nxt.hbp;
@@ -530,18 +533,18 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
             }
             ki_b = coef_i(r, a_cur.g);
             cd vp, vq;
-            out_row(a_cur, ki_b, a_hbp_m, ubp_p, hbp_p, vp, vq);
+            out_row(r, a_cur, ki_b, a_hbp_m, ubp_p, hbp_p, vp, vq, 0);
             store_mid(r, vp, vq);
             const Ang gr = a_cur.g;
             a_hbp_m = a_cur.hbp;
             a_cur = a_nxt;
             if (r < j0) {  // step B's halo row j0-1
-                const Row h = fresh(r, vp, vq, b_ubp_m, false, gr, kh_a);
+                const Row h = fresh(r, vp, vq, b_ubp_m, false, gr, kh_a, 1);
                 sample(r, h.p, acc_mid);
                 b_ubp_m = h.ubp;
                 b_hbp_m = h.hbp;
             } else {
-                b_cur = fresh(r, vp, vq, b_ubp_m, true, gr, kh_a);
+                b_cur = fresh(r, vp, vq, b_ubp_m, true, gr, kh_a, 1);
                 sample(r, b_cur.p, acc_mid);
                 if (r == 0) b_hbp_m = cscale(sg, b_cur.hbp);
             }
@@ -568,7 +571,7 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
         g_next = ang_row(r + 2);
         if (!pole || r + 1 < nth) {
             khn = coef_h(r + 1, g1);
-            an = fresh(r + 1, rp, rq, ac.ubp, true, g1, khn);
+            an = fresh(r + 1, rp, rq, ac.ubp, true, g1, khn, 0);
             sample(r + 1, an.p, acc_in);
             ubp_p = an.ubp;
             hbp_p = an.hbp;
@@ -581,14 +584,14 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
         load_row(r + 1 + kRowsInFlight2, rp, rq);
         kin = coef_i(r, ac.g);
         cd vp, vq;
-        out_row(ac, kin, a_hbp_m, ubp_p, hbp_p, vp, vq);
+        out_row(r, ac, kin, a_hbp_m, ubp_p, hbp_p, vp, vq, 0);
         store_mid(r, vp, vq);
         a_hbp_m = ac.hbp;
 
-        bn = fresh(r, vp, vq, bc.ubp, true, ac.g, khc);
+        bn = fresh(r, vp, vq, bc.ubp, true, ac.g, khc, 1);
         sample(r, bn.p, acc_mid);
         cd wp, wq;
-        out_row(bc, kic, b_hbp_m, bn.ubp, bn.hbp, wp, wq);
+        out_row(r - 1, bc, kic, b_hbp_m, bn.ubp, bn.hbp, wp, wq, 1);
         if (store_ok) {
             const size_t o = (size_t)(r - 1) * P + col;
             put(o, wp);
@@ -599,7 +602,7 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
     // the grid's last row: step B with the pole ghost row
     auto last_row = [&](const Row& bc, const Coef& kic) {
         cd wp, wq;
-        out_row(bc, kic, b_hbp_m, cscale(sg, bc.ubp), cscale(sg, bc.hbp), wp, wq);
+        out_row(nth - 1, bc, kic, b_hbp_m, cscale(sg, bc.ubp), cscale(sg, bc.hbp), wp, wq, 1);
         if (store_ok) {
             const size_t o = (size_t)(nth - 1) * P + col;
             put(o, wp);
@@ -637,12 +640,14 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
 // 2 x kNumRad x 64 doubles (13 KB) per wavefront, sized at launch.
 constexpr size_t kRadSliceBytes = 2 * kNumRad * kWave * sizeof(double);
 
-template <bool KERR>
+// SRC: the inhomogeneous variant (source profile src_i, src_h; time factors in A.sf).
+template <bool KERR, bool SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4)))
     lw_step2_kernel(const double2* __restrict__ u_in, double2* __restrict__ u_out, const double* __restrict__ rad,
                     const double* __restrict__ ang, const double* __restrict__ uci, const double* __restrict__ uch,
                     const ExtPoint* __restrict__ ext, double2* __restrict__ series_in,
-                    double2* __restrict__ series_mid, double2* __restrict__ u_mid, StepScalars A) {
+                    double2* __restrict__ series_mid, double2* __restrict__ u_mid, const double2* __restrict__ src_i,
+                    const double2* __restrict__ src_h, StepScalars A) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
     const int tile = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x / kWave));
@@ -650,92 +655,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
     const int chunk = tile / A.n_strips;
     extern __shared__ double rad_s[];
     if (chunk >= A.n_chunks) return;  // tiles beyond the last
-    sweep_tile2<KERR>((gin_t)u_in, (gout_t)u_out, (ctab_t)rad, (ctab_t)ang, (ctab_t)uci, (ctab_t)uch, (cext_t)ext,
-                      series_in, series_mid, (gout_t)u_mid,
-                      (lds_t)(rad_s + (threadIdx.x / kWave) * 2 * kNumRad * kWave), A, strip, chunk, lane);
-}
-
-// Polls of the barrier counter before a workgroup gives up (about a
-// second): the launch then ends with the error flag set instead of hanging.
-constexpr int kBarrierSpins = 1 << 21;
-
-// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima).
-constexpr int kWaitVmcnt0 = 0x0F70;
-
-// Grid-wide barrier number `target / gridDim.x` of a cooperative launch
-// (all workgroups resident).  The state is written and read with
-// agent-scope coherent accesses (ld_coherent, st_coherent), so a wavefront
-// only waits until its stores are complete; the workgroup then counts itself
-// in and waits until all have.  No L2 write-back or invalidation is needed,
-// and the cached coefficient tables stay in the L2.  Returns false when this
-// or another workgroup timed out.
-__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int* err, int* leave) {
-    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        atomicAdd(bar, 1u);
-        int ok = 1;
-        for (int spins = 0; __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++spins) {
-            if (spins >= kBarrierSpins || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
-        if (!ok) atomicOr(err, 1);
-        *leave = !ok;
-    }
-    __syncthreads();
-    return !*leave;
-}
-
-// The launch arguments, read afresh from the kernel-argument segment at each
-// use: the pointer is passed through an empty asm statement, so the compiler
-// cannot keep earlier loads live across a pass (the sweep alone fills the
-// registers).
-typedef const __attribute__((address_space(4))) PersistArgs* cpersist_t;
-__device__ __forceinline__ const PersistArgs& persist_args() {
-    cpersist_t p = (cpersist_t)__builtin_amdgcn_kernarg_segment_ptr();
-    asm volatile("" : "+s"(p));
-    return *(const PersistArgs*)p;
-}
-
-// `passes` two-step passes in one cooperative launch: each wavefront keeps
-// its tile (of the two-step kernel's tiling) from pass to pass, and a grid
-// barrier separates the passes.  Same sweep, same arithmetic (the state
-// accessed coherently): the states equal the two-step kernel's bit for bit.
-// Not used by default: one launch per pass measures faster, even on small
-// grids, whose passes are bound by the latency of one short tile per
-// wavefront rather than by the launches.
-template <bool KERR>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4)))
-    lw_persist2_kernel(PersistArgs) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wpb = blockDim.x / kWave;
-    const int wave = threadIdx.x / kWave;
-    extern __shared__ double rad_s[];
-    __shared__ int leave;
-    for (int p = 0;; ++p) {
-        {
-            const PersistArgs& P = persist_args();
-            const int tile = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + wave);
-            const int strip = tile % P.k.n_strips;
-            const int chunk = tile / P.k.n_strips;
-            if (chunk < P.k.n_chunks) {  // the others only take part in the barriers
-                const int ne = P.k.n_ext;
-                const int64_t k = P.k0 + 2 * (int64_t)p;
-                double2* s_in = (P.series && k > 0) ? P.series + (k - 1) * ne : nullptr;
-                double2* s_mid = P.series ? P.series + k * ne : nullptr;
-                sweep_tile2<KERR, true>((gin_t)P.u[p & 1], (gout_t)P.u[1 - (p & 1)], (ctab_t)P.rad,
-                                        (ctab_t)P.ang, (ctab_t)P.uci, (ctab_t)P.uch, (cext_t)P.ext, s_in, s_mid,
-                                        nullptr, (lds_t)(rad_s + wave * 2 * kNumRad * kWave), P.k, strip, chunk,
-                                        lane);
-            }
-        }
-        const PersistArgs& P = persist_args();
-        if (p + 1 >= P.passes) return;
-        if (!grid_barrier(P.bar, (unsigned)(p + 1) * gridDim.x, P.err, &leave)) return;
-    }
+    sweep_tile2<KERR, SRC>((gin_t)u_in, (gout_t)u_out, (ctab_t)rad, (ctab_t)ang, (ctab_t)uci, (ctab_t)uch,
+                           (cext_t)ext, series_in, series_mid, (gout_t)u_mid,
+                           (lds_t)(rad_s + (threadIdx.x / kWave) * 2 * kNumRad * kWave), A, strip, chunk, lane,
+                           (gin_t)src_i, (gin_t)src_h);
 }
 
 __global__ void zero_ints_kernel(int* p, int n) {
@@ -743,12 +666,12 @@ __global__ void zero_ints_kernel(int* p, int n) {
     if (i < n) p[i] = 0;
 }
 
-template <bool KERR>
+template <bool KERR, bool SRC>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_WAVES_PER_SIMD, 8)))
     lw_step_kernel(const double2* __restrict__ u_in, double2* __restrict__ u_out, const double* __restrict__ rad,
                    const double* __restrict__ ang, const double* __restrict__ uci, const double* __restrict__ uch,
                    const ExtPoint* __restrict__ ext, double2* __restrict__ series, double2* __restrict__ win,
-                   StepScalars A) {
+                   const double2* __restrict__ src_i, const double2* __restrict__ src_h, StepScalars A) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
     // Tiles are numbered strip-fastest, so the wavefronts of a workgroup take
@@ -769,8 +692,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_W
     const int chunk = tile / A.n_strips;
     if (chunk >= A.n_chunks) return;  // tiles beyond the last
 #endif
-    sweep_tile<KERR>((gin_t)u_in, (gout_t)u_out, (ctab_t)rad, (ctab_t)ang, (ctab_t)uci, (ctab_t)uch, (cext_t)ext,
-                     series, (gout_t)win, A, strip, chunk, lane);
+    sweep_tile<KERR, SRC>((gin_t)u_in, (gout_t)u_out, (ctab_t)rad, (ctab_t)ang, (ctab_t)uci, (ctab_t)uch,
+                          (cext_t)ext, series, (gout_t)win, A, strip, chunk, lane, (gin_t)src_i, (gin_t)src_h);
 }
 
 // Many grids in one persistent launch: the tiles of all members form one
@@ -929,6 +852,21 @@ __global__ void nonfinite_kernel(const double2* __restrict__ u, int nr, int nth,
     }
 }
 
+// As nonfinite_kernel for the in-loop check: the first check (in stream
+// order) that finds a non-finite value records its step count (>= 1).
+__global__ void nonfinite_step_kernel(const double2* __restrict__ u, int nr, int nth, int pitch,
+                                      unsigned long long* first, long long step) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    bool bad = false;
+    for (int j = blockIdx.y; j < nth; j += gridDim.y) {
+        const size_t o = (size_t)j * pitch + i;
+        const double2 a = u[o], b = u[o + (size_t)nth * pitch];
+        bad = bad || !isfinite(a.x) || !isfinite(a.y) || !isfinite(b.x) || !isfinite(b.y);
+    }
+    if (bad) atomicCAS(first, 0ull, (unsigned long long)step);
+}
+
 __global__ void pitch_copy_kernel(const double* __restrict__ src, double* __restrict__ dst, int rows, int cols,
                                   int pitch) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -942,42 +880,23 @@ __global__ void pitch_copy_kernel(const double* __restrict__ src, double* __rest
 hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s) {
     const int nb = (a.k.n_strips * a.k.n_chunks + waves_per_block - 1) / waves_per_block;
     const dim3 block(kWave * waves_per_block), grid(nb);
-    auto kern = kerr ? lw_step_kernel<true> : lw_step_kernel<false>;
+    const bool src = a.src_i != nullptr;
+    auto kern = kerr ? (src ? lw_step_kernel<true, true> : lw_step_kernel<true, false>)
+                     : (src ? lw_step_kernel<false, true> : lw_step_kernel<false, false>);
     hipLaunchKernelGGL(kern, grid, block, 0, s, a.u_in, a.u_out, a.rad, a.ang, a.uci, a.uch,
-                       a.ext, a.series, a.win, a.k);
+                       a.ext, a.series, a.win, a.src_i, a.src_h, a.k);
     return hipGetLastError();
 }
 
 hipError_t launch_step2(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s) {
     const int nb = (a.k.n_strips * a.k.n_chunks + waves_per_block - 1) / waves_per_block;
     const dim3 block(kWave * waves_per_block), grid(nb);
-    auto kern = kerr ? lw_step2_kernel<true> : lw_step2_kernel<false>;
+    const bool src = a.src_i != nullptr;
+    auto kern = kerr ? (src ? lw_step2_kernel<true, true> : lw_step2_kernel<true, false>)
+                     : (src ? lw_step2_kernel<false, true> : lw_step2_kernel<false, false>);
     hipLaunchKernelGGL(kern, grid, block, kerr ? waves_per_block * kRadSliceBytes : 0, s, a.u_in, a.u_out, a.rad, a.ang,
-                       a.uci, a.uch, a.ext, a.series, a.series_mid, a.win, a.k);
+                       a.uci, a.uch, a.ext, a.series, a.series_mid, a.win, a.src_i, a.src_h, a.k);
     return hipGetLastError();
-}
-
-int persist2_capacity(bool kerr, int waves_per_block) {
-    int dev = 0, coop = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    const void* kern = kerr ? reinterpret_cast<const void*>(lw_persist2_kernel<true>)
-                            : reinterpret_cast<const void*>(lw_persist2_kernel<false>);
-    const size_t lds = kerr ? waves_per_block * kRadSliceBytes : 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave * waves_per_block, lds) != hipSuccess)
-        return 0;
-    return per_cu * cus;
-}
-
-hipError_t launch_persist2(const PersistArgs& a, bool kerr, int waves_per_block, hipStream_t s) {
-    const int nb = (a.k.n_strips * a.k.n_chunks + waves_per_block - 1) / waves_per_block;
-    const void* kern = kerr ? reinterpret_cast<const void*>(lw_persist2_kernel<true>)
-                            : reinterpret_cast<const void*>(lw_persist2_kernel<false>);
-    PersistArgs arg = a;
-    void* params[] = {&arg};
-    return hipLaunchCooperativeKernel(kern, dim3(nb), dim3(kWave * waves_per_block), params,
-                                      kerr ? waves_per_block * kRadSliceBytes : 0, s);
 }
 
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
@@ -1036,6 +955,14 @@ hipError_t launch_assemble(const AssembleArgs& a, int64_t n_samples, const doubl
 hipError_t launch_nonfinite(const double2* u, int nr, int nth, int pitch, int* flag, hipStream_t s) {
     const dim3 block(256), grid((nr + 255) / 256, std::min(nth, kMaxGridY));
     hipLaunchKernelGGL(nonfinite_kernel, grid, block, 0, s, u, nr, nth, pitch, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_nonfinite_step(const double2* u, int nr, int nth, int pitch, long long* first, int64_t step,
+                                 hipStream_t s) {
+    const dim3 block(256), grid((nr + 255) / 256, std::min(nth, kMaxGridY));
+    hipLaunchKernelGGL(nonfinite_step_kernel, grid, block, 0, s, u, nr, nth, pitch,
+                       reinterpret_cast<unsigned long long*>(first), (long long)step);
     return hipGetLastError();
 }
 

@@ -204,8 +204,8 @@ struct teuk_grid {
     bool fused_ext = true;
     int steps_per_pass = 2;  // 2: pairs of steps in one pass (temporal blocking)
     bool fused_ext2 = true;  // extraction fusable with the two-step strips
-    int persist_mode = 0;    // teuk_set_persistent: 1 = persistent launch whenever the tiles fit
-    int persist_cap = -1;    // workgroups a cooperative persistent launch can hold (-1: not yet queried)
+    int64_t check_every = 0;  // teuk_set_finite_check: steps between device checks of the state (0: off)
+    char* sws = nullptr;      // source profile (teuk_set_source): [integer, half][nth][pitch] complex128
     bool coef_set = false;
     // adjoint (teuk_enable_adjoint)
     char* aws = nullptr;      // adjoint workspace
@@ -269,6 +269,14 @@ int check_grid(const teuk_grid* g) {
     if (!g) return fail(TEUK_E_INVALID_ARG, "grid handle is NULL");
     return TEUK_OK;
 }
+
+// Bytes of one plane of the source profile ([nth][pitch] complex128).
+size_t source_plane_bytes(const teuk_grid* g) { return align_up((size_t)g->p.ntheta * g->L.pitch * sizeof(double2)); }
+
+// Status block of the workspace: [int] non-finite flag of teuk_check_finite,
+// then at byte 8 the step count recorded by the first failing in-loop check
+// (0: none).
+long long* first_nonfinite(const teuk_grid* g) { return reinterpret_cast<long long*>(g->ws + g->L.off_flag + 8); }
 
 // Default tile of the two-step pass.  The device holds two of its wavefronts
 // per SIMD, so its tiles run in rounds of 8 x CUs; a last round that is only
@@ -528,8 +536,10 @@ int teuk_set_initial_data(teuk_grid* g, const void* d_phi, const void* d_pi) {
 namespace {
 
 // n steps; optional extraction series and optional window of input states
-// (slot k = the state before step k, stride L.state bytes).
-int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window) {
+// (slot k = the state before step k, stride L.state bytes); h_f: the time
+// factors of the source term for the n steps (4 doubles per step), or
+// nullptr for the homogeneous equation.
+int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window, const double* h_f = nullptr) {
     if (int rc = check_grid(g)) return rc;
     if (n < 0) return fail(TEUK_E_INVALID_ARG, "n=%lld < 0", (long long)n);
     if (!g->coef_set) return fail(TEUK_E_STATE, "USER-mode coefficients not set");
@@ -538,6 +548,14 @@ int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window) {
     const int ne = g->p.n_extract;
     double2* series = (ne > 0) ? static_cast<double2*>(d_series) : nullptr;
     StepArgs a = step_args(g);
+    if (h_f) {
+        a.src_i = reinterpret_cast<const double2*>(g->sws);
+        a.src_h = reinterpret_cast<const double2*>(g->sws + source_plane_bytes(g));
+    }
+    auto set_f = [&](StepScalars& k, int64_t step, int nsteps) {
+        if (h_f)
+            for (int j = 0; j < 4 * nsteps; ++j) k.sf[j] = h_f[4 * step + j];
+    };
     const bool kerr = g->p.coef_mode == TEUK_COEF_KERR;
     const ExtPoint* ext = g->at<ExtPoint>(g->L.off_ext);
     char* win = static_cast<char*>(d_window);
@@ -569,56 +587,44 @@ int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window) {
     // state); otherwise a separate pass samples each new state.
     const bool fused = g->fused_ext;
     int64_t sampled = 0;
-    // On request, runs of two-step passes go to one persistent launch
-    // (cooperative, grid barrier between passes) instead of one launch each.
-    int* flags = g->at<int>(g->L.off_flag);  // [0] non-finite, [1] barrier time-out, [2] barrier counter
-    bool persist = false;
-    int64_t persist_blocks = 1;
-    if (two && !win && n >= 4 && g->persist_mode == 1) {
-        persist_blocks = ((int64_t)a2.k.n_strips * a2.k.n_chunks + wpb2 - 1) / wpb2;
-        if (g->persist_cap < 0) g->persist_cap = persist2_capacity(kerr, wpb2);
-        persist = persist_blocks <= g->persist_cap;
-    }
+    // Optional device check of the state every check_every steps (at the
+    // first pass boundary at or after each multiple) and at the end of the
+    // call: the first check that finds a non-finite value records its step
+    // count on the device; the call reads it once, at its end.
+    long long* first_bad = first_nonfinite(g);
+    const int64_t start = g->steps;
+    int64_t last_check = start, next_check = start + g->check_every;
+    auto check_state = [&](const double2* u) -> int {
+        HIP_TRY(launch_nonfinite_step(u, (int)g->p.nr, (int)g->p.ntheta, g->L.pitch, first_bad, g->steps,
+                                      g->stream));
+        last_check = g->steps;
+        return TEUK_OK;
+    };
+    auto maybe_check = [&](const double2* u) -> int {
+        if (g->check_every <= 0 || g->steps < next_check) return TEUK_OK;
+        next_check = start + ((g->steps - start) / g->check_every + 1) * g->check_every;
+        return check_state(u);
+    };
     auto extract_state = [&](const double2* u, int64_t j) -> int {
         HIP_TRY(launch_extract(u, g->L.pitch, ext, ne, series + (j - 1) * ne, g->stream));
         sampled = j;
         return TEUK_OK;
     };
     for (int64_t k = 0; k < n;) {
-        if (persist && k + 4 <= n) {
-            PersistArgs pa{};
-            pa.u[0] = in;
-            pa.u[1] = g->u(1 - cur);
-            pa.rad = a2.rad;
-            pa.ang = a2.ang;
-            pa.uci = a2.uci;
-            pa.uch = a2.uch;
-            pa.ext = a2.ext;
-            pa.series = series;
-            pa.k0 = k;
-            pa.bar = reinterpret_cast<unsigned*>(flags + 2);
-            pa.err = flags + 1;
-            // the barrier counter reaches passes x blocks: kept below 2^31
-            pa.passes = (int)std::min<int64_t>((n - k) / 2, ((int64_t)1 << 31) / persist_blocks - 1);
-            pa.k = a2.k;
-            HIP_TRY(launch_zero_ints(flags + 2, 1, g->stream));
-            HIP_TRY(launch_persist2(pa, kerr, wpb2, g->stream));
-            if (pa.passes & 1) advance(g->u(1 - cur));
-            k += 2 * (int64_t)pa.passes;
-            g->steps += 2 * (int64_t)pa.passes;
-            if (series) sampled = k - 1;
-        } else if (two && k + 2 <= n && !(win && k == 0)) {
+        if (two && k + 2 <= n && !(win && k == 0)) {
             double2* out = next_buffer(k + 2);
             a2.u_in = in;
             a2.u_out = out;
             a2.win = win ? window_state(k + 1) : nullptr;
             a2.series = (series && k > 0) ? series + (k - 1) * ne : nullptr;
             a2.series_mid = series ? series + k * ne : nullptr;
+            set_f(a2.k, k, 2);
             HIP_TRY(launch_step2(a2, kerr, wpb2, g->stream));
             if (series) sampled = k + 1;
             advance(out);
             k += 2;
             g->steps += 2;
+            if (int rc = maybe_check(in)) return rc;
         } else {
             if (series && !fused && k > sampled)
                 if (int rc = extract_state(in, k)) return rc;
@@ -627,6 +633,7 @@ int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window) {
             a.u_out = out;
             a.win = (win && k == 0) ? window_state(0) : nullptr;
             a.series = (series && fused && k > 0) ? series + (k - 1) * ne : nullptr;
+            set_f(a.k, k, 1);
             HIP_TRY(launch_step(a, kerr, g->wpb, g->stream));
             if (series && fused && k > 0) sampled = k;
             advance(out);
@@ -634,17 +641,71 @@ int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window) {
             g->steps += 1;
             if (series && !fused)
                 if (int rc = extract_state(out, k)) return rc;
+            if (int rc = maybe_check(in)) return rc;
         }
     }
     if (series && sampled < n)
         if (int rc = extract_state(in, n)) return rc;
     g->cur = win ? 1 - cur0 : cur;
+    if (g->check_every > 0) {
+        if (last_check != g->steps)
+            if (int rc = check_state(in)) return rc;
+        long long bad = 0;
+        HIP_TRY(hipMemcpyAsync(&bad, first_bad, sizeof(bad), hipMemcpyDeviceToHost, g->stream));
+        HIP_TRY(hipStreamSynchronize(g->stream));
+        if (bad) {
+            HIP_TRY(launch_zero_ints(reinterpret_cast<int*>(first_bad), 2, g->stream));
+            return fail(TEUK_E_NONFINITE, "the state holds a non-finite value, first seen by the check after step %lld",
+                        bad);
+        }
+    }
     return TEUK_OK;
 }
 
 }  // namespace
 
 int teuk_step_n(teuk_grid* g, int64_t n, void* d_series) { return step_n_impl(g, n, d_series, nullptr); }
+
+size_t teuk_source_workspace_bytes(const teuk_grid* g) {
+    if (!g) {
+        fail(TEUK_E_INVALID_ARG, "grid handle is NULL");
+        return 0;
+    }
+    return 2 * source_plane_bytes(g);
+}
+
+int teuk_set_source(teuk_grid* g, void* d_src_workspace, size_t bytes, const void* d_gi, const void* d_gh) {
+    if (int rc = check_grid(g)) return rc;
+    if (!d_gi && !d_gh) {
+        g->sws = nullptr;
+        return TEUK_OK;
+    }
+    if (!d_gi || !d_gh) return fail(TEUK_E_INVALID_ARG, "give both source profiles or neither");
+    if (!d_src_workspace) return fail(TEUK_E_INVALID_ARG, "source workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(d_src_workspace) % kAlign)
+        return fail(TEUK_E_WORKSPACE, "source workspace not %zu-byte aligned", kAlign);
+    if (bytes < 2 * source_plane_bytes(g))
+        return fail(TEUK_E_WORKSPACE, "source workspace has %zu bytes, needs %zu", bytes, 2 * source_plane_bytes(g));
+    if (int rc = set_device(g)) return rc;
+    const int nr = (int)g->p.nr, nth = (int)g->p.ntheta, P = g->L.pitch;
+    char* ws = static_cast<char*>(d_src_workspace);
+    // complex128 rows as pairs of doubles: dense [nth][cols] -> pitched [nth][pitch]
+    HIP_TRY(launch_pitch_copy(static_cast<const double*>(d_gi), reinterpret_cast<double*>(ws), nth, 2 * nr, 2 * P,
+                              g->stream));
+    HIP_TRY(launch_pitch_copy(static_cast<const double*>(d_gh), reinterpret_cast<double*>(ws + source_plane_bytes(g)),
+                              nth, 2 * (nr - 1), 2 * P, g->stream));
+    g->sws = ws;
+    return TEUK_OK;
+}
+
+int teuk_step_n_source(teuk_grid* g, int64_t n, void* d_series, const double* h_f) {
+    if (int rc = check_grid(g)) return rc;
+    if (!g->sws) return fail(TEUK_E_STATE, "no source profile: call teuk_set_source first");
+    if (n > 0 && !h_f) return fail(TEUK_E_INVALID_ARG, "time factors are NULL");
+    for (int64_t j = 0; j < 4 * n; ++j)
+        if (!std::isfinite(h_f[j])) return fail(TEUK_E_INVALID_ARG, "time factor %lld is not finite", (long long)j);
+    return step_n_impl(g, n, d_series, nullptr, h_f);
+}
 
 size_t teuk_window_bytes(const teuk_grid* g, int64_t n) {
     if (!g || n < 0) {
@@ -748,17 +809,19 @@ int teuk_check_finite(teuk_grid* g) {
     if (int rc = check_grid(g)) return rc;
     if (int rc = set_device(g)) return rc;
     int* flag = g->at<int>(g->L.off_flag);
-    HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), g->stream));
+    HIP_TRY(launch_zero_ints(flag, 1, g->stream));
     HIP_TRY(launch_nonfinite(g->u(g->cur), (int)g->p.nr, (int)g->p.ntheta, g->L.pitch, flag, g->stream));
-    int h[2] = {0, 0};  // non-finite flag, barrier time-out flag of the persistent launches
-    HIP_TRY(hipMemcpyAsync(h, flag, sizeof(h), hipMemcpyDeviceToHost, g->stream));
+    int h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
-    if (h[1]) {
-        HIP_TRY(hipMemsetAsync(flag + 1, 0, sizeof(int), g->stream));
-        HIP_TRY(hipStreamSynchronize(g->stream));
-        return fail(TEUK_E_HIP, "a persistent launch timed out at a grid barrier: the state is not valid");
-    }
-    if (h[0]) return fail(TEUK_E_NONFINITE, "state holds a non-finite value after %lld steps", (long long)g->steps);
+    if (h) return fail(TEUK_E_NONFINITE, "state holds a non-finite value after %lld steps", (long long)g->steps);
+    return TEUK_OK;
+}
+
+int teuk_set_finite_check(teuk_grid* g, int64_t every) {
+    if (int rc = check_grid(g)) return rc;
+    if (every < 0) return fail(TEUK_E_INVALID_ARG, "every=%lld < 0", (long long)every);
+    g->check_every = every;
     return TEUK_OK;
 }
 
@@ -774,7 +837,6 @@ int teuk_set_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per_block) 
         return fail(TEUK_E_INVALID_ARG, "waves_per_block=%d not in {1, 2, 4, 8}", waves_per_block);
     g->rows = rows_per_tile;
     g->wpb = waves_per_block;
-    g->persist_cap = -1;  // depends on the workgroup size
     update_fusion(g);
     return TEUK_OK;
 }
@@ -784,19 +846,6 @@ int teuk_set_steps_per_pass(teuk_grid* g, int32_t steps_per_pass) {
     if (steps_per_pass != 1 && steps_per_pass != 2)
         return fail(TEUK_E_INVALID_ARG, "steps_per_pass=%d not in {1, 2}", steps_per_pass);
     g->steps_per_pass = steps_per_pass;
-    return TEUK_OK;
-}
-
-int teuk_set_persistent(teuk_grid* g, int32_t mode) {
-    if (int rc = check_grid(g)) return rc;
-    if (mode != 0 && mode != 1) return fail(TEUK_E_INVALID_ARG, "mode=%d not in {0, 1}", mode);
-    g->persist_mode = mode;
-    return TEUK_OK;
-}
-
-int teuk_get_persistent(const teuk_grid* g, int32_t* mode) {
-    if (int rc = check_grid(g)) return rc;
-    if (mode) *mode = g->persist_mode;
     return TEUK_OK;
 }
 

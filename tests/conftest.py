@@ -32,14 +32,31 @@ def orc():
     return oracle
 
 
+def say(config, msg):
+    """Write a line to the terminal past pytest's output capture (progress of
+    long GPU cases, and the case that was running if a run ends abruptly)."""
+    capman = config.pluginmanager.getplugin("capturemanager")
+    if capman is None:
+        sys.stderr.write(msg + "\n")
+        sys.stderr.flush()
+        return
+    with capman.global_and_fixture_disabled():
+        sys.stderr.write(msg + "\n")
+        sys.stderr.flush()
+
+
 @pytest.fixture(autouse=True)
 def _announce_gpu_case(request):
-    """Name each GPU case on the real stderr before it runs, so that a run
-    that ends abruptly still says which case was executing."""
+    """Name each GPU case on the terminal before it runs."""
     if request.node.get_closest_marker("gpu") is not None:
-        sys.__stderr__.write(f"\n[gpu-case] {request.node.nodeid}\n")
-        sys.__stderr__.flush()
+        say(request.config, f"\n[gpu-case] {request.node.nodeid}")
     yield
+
+
+@pytest.fixture
+def progress(request):
+    """progress(msg): a line on the terminal during a long test."""
+    return lambda msg: say(request.config, msg)
 
 
 @pytest.fixture(scope="session")

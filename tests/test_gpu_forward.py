@@ -37,8 +37,14 @@ def test_random_state_parity(gpu, a, s, m, nr, nth):
 
 
 def test_schwarzschild_400x32_full_run(gpu):
-    """The small standard workload, all 1000 steps, at the policy time step."""
-    w = inputs.workload("schwarzschild_400x32")
+    """The small standard workload, all 1000 steps, at the policy time step.
+    Besides its own extraction point (r* = 100, which the pulse does not
+    reach within t = 19.6 at that step), a point the pulse does reach
+    (about its centre + t/2), so that the series compared is not all tails."""
+    w = dict(inputs.workload("schwarzschild_400x32"))
+    t_end = w["steps"] * w["dt"]
+    w["extract_rstar"] = w["extract_rstar"] + [w["center"] + 0.5 * t_end]
+    w["extract_theta"] = w["extract_theta"] + [math.pi / 2]
     phi0, pi0 = inputs.initial_data(w)
     g = run_gpu(gpu, w, phi0, pi0, w["steps"])
     o = run_oracle(w, phi0, pi0, w["steps"])
@@ -46,6 +52,7 @@ def test_schwarzschild_400x32_full_run(gpu):
     assert rel_err(g[0], o[0]) <= TOL
     assert rel_err(g[1], o[1]) <= TOL
     assert rel_err(g[2], o[2]) <= TOL
+    assert np.max(np.abs(o[2][:, 1])) > 1e-3 * np.max(np.abs(o[0]))  # a real signal
 
 
 @pytest.mark.parametrize("tile", [(1, 1), (3, 2), (41, 4), (5, 8), (20, 4)])
@@ -411,3 +418,59 @@ def test_maximum_sizes(gpu):
             hi = 2000 if i1 == nr - 1 else 2000 - n - 1
             for a, b in ((got[0][:, i0:i1 + 1], p), (got[1][:, i0:i1 + 1], q)):
                 assert rel_err(a[:, lo:hi], b[:, lo:hi]) <= TOL, (i0, rel_err(a[:, lo:hi], b[:, lo:hi]))
+
+
+def test_in_loop_finite_check(gpu):
+    """teuk_set_finite_check: a NaN planted in the initial data is reported by
+    the first check (after `every` steps); a run at the literal time step
+    0.5 dr* of the 400 x 32 grid, which blows up, is reported by the first
+    check at or after the step at which the oracle's state first turns
+    non-finite; a finite run returns normally; the checked calls take all
+    their steps, with the states of unchecked calls."""
+    import torch
+
+    import oracle
+
+    w = small_case(0.5, -2, 2, 150, 24, ext=())
+    phi0, pi0 = inputs.random_state(150, 24, seed=3)
+    bad = phi0.copy()
+    bad[7, 40] = np.nan
+    g = gpu.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"])
+    g.set_finite_check(10)
+    g.set_initial_data(torch.from_numpy(bad).cuda(), torch.from_numpy(pi0).cuda())
+    with pytest.raises(gpu.TeukError) as ei:
+        g.step(25)
+    assert ei.value.code == gpu.TEUK_E_NONFINITE and "after step 10" in str(ei.value), str(ei.value)
+    assert g.steps == 25
+    g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
+    g.step(25)  # finite: no error, and the flag of the failed call was cleared
+    checked = [t.cpu().numpy() for t in g.state()]
+    g.close()
+    ref = run_gpu(gpu, w, phi0, pi0, 25)
+    assert np.array_equal(checked[0], ref[0]) and np.array_equal(checked[1], ref[1])
+
+    # blow-up at the literal time step
+    wl = dict(inputs.workload("schwarzschild_400x32"))
+    wl["dt"] = 0.5 * (wl["rstar_max"] - wl["rstar_min"]) / (wl["nr"] - 1)
+    p0, q0 = inputs.initial_data(wl)
+    o = oracle.OracleGrid(wl["a"], wl["s"], wl["m"], wl["nr"], wl["ntheta"], wl["rstar_min"], wl["rstar_max"],
+                          wl["dt"])
+    p, q = o.project(p0, q0)
+    first = None
+    for k in range(1, 1001):
+        p, q = o.step(p, q, 1)
+        if not (np.isfinite(p).all() and np.isfinite(q).all()):
+            first = k
+            break
+    assert first is not None and first > 20
+    every = 7
+    g = gpu.TeukGrid(wl["a"], wl["s"], wl["m"], wl["nr"], wl["ntheta"], wl["rstar_min"], wl["rstar_max"], wl["dt"])
+    g.set_finite_check(every)
+    g.set_initial_data(torch.from_numpy(p0).cuda(), torch.from_numpy(q0).cuda())
+    with pytest.raises(gpu.TeukError) as ei:
+        g.step(first + 100)
+    assert ei.value.code == gpu.TEUK_E_NONFINITE
+    seen = int(str(ei.value).rsplit("after step ", 1)[1].split()[0])
+    # checks run at the first pass boundary (two steps per pass) at or after each multiple of `every`
+    assert first - 1 <= seen <= first + every + 2, (first, seen)
+    g.close()

@@ -7,12 +7,14 @@ combinations the hand-written cases do not (ragged strips and chunks of every
 size, pole rows inside and at the edges of tiles, extraction points anywhere).
 
 Forward: one and two steps per pass bit-identical; state and series within
-1e-11 normwise of the oracle; the persistent step loop bit-identical to one
-launch per pass over a longer run.  Adjoint: the spin path's cotangents within
-1e-11 of the oracle's transposed steps and dL/da within 1e-10; the
-cotangent-only paths (one and two steps per pass) bit-identical to the spin
-path's cotangents.  Batch: random member sets and persistent launch shapes
-bit-identical to single-grid evolutions and extractions.
+1e-11 normwise of the oracle; a longer run with the in-loop finite check on
+(random interval) bit-identical to one without it.  Adjoint: the spin path's
+cotangents within 1e-11 of the oracle's transposed steps and dL/da within
+1e-10; the cotangent-only paths (one and two steps per pass) and the
+stored-tangent route bit-identical to the spin path's cotangents, the
+tangent route's dL/da within 1e-10 of the oracle.  Batch: random member sets
+and persistent launch shapes bit-identical to single-grid evolutions and
+extractions.
 """
 import math
 
@@ -38,7 +40,8 @@ def _draw(seed, n_max, ext_min):
     ne = int(rng.integers(ext_min, 4))
     c["ext"] = tuple((float(rng.uniform(-30.0, 60.0)), float(rng.uniform(0, math.pi))) for _ in range(ne))
     c["gser"] = rng.standard_normal((c["n"], max(ne, 1))) + 1j * rng.standard_normal((c["n"], max(ne, 1)))
-    c["persistent_n"] = int(rng.integers(4, 24))  # drawn last: the earlier draws are unchanged
+    c["long_n"] = int(rng.integers(4, 24))  # drawn last: the earlier draws are unchanged
+    c["check_every"] = int(rng.integers(1, 6))
     return c
 
 
@@ -56,14 +59,14 @@ def test_random_forward(gpu, case):
     assert rel_err(two[0], o[0]) <= TOL and rel_err(two[1], o[1]) <= TOL, c
     if c["ext"]:
         assert rel_err(two[2], o[2]) <= TOL, c
-    # the persistent step loop (one cooperative launch for the run) against
-    # one launch per pass, over a longer run
-    m = c["persistent_n"]
-    per = run_gpu(gpu, w, phi0, pi0, m, tile=(c["rows"], c["wpb"]), steps_per_pass=2, persistent=1)
-    ref = run_gpu(gpu, w, phi0, pi0, m, tile=(c["rows"], c["wpb"]), steps_per_pass=2, persistent=0)
+    # a longer run with the in-loop finite check: the checks only read the state
+    m = c["long_n"]
+    chk = run_gpu(gpu, w, phi0, pi0, m, tile=(c["rows"], c["wpb"]), steps_per_pass=2,
+                  check_every=c["check_every"])
+    ref = run_gpu(gpu, w, phi0, pi0, m, tile=(c["rows"], c["wpb"]), steps_per_pass=2)
     for k in range(3):
         if ref[k] is not None:
-            assert np.array_equal(per[k], ref[k]), (c, k)
+            assert np.array_equal(chk[k], ref[k]), (c, k)
 
 
 @pytest.mark.parametrize("case", range(16))
@@ -96,11 +99,21 @@ def test_random_adjoint(gpu, case):
         d = g.adjoint(n, lp, lq, gs, win if spin else None, spin=spin)
         torch.cuda.synchronize()
         outs.append((lp.cpu().numpy(), lq.cpu().numpy(), d))
+    # the stored-tangent route over the same steps
+    g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
+    g.set_steps_per_pass(2)
+    g.step_tangent(n, win)
+    lp = torch.from_numpy(lam0[0].copy()).cuda()
+    lq = torch.from_numpy(lam0[1].copy()).cuda()
+    d = g.adjoint(n, lp, lq, gs, win, tangent=True)
+    torch.cuda.synchronize()
+    outs.append((lp.cpu().numpy(), lq.cpu().numpy(), d))
     g.close()
-    for k in (1, 2):
+    for k in (1, 2, 3):
         assert np.array_equal(outs[0][0], outs[k][0]) and np.array_equal(outs[0][1], outs[k][1]), (c, k)
     assert rel_err(outs[0][0], ref_p) <= TOL and rel_err(outs[0][1], ref_q) <= TOL, c
     assert abs(outs[0][2] - ref_dlda) <= 1e-10 * abs(ref_dlda), (c, outs[0][2], ref_dlda)
+    assert abs(outs[3][2] - ref_dlda) <= 1e-10 * abs(ref_dlda), (c, outs[3][2], ref_dlda)
 
 
 @pytest.mark.parametrize("case", range(8))

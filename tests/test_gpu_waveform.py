@@ -2,7 +2,8 @@
 them at observers (C ABI teuk_batch_extract, teuk_assemble_modes; module
 waveform): batched samples equal single-grid samples bit for bit, mode
 samples match the oracle within the forward tolerance, and the assembled
-field matches the mode sum of the oracle's samples."""
+field matches the oracle's mode sum (oracle.mode_sum) of the oracle's
+samples."""
 import math
 
 import numpy as np
@@ -73,8 +74,27 @@ def test_mode_sum_against_oracle(gpu):
         _, _, ser = o.evolve(p, q, n_samples * every, obs_r, obs_t)
         ref[:, j, :] = ser[every - 1::every]
     assert rel_err(samples, ref) <= TOL
-    r = np.array([1.0 + math.sqrt(1.0 - a * a) + oracle.tortoise_x(a, rs) for rs in obs_r])
-    phase = np.exp(1j * np.outer(modes, [ob[2] for ob in observers]))  # [mode][observer]
-    psi_ref = (ref * phase[None, :, :]).sum(axis=1) * r[None, :] ** 3
+    psi_ref = oracle.mode_sum(a, modes, obs_r, [ob[2] for ob in observers], ref)
     assert rel_err(psi, psi_ref) <= TOL
     ms.close()
+
+
+@pytest.mark.parametrize("n_modes,n_obs,n_samples", [(1, 1, 1), (9, 4, 37), (64, 64, 3), (17, 5, 300)])
+def test_assemble_modes_against_oracle(gpu, n_modes, n_obs, n_samples):
+    """teuk_assemble_modes on random mode samples, the observers' radii from
+    teuk_radius, against the oracle's mode sum (its own tortoise inversion),
+    up to the library's limits of 64 modes and 64 observers."""
+    rng = np.random.default_rng(n_modes * 1000 + n_obs)
+    a = 0.83
+    modes = list(rng.choice(np.arange(-40, 41), size=n_modes, replace=False))
+    rstar = rng.uniform(-20.0, 300.0, n_obs)
+    phi = rng.uniform(-math.pi, math.pi, n_obs)
+    smp = rng.standard_normal((n_samples, n_modes, n_obs)) + 1j * rng.standard_normal((n_samples, n_modes, n_obs))
+    r = [binding.teuk_radius(a, x) for x in rstar]
+    stream = torch.cuda.current_stream()
+    d_smp = torch.from_numpy(smp).cuda()
+    psi = torch.empty((n_samples, n_obs), dtype=torch.complex128, device="cuda")
+    binding.teuk_assemble_modes(d_smp, modes, phi, r, psi, stream)
+    torch.cuda.synchronize()
+    ref = oracle.mode_sum(a, modes, rstar, phi, smp)
+    assert rel_err(psi.cpu().numpy(), ref) <= TOL
