@@ -11,17 +11,21 @@ in HBM before the timed region starts.  The library advances pairs of steps
 in one pass (temporal blocking); the launch shape is autotuned first.
 
 Prints one JSON line.  `value` is grid-point updates per second (one update
-= one (r*, theta) point advanced one full step).  `roofline` describes the
-dominant kernel, the two-step pass: it moves 64 algorithmic bytes per point
-per pass (Phi, Pi read and written once, complex128), i.e. 32 B per update,
-and executes about 192 FP64 flops per update (FMA = 2; counted from its
-instruction stream, coefficient rebuild included), so with the state traffic
-halved its ceiling is FP64 arithmetic: `bound` "alu", peak 78.6 TFLOP/s;
-the HBM view is given beside it.  `batched` reports the 64-member uneven
-batch in one persistent launch per pass and its ratio to `value`; `adjoint`
-the backward (recompute + adjoint) over forward time of a checkpointed
-waveform-loss gradient on the 6400 x 256 grid.  `cpu_baseline` times the
-CPU oracle (test infrastructure, plain C + OpenMP) on a bounded number of
+= one (r*, theta) point advanced one full step) over exactly the timed steps.
+`roofline` describes the dominant kernel, the two-step pass: it moves 64
+algorithmic bytes per point per pass (Phi, Pi read and written once,
+complex128), i.e. 32 B per update, against HBM (`bound` "hbm", 8 TB/s), with
+its FP64 rate and vector-instruction issue rate beside it.  `repeats` are
+five more windows as long as the timed one, `sustained` a window of 2000
+steps (the device's steady state; short windows after an idle period run
+slower while the clocks come up).  `c1` and `c2` are the 400 x 32 and
+6400 x 256 workloads for all their steps with their extraction points;
+`batched` the 64-member uneven batch in one persistent launch per pass and
+its ratio to `value`; `waveform` nine modes of one problem and their sum;
+`adjoint` the backward (recompute + adjoint) over forward time of a
+checkpointed waveform-loss gradient on the 6400 x 256 grid, by the default
+stored-tangent route and by the stored-state route.  `cpu_baseline` times
+the CPU oracle (test infrastructure, plain C + OpenMP) on a bounded number of
 steps of the same grid.
 """
 import argparse
@@ -227,6 +231,39 @@ def batched_leg(steps=200, launch=None):
     return out
 
 
+def workload_leg(name):
+    """A standard workload for all its steps from its own initial data, with
+    its extraction points, in the library's default launch: updates/s and ms
+    per step over the whole run (HIP events on the grid's stream)."""
+    import torch
+
+    from paper_1010_3816_amd import binding, inputs
+
+    w = inputs.workload(name)
+    g = binding.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"],
+                         extract_rstar=w["extract_rstar"], extract_theta=w["extract_theta"])
+    phi0, pi0 = (torch.from_numpy(x).cuda() for x in inputs.initial_data(w))
+    n = w["steps"]
+    series = torch.empty((n, g.n_extract), dtype=torch.complex128, device="cuda")
+    g.set_initial_data(phi0, pi0)
+    binding.teuk_step_n(g.handle, min(n, 200), series)  # warm-up
+    g.set_initial_data(phi0, pi0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(g.stream)
+    binding.teuk_step_n(g.handle, n, series)
+    e1.record(g.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    assert g.check_finite(), "state became non-finite"
+    rows, wpb = g.tile()
+    out = {"workload": name, "steps": n, "n_extract": g.n_extract, "ms_per_step": ms / n,
+           "value": w["nr"] * w["ntheta"] * n / (ms * 1e-3), "unit": "grid-point updates/s",
+           "tile_rows": rows, "waves_per_block": wpb}
+    g.close()
+    return out
+
+
 def adjoint_leg(n_steps=None, checkpoint_every=None):
     """Forward (with checkpoints) and backward (recompute + adjoint) of the
     waveform misfit on the adjoint workload: 6400 x 256, a = 0.7, 8000 steps,
@@ -251,21 +288,25 @@ def adjoint_leg(n_steps=None, checkpoint_every=None):
     P = torch.from_numpy(p0).cuda().requires_grad_(True)
     Q = torch.from_numpy(q0).cuda().requires_grad_(True)
     A = torch.tensor(w["a"], dtype=torch.float64, device="cuda", requires_grad=True)
-    times = []
-    for _ in range(2):  # the first pass warms up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ser = evolve(P, Q, A, cfg, n_steps, checkpoint_every)
-        L = ((ser - target).abs() ** 2).sum()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        L.backward()
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        times.append((t1 - t0, t2 - t1))
-        dlda = float(A.grad)
-        P.grad = Q.grad = A.grad = None
-    fwd, bwd = times[-1]
+    def timed(tangent):
+        times = []
+        for _ in range(2):  # the first pass warms up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ser = evolve(P, Q, A, cfg, n_steps, checkpoint_every, tangent=tangent)
+            L = ((ser - target).abs() ** 2).sum()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            L.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            times.append((t1 - t0, t2 - t1))
+            dlda = float(A.grad)
+            P.grad = Q.grad = A.grad = None
+        return times[-1], L, dlda
+
+    (fwd_s, bwd_s), _, dlda_s = timed(False)
+    (fwd, bwd), L, dlda = timed(True)
     # the same loss, gradients with respect to the initial data only: no
     # checkpoints, one cotangent sweep (nothing to recompute)
     A0 = A.detach()
@@ -285,7 +326,9 @@ def adjoint_leg(n_steps=None, checkpoint_every=None):
     fwd0, bwd0 = times0[-1]
     return {"workload": "adjoint_a0.7_6400x256", "steps": n_steps, "checkpoint_every": checkpoint_every,
             "extract": [w["extract_rstar"][0], w["extract_theta"][0]], "loss": float(L.detach()), "dL_da": dlda,
-            "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3, "ratio": bwd / fwd,
+            "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3, "ratio": bwd / fwd, "route": "stored step tangents",
+            "state_route": {"forward_ms": fwd_s * 1e3, "backward_ms": bwd_s * 1e3, "ratio": bwd_s / fwd_s,
+                            "dL_da": dlda_s},
             "initial_data_only": {"forward_ms": fwd0 * 1e3, "backward_ms": bwd0 * 1e3, "ratio": bwd0 / fwd0}}
 
 
@@ -297,7 +340,7 @@ def main():
     ap.add_argument("--workload", default="kerr_a0.99_25600x512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint legs")
-    ap.add_argument("--only", choices=["batched", "adjoint", "waveform"],
+    ap.add_argument("--only", choices=["batched", "adjoint", "waveform", "c1", "c2"],
                     help="run only this leg and print its JSON object (for profiling)")
     ap.add_argument("--batch-launch", default=None,
                     help="rows,waves_per_block,blocks for the batched leg (default: autotune)")
@@ -330,25 +373,35 @@ def main():
     if args.only == "adjoint":
         print(json.dumps(adjoint_leg(n_steps=args.adjoint_steps)), flush=True)
         return
+    if args.only in ("c1", "c2"):
+        name = {"c1": "schwarzschild_400x32", "c2": "kerr_a0.9_6400x256"}[args.only]
+        print(json.dumps(workload_leg(name)), flush=True)
+        return
     w = inputs.workload(args.workload)
     g = binding.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"],
                          extract_rstar=w["extract_rstar"], extract_theta=w["extract_theta"])
     if args.steps_per_pass:
         g.set_steps_per_pass(args.steps_per_pass)
     spp = g.steps_per_pass()
-    if args.tile:
-        g.set_tile(*(int(x) for x in args.tile.split(",")))
-    else:
-        autotune.tune_grid(g, waves=(1, 2, 4), steps=20, use_cache=False)
-    phi0, pi0 = inputs.initial_data(w)
-    g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
-    series = torch.empty((max(args.steps, args.warmup, 1), max(g.n_extract, 1)), dtype=torch.complex128,
-                         device="cuda")
+    # The initial data are made and moved to the device first; the launch
+    # shape is tuned on the grid after that, so the device works up to the
+    # warm-up and the timed region (an idle device lowers its clocks, and
+    # short windows then run slower).  The timed run starts from the
+    # workload's data again.
+    phi0, pi0 = (torch.from_numpy(x).cuda() for x in inputs.initial_data(w))
+    g.set_initial_data(phi0, pi0)
+    n_series = max(args.steps, args.warmup, 2000, 1)
+    series = torch.empty((n_series, max(g.n_extract, 1)), dtype=torch.complex128, device="cuda")
     stream = g.stream
 
     def run(n):
         binding.teuk_step_n(g.handle, n, series if g.n_extract else None)
 
+    if args.tile:
+        g.set_tile(*(int(x) for x in args.tile.split(",")))
+    else:
+        autotune.tune_grid(g, waves=(1, 2, 4), steps=50, use_cache=False)
+    g.set_initial_data(phi0, pi0)
     run(args.warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -361,8 +414,9 @@ def main():
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     assert g.check_finite(), "state became non-finite"
-    # run-to-run spread: five more windows of steps/5 (outside the timed region)
-    n_rep = max(2, (args.steps // 5) // 2 * 2)
+    # run-to-run spread: five more windows as long as the timed one, then the
+    # steady state over 2000 steps (outside the timed region)
+    n_rep = args.steps
     reps = []
     for _ in range(5):
         a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -371,6 +425,12 @@ def main():
         a1.record(stream)
         torch.cuda.synchronize()
         reps.append(w["nr"] * w["ntheta"] * n_rep / (a0.elapsed_time(a1) * 1e-3))
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a0.record(stream)
+    run(2000)
+    a1.record(stream)
+    torch.cuda.synchronize()
+    ms_sus = a0.elapsed_time(a1) / 2000
     assert g.check_finite(), "state became non-finite"
 
     pts = w["nr"] * w["ntheta"]
@@ -433,9 +493,15 @@ def main():
         "roofline": roof,
         "wall_s_timed_region": wall,
         "repeats": {"windows": 5, "steps_each": n_rep, "median": sorted(reps)[2], "min": min(reps), "max": max(reps)},
+        "sustained": {"steps": 2000, "ms_per_step": ms_sus,
+                      "value": w["nr"] * w["ntheta"] / (ms_sus * 1e-3),
+                      "roofline_frac": BYTES_PER_POINT_PASS * w["nr"] * w["ntheta"] / (spp * ms_sus * 1e-3) / 1e9
+                      / HBM_PEAK_GBS},
     }
     g.close()
     if not args.no_extras:
+        out["c1"] = workload_leg("schwarzschild_400x32")
+        out["c2"] = workload_leg("kerr_a0.9_6400x256")
         bl = batched_leg(launch=launch)
         bl["ratio_to_single"] = bl["value"] / ups
         out["batched"] = bl

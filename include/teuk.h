@@ -109,9 +109,11 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
  * stream has passed this call. */
 int teuk_set_coefficients(teuk_grid* g, const double* d_ci, const double* d_ch);
 
-/* Set the state to (d_phi, d_pi) (complex128 [ntheta][nr], read only),
- * applying the radial boundary condition (columns 0 and nr-1 set to 0), and
- * reset the step counter to 0. */
+/* Set the state to (d_phi, d_pi) (complex128 [ntheta][nr], read only), the
+ * initial data of the evolution of Sec. 3.2 (the paper does not state its
+ * initial data; any caller data are taken), applying the radial boundary
+ * condition of Sec. 3.2 (Phi = Pi = 0 on columns 0 and nr-1) so that the data
+ * lie in the space the steps act on, and reset the step counter to 0. */
 int teuk_set_initial_data(teuk_grid* g, const void* d_phi, const void* d_pi);
 
 /* Advance the state by n >= 0 Lax-Wendroff steps, Eqs. (lw1)-(lw2), each
@@ -147,9 +149,14 @@ int teuk_set_source(teuk_grid* g, void* d_src_workspace, size_t bytes, const voi
  * without teuk_set_source; TEUK_E_INVALID_ARG for a NULL or non-finite h_f. */
 int teuk_step_n_source(teuk_grid* g, int64_t n, void* d_series, const double* h_f);
 
-/* Bilinear interpolation of the current Phi at n points (h_rstar, h_theta:
- * host arrays, r* in range, theta in [0, pi]; outside the first and last row
- * centres the angular ghost rows are used) into d_out (complex128 [n]). */
+/* The waveform samples of Sec. 3 (the purpose of the evolution is the
+ * gravitational waveform; the paper does not say how the field is sampled,
+ * and bilinear interpolation of Phi in (r*, theta) between the bracketing
+ * columns and cell-centred rows is the reading used here): the current Phi at
+ * n points (h_rstar, h_theta: host arrays, r* in range, theta in [0, pi];
+ * outside the first and last row centres the angular ghost rows of the pole
+ * condition of Sec. 3.2 are used) into d_out (complex128 [n]).  Synchronises
+ * the grid's stream. */
 int teuk_extract(teuk_grid* g, int32_t n, const double* h_rstar, const double* h_theta, void* d_out);
 
 /* Allocation-free variant of teuk_extract, for callers that cannot allocate
@@ -164,7 +171,8 @@ int teuk_extract(teuk_grid* g, int32_t n, const double* h_rstar, const double* h
  * device (other threads or streams) race for it. */
 int teuk_extract_noalloc(teuk_grid* g, int32_t n, const double* h_rstar, const double* h_theta, void* d_out);
 
-/* Copy the current state into caller arrays (complex128 [ntheta][nr]). */
+/* Copy the current state (Phi, Pi of Sec. 3.2 after teuk_steps_taken steps)
+ * into caller arrays (complex128 [ntheta][nr]); asynchronous. */
 int teuk_get_state(teuk_grid* g, void* d_phi, void* d_pi);
 
 /* Synchronous check of the current state: TEUK_OK if every value is finite,

@@ -4,7 +4,9 @@ The paper's only per-device tuning knob was OpenCL's local_work_size
 (Sec. 4); here the knobs are the theta rows per wavefront tile, the
 wavefronts per workgroup and, for batched launches, the number of workgroups
 of the persistent launch.  Candidates are timed with HIP events on the
-grid's own stream, the fastest is applied, and the choice is cached in a JSON
+grid's own stream (median of three windows), the fastest is applied (for a
+single grid only if it beats the library's default by a margin), and the
+choice is cached in a JSON
 file keyed by device and problem shape ($TEUK_TUNE_CACHE, default
 ~/.cache/paper_1010_3816_amd/launch.json).  Results of the kernels do not
 depend on the launch shape, only their speed does.
@@ -56,8 +58,10 @@ def _device_key(torch, device):
 
 
 def _time(torch, stream, fn, steps, reps=3):
+    """Median over `reps` windows of `steps` steps (ms per step), after a
+    short warm-up."""
     fn(2)
-    best = float("inf")
+    times = []
     for _ in range(reps):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -65,8 +69,8 @@ def _time(torch, stream, fn, steps, reps=3):
         fn(steps)
         e1.record(stream)
         e1.synchronize()
-        best = min(best, e0.elapsed_time(e1) / steps)
-    return best
+        times.append(e0.elapsed_time(e1) / steps)
+    return sorted(times)[len(times) // 2]
 
 
 def round_rows(nr, ntheta, cus, strip_cols=60, waves_per_simd=2, rounds=(1, 2, 3, 4), lo=1, hi=128):
@@ -85,10 +89,13 @@ def round_rows(nr, ntheta, cus, strip_cols=60, waves_per_simd=2, rounds=(1, 2, 3
     return sorted(out)
 
 
-def tune_grid(grid, rows=None, waves=GRID_WAVES, steps=20, use_cache=True):
+def tune_grid(grid, rows=None, waves=GRID_WAVES, steps=20, use_cache=True, margin=0.02):
     """Pick (rows_per_tile, waves_per_block) for a TeukGrid; returns
     {"rows": r, "waves": w, "ms": t, "table": [...]}.  rows=None: GRID_ROWS
-    and the heights of round_rows."""
+    and the heights of round_rows.  The library's default shape is kept
+    unless a candidate is faster by more than `margin` (a fraction): run to
+    run spread on the device is a few per cent, and the default is the
+    round-filling shape."""
     torch = grid.torch
     key = f"grid|{_device_key(torch, grid.device)}|{grid.nr}x{grid.ntheta}"
     if use_cache:
@@ -99,13 +106,17 @@ def tune_grid(grid, rows=None, waves=GRID_WAVES, steps=20, use_cache=True):
     if rows is None:
         cus = torch.cuda.get_device_properties(grid.device).multi_processor_count
         rows = tuple(GRID_ROWS) + tuple(round_rows(grid.nr, grid.ntheta, cus))
+    default = grid.tile()
     table = []
-    for r in sorted({min(r, grid.ntheta) for r in rows}):
-        for w in waves:
-            grid.set_tile(r, w)
-            ms = _time(torch, grid.stream, lambda n: binding.teuk_step_n(grid.handle, n, None), steps)
-            table.append({"rows": r, "waves": w, "ms": ms})
+    cands = {(min(r, grid.ntheta), w) for r in rows for w in waves} | {default}
+    for r, w in sorted(cands):
+        grid.set_tile(r, w)
+        ms = _time(torch, grid.stream, lambda n: binding.teuk_step_n(grid.handle, n, None), steps)
+        table.append({"rows": r, "waves": w, "ms": ms})
     best = min(table, key=lambda e: e["ms"])
+    dflt = next(e for e in table if (e["rows"], e["waves"]) == default)
+    if dflt["ms"] <= best["ms"] * (1.0 + margin):
+        best = dflt
     grid.set_tile(best["rows"], best["waves"])
     out = {"rows": best["rows"], "waves": best["waves"], "ms": best["ms"], "table": table}
     if use_cache:
