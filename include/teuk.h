@@ -221,6 +221,24 @@ int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per
 int teuk_set_steps_per_pass(teuk_grid* g, int32_t steps_per_pass);
 int teuk_get_steps_per_pass(const teuk_grid* g, int32_t* steps_per_pass);
 
+/* Cache policy of the stores that write the next state (teuk_step_n and its
+ * variants, teuk_step_n_tangent) and the next cotangents
+ * (teuk_adjoint_step_n): with TEUK_CACHE_KEEP they are ordinary stores,
+ * whose lines stay in the device's last-level cache (256 MB on MI355X), so
+ * the next pass reads them from there; with TEUK_CACHE_STREAM they are
+ * non-temporal, which leaves the cache to the pass's input.  TEUK_CACHE_AUTO
+ * (the default) keeps them when two states (the input and the output of a
+ * pass) take at most 192 MiB.  Window slots and step tangents are always
+ * streamed.  Results do not depend on the policy, only the speed does.
+ * TEUK_E_INVALID_ARG for other values.  teuk_get_cache_policy returns the
+ * policy and, in *keeps, whether states are currently kept (either may be
+ * NULL). */
+#define TEUK_CACHE_AUTO 0
+#define TEUK_CACHE_KEEP 1
+#define TEUK_CACHE_STREAM 2
+int teuk_set_cache_policy(teuk_grid* g, int32_t policy);
+int teuk_get_cache_policy(const teuk_grid* g, int32_t* policy, int32_t* keeps);
+
 /* Host-only: the Boyer-Lindquist radius r (M = 1) at tortoise coordinate
  * rstar for spin a (the inverse of r*(r) of Sec. 3.2 as read here: r* = r +
  * 2r+/(r+ - r-) ln((r - r+)/2) - 2r-/(r+ - r-) ln((r - r-)/2)), e.g. for the
@@ -319,6 +337,15 @@ int teuk_step_n_tangent(teuk_grid* g, int64_t n, void* d_window);
 int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi, const void* d_dL_dseries,
                         const void* d_window, int32_t flags, double* h_dL_da_accum);
 
+/* As teuk_adjoint_step_n with the spin gradient, but this segment's part of
+ * dL/da is added to the device double *d_dL_da_accum on the grid's stream
+ * (accumulators of consecutive calls add in call order) and the call does
+ * not synchronise: a reverse pass over many segments keeps the device busy
+ * and reads the sum once.  The accumulator must stay allocated until the
+ * stream has passed the call.  TEUK_E_INVALID_ARG for a NULL accumulator. */
+int teuk_adjoint_step_n_async(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi, const void* d_dL_dseries,
+                              const void* d_window, int32_t flags, double* d_dL_da_accum);
+
 /* ---- Batched evolutions ------------------------------------------------
  * Many independent grids (each its own a, s, m, nr, ntheta, r* range, dt
  * and extraction points; TEUK_COEF_KERR) advanced together: one persistent
@@ -372,6 +399,9 @@ int teuk_assemble_modes(int64_t n_samples, int32_t n_modes, const int32_t* h_m, 
  * default is 64 rows (each member's rows at most), 4 wavefronts and
  * 4 x CUs workgroups (four wavefronts per SIMD). */
 int teuk_batch_set_launch(teuk_batch* b, int32_t rows_per_tile, int32_t waves_per_block, int32_t n_blocks);
+/* A batch writes its members' next states with cache-keeping stores (see
+ * teuk_set_cache_policy) when all their states, two per member, take at most
+ * 192 MiB; otherwise it streams them. */
 /* Steps per launch of the batch: 1 or 2 (default; see teuk_set_steps_per_pass).
  * Member results do not depend on it.  Synchronises the batch's stream. */
 int teuk_batch_set_steps_per_pass(teuk_batch* b, int32_t steps_per_pass);

@@ -15,11 +15,13 @@ recompute the spin term from them: the same gradient, by another route.
 
 With overlap (the default) the recompute of the next segment runs on a
 second grid and stream while the adjoint of the current one runs, into the
-other of two windows: the two passes use different device resources (the
-recompute streams the state, the adjoint is about half arithmetic and half
-memory latency), so they share the device better than they run one after
-the other.  The arithmetic and the order of the dL/da sums are unchanged, so
-the gradients are the same bit for bit.  Device memory: one more window.
+other of two windows: the two passes share the device better than they run
+one after the other.  dL/da accumulates on the device (one partial sum per
+segment, added in segment order) and the window handed back and forth is
+guarded by events, so the host never waits inside the reverse pass and the
+device is never left idle while it enqueues the next segment.  The
+arithmetic and the order of the dL/da sums are unchanged, so the gradients
+are the same bit for bit.  Device memory: one more window.
 
 When the spin needs no gradient, no checkpoints are kept and the backward
 is one adjoint sweep over all steps: the cotangents of the linear step do
@@ -49,46 +51,52 @@ def _recompute(grid, m, window, tangent):
 
 def _reverse_sequential(grid, ckpts, segs, K, gseries, lam_phi, lam_pi, tangent):
     window = grid.new_window(K)
-    dlda = 0.0
+    dlda = grid.torch.zeros((), dtype=grid.torch.float64, device=grid.device)
     for idx in range(len(segs) - 1, -1, -1):
         k, m = segs[idx]
         grid.set_initial_data(*ckpts[idx])
         _recompute(grid, m, window, tangent)
-        dlda += grid.adjoint(m, lam_phi, lam_pi, gseries[k:k + m], window, project_initial=(idx == 0),
-                             tangent=tangent)
+        grid.adjoint(m, lam_phi, lam_pi, gseries[k:k + m], window, project_initial=(idx == 0), tangent=tangent,
+                     accum=dlda)
     return dlda
 
 
 def _reverse_overlapped(grid, a, cfg, ckpts, segs, K, gseries, lam_phi, lam_pi, tangent):
     """Segments in reverse; the recompute of segment idx-1 (second grid, own
     stream, window (idx-1) % 2) is queued before the adjoint of segment idx
-    (this grid's stream, window idx % 2), which waits for its own recompute
-    only.  A window is rewritten two segments after it was filled; by then
-    its adjoint has returned (the adjoint with dL/da waits for its stream)."""
+    (this grid's stream, window idx % 2), which waits (an event) for its own
+    recompute only.  A recompute rewrites a window two segments after it was
+    filled, and waits (an event) for the adjoint that read it.  Nothing here
+    waits on the host."""
     torch = grid.torch
     rs = torch.cuda.Stream(device=grid.device)  # default priority
     rs.wait_stream(grid.stream)                 # the checkpoints were written on the forward stream
     rec = _make_grid(a, cfg, stream=rs)
     windows = [grid.new_window(K), grid.new_window(K)]
-    done = [torch.cuda.Event(), torch.cuda.Event()]
+    done = [torch.cuda.Event(), torch.cuda.Event()]       # window filled
+    released = [torch.cuda.Event(), torch.cuda.Event()]   # window read by its adjoint
 
-    def recompute(idx):
+    def recompute(idx, after_adjoint):
         m = segs[idx][1]
+        if after_adjoint:
+            rs.wait_event(released[idx % 2])
         rec.set_initial_data(*ckpts[idx])
         _recompute(rec, m, windows[idx % 2], tangent)
         done[idx % 2].record(rs)
 
-    dlda = 0.0
+    dlda = torch.zeros((), dtype=torch.float64, device=grid.device)
     last = len(segs) - 1
-    recompute(last)
+    recompute(last, False)
     for idx in range(last, -1, -1):
         if idx > 0:
-            recompute(idx - 1)
+            recompute(idx - 1, idx + 1 <= last)  # its window was last read by the adjoint of segment idx+1
         grid.stream.wait_event(done[idx % 2])
         k, m = segs[idx]
-        dlda += grid.adjoint(m, lam_phi, lam_pi, gseries[k:k + m], windows[idx % 2], project_initial=(idx == 0),
-                             tangent=tangent)
-    rs.synchronize()
+        grid.adjoint(m, lam_phi, lam_pi, gseries[k:k + m], windows[idx % 2], project_initial=(idx == 0),
+                     tangent=tangent, accum=dlda)
+        released[idx % 2].record(grid.stream)
+    grid.stream.wait_stream(rs)  # the second grid's work is done before it is released
+    torch.cuda.current_stream(grid.device).wait_stream(grid.stream)
     rec.close()
     return dlda
 
@@ -143,7 +151,7 @@ class TeukEvolve(torch.autograd.Function):
             else:
                 dlda = _reverse_sequential(grid, ctx.ckpts, segs, min(K, n), gseries, lam_phi, lam_pi, ctx.tangent)
             dtype, device, shape = ctx.a_meta
-            grad_a = torch.full(shape, dlda, dtype=dtype, device=device)
+            grad_a = dlda.to(dtype=dtype, device=device).reshape(shape)
         else:
             grid.adjoint(n, lam_phi, lam_pi, gseries, None, project_initial=True, spin=False)
         ctx.grid = None

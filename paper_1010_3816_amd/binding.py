@@ -71,6 +71,8 @@ def _load():
         "teuk_get_tile": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "teuk_set_steps_per_pass": (ctypes.c_int, [V, I32]),
         "teuk_get_steps_per_pass": (ctypes.c_int, [V, ctypes.POINTER(I32)]),
+        "teuk_set_cache_policy": (ctypes.c_int, [V, I32]),
+        "teuk_get_cache_policy": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "teuk_set_finite_check": (ctypes.c_int, [V, I64]),
         "teuk_set_adjoint_tile": (ctypes.c_int, [V, I32, I32]),
         "teuk_get_adjoint_tile": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
@@ -87,6 +89,7 @@ def _load():
         "teuk_adjoint_workspace_bytes": (ctypes.c_size_t, [V]),
         "teuk_enable_adjoint": (ctypes.c_int, [V, V, ctypes.c_size_t]),
         "teuk_adjoint_step_n": (ctypes.c_int, [V, I64, V, V, V, V, I32, ctypes.POINTER(D)]),
+        "teuk_adjoint_step_n_async": (ctypes.c_int, [V, I64, V, V, V, V, I32, V]),
         "teuk_batch_workspace_bytes": (ctypes.c_size_t, [P, I32]),
         "teuk_batch_init": (ctypes.c_int, [P, I32, V, V, ctypes.c_size_t, ctypes.POINTER(V)]),
         "teuk_batch_set_initial_data": (ctypes.c_int, [V, I32, V, V]),
@@ -116,13 +119,14 @@ EXPORTED = ("teuk_workspace_bytes", "teuk_init_grid", "teuk_set_coefficients", "
             "teuk_get_dt", "teuk_set_tile", "teuk_get_tile", "teuk_suggest_dt", "teuk_free",
             "teuk_last_error", "teuk_window_bytes", "teuk_step_n_store", "teuk_adjoint_workspace_bytes",
             "teuk_enable_adjoint", "teuk_adjoint_step_n", "teuk_set_adjoint_tile", "teuk_get_adjoint_tile",
-            "teuk_set_steps_per_pass", "teuk_get_steps_per_pass", "teuk_batch_workspace_bytes", "teuk_batch_init",
+            "teuk_set_steps_per_pass", "teuk_get_steps_per_pass", "teuk_set_cache_policy", "teuk_get_cache_policy",
+            "teuk_batch_workspace_bytes", "teuk_batch_init",
             "teuk_batch_set_initial_data", "teuk_batch_get_state", "teuk_batch_step_n", "teuk_batch_set_launch",
             "teuk_batch_get_launch", "teuk_batch_total_points", "teuk_batch_free",
             "teuk_batch_set_steps_per_pass", "teuk_batch_extract", "teuk_batch_n_extract", "teuk_radius",
             "teuk_assemble_modes", "teuk_set_finite_check", "teuk_extract_noalloc",
             "teuk_step_n_tangent", "teuk_get_window_slot", "teuk_source_workspace_bytes", "teuk_set_source",
-            "teuk_step_n_source")
+            "teuk_step_n_source", "teuk_adjoint_step_n_async")
 
 
 def _check(rc):
@@ -238,6 +242,20 @@ def teuk_set_steps_per_pass(h, steps_per_pass):
     return _check(_lib.teuk_set_steps_per_pass(h, int(steps_per_pass)))
 
 
+TEUK_CACHE_AUTO, TEUK_CACHE_KEEP, TEUK_CACHE_STREAM = 0, 1, 2
+
+
+def teuk_set_cache_policy(h, policy):
+    return _check(_lib.teuk_set_cache_policy(h, int(policy)))
+
+
+def teuk_get_cache_policy(h):
+    """(policy, keeps): the policy and whether states are currently kept in cache."""
+    p, k = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.teuk_get_cache_policy(h, ctypes.byref(p), ctypes.byref(k)))
+    return p.value, bool(k.value)
+
+
 def teuk_get_steps_per_pass(h):
     v = ctypes.c_int32()
     _check(_lib.teuk_get_steps_per_pass(h, ctypes.byref(v)))
@@ -320,10 +338,25 @@ def teuk_adjoint_step_n(h, n, lam_phi, lam_pi, dseries, window, flags=0, spin=Tr
     return acc.value if spin else None
 
 
+def teuk_adjoint_step_n_async(h, n, lam_phi, lam_pi, dseries, window, flags, accum):
+    """As teuk_adjoint_step_n with dL/da added to the device float64 tensor
+    `accum` (one element) on the grid's stream; no synchronisation."""
+    return _check(_lib.teuk_adjoint_step_n_async(h, int(n), _dptr(lam_phi), _dptr(lam_pi), _dptr(dseries),
+                                                 _dptr(window), int(flags), _dptr(accum)))
+
+
 def _aligned_bytes(torch, nbytes, device):
     buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
     off = (-buf.data_ptr()) % 256
     return buf[off:off + nbytes]
+
+
+def _cuda_device(torch, device):
+    """The device with its index filled in (the current one for "cuda" or None)."""
+    d = torch.device(device) if device is not None else torch.device("cuda")
+    if d.index is None:
+        d = torch.device(d.type, torch.cuda.current_device())
+    return d
 
 
 class TeukGrid:
@@ -336,7 +369,7 @@ class TeukGrid:
         import torch
 
         self.torch = torch
-        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = _cuda_device(torch, device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.params = make_params(a, s, m, nr, ntheta, rstar_min, rstar_max, dt, coef_mode,
                                   extract_rstar, extract_theta, stable_steps)
@@ -454,16 +487,23 @@ class TeukGrid:
         teuk_get_window_slot(self.handle, window, k, phi, pi)
         return phi, pi
 
-    def adjoint(self, n, lam_phi, lam_pi, dseries, window, project_initial=False, spin=True, tangent=False):
+    def adjoint(self, n, lam_phi, lam_pi, dseries, window, project_initial=False, spin=True, tangent=False,
+                accum=None):
         """Reverse of n stored steps; updates (lam_phi, lam_pi) in place, returns the dL/da part
         (spin=False: cotangents only, window may be None, returns None).  tangent: the window
-        holds step tangents (step_tangent) instead of states (step_store)."""
+        holds step tangents (step_tangent) instead of states (step_store).  accum: a one-element
+        float64 device tensor to which dL/da is added without synchronising (returns None)."""
         self.enable_adjoint()
         if dseries is not None:
             dseries = self.torch.as_tensor(dseries, dtype=self.torch.complex128, device=self.device).contiguous()
             if tuple(dseries.shape) != (int(n), self.n_extract):
                 raise ValueError("dseries must have shape (n, n_extract)")
         flags = (TEUK_ADJ_PROJECT_INITIAL if project_initial else 0) | (TEUK_ADJ_TANGENT_WINDOW if tangent else 0)
+        if accum is not None:
+            if accum.dtype != self.torch.float64 or accum.numel() != 1 or accum.device != self.device:
+                raise ValueError("accum must be a one-element float64 tensor on the grid's device")
+            teuk_adjoint_step_n_async(self.handle, n, lam_phi, lam_pi, dseries, window, flags, accum)
+            return None
         return teuk_adjoint_step_n(self.handle, n, lam_phi, lam_pi, dseries, window, flags, spin)
 
     def check_finite(self):
@@ -480,6 +520,12 @@ class TeukGrid:
 
     def steps_per_pass(self):
         return teuk_get_steps_per_pass(self.handle)
+
+    def set_cache_policy(self, policy):
+        teuk_set_cache_policy(self.handle, policy)
+
+    def cache_policy(self):
+        return teuk_get_cache_policy(self.handle)
 
     def set_finite_check(self, every):
         """Device check of the state every `every` steps inside step(); 0: off."""
@@ -513,7 +559,7 @@ class TeukBatch:
         import torch
 
         self.torch = torch
-        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = _cuda_device(torch, device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.members = [dict(m) for m in members]
         arr = (teuk_params * len(members))()

@@ -177,7 +177,7 @@ struct AdjRow {
 // DOT (with SPIN = false): u_in holds T_m = (dA/da) u^m (lw_tangent_kernel)
 // instead of u^m, and the spin gradient's term of this step is the dot
 // product Re <lambda^{m+1}, T_m> over the owned points.
-template <bool SPIN, bool DOT = false>
+template <bool SPIN, bool DOT, int KEEP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
     lw_adjoint_kernel(const double2* __restrict__ nu_in, const double2* __restrict__ u_in,
                       double2* __restrict__ lam_out, const double* __restrict__ rad,
@@ -422,8 +422,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
         }
         if (own) {
             const size_t o = (size_t)t * P + col;
-            st(lam_out, o, outp);
-            st(lam_out, o + A.plane, outq);
+            st_state<KEEP>(lam_out, o, outp);
+            st_state<KEEP>(lam_out, o + A.plane, outq);
         }
 
         // spin gradient: coefficient derivatives against the cotangents of
@@ -507,7 +507,7 @@ struct AdjCot {
 // Re <lambda^{m+2}, T_{m+1}> (tan_a, with the input rows as sweep A
 // completes them) and Re <lambda^{m+1}, T_m> (tan_b, with sweep B's rows),
 // over the owned points, summed per tile into slots.
-template <bool DOT>
+template <bool DOT, int KEEP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
     lw_adjoint2_kernel(const double2* __restrict__ nu_in, double2* __restrict__ lam_out, const double* __restrict__ rad, const double* __restrict__ ang,
                        const ExtPoint* __restrict__ ext, const double* __restrict__ gsample_a,
@@ -744,8 +744,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
         load_tan(tan_b, r, tbr);
         if (own) {
             const size_t o = (size_t)(r - 1) * P + col;
-            st(lam_out, o, wp);
-            st(lam_out, o + A.plane, wq);
+            st_state<KEEP>(lam_out, o, wp);
+            st_state<KEEP>(lam_out, o + A.plane, wq);
         }
         b_below = bc.up;
         b_below_h = bc.uph;
@@ -757,8 +757,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
         dot(bc, tbr);
         if (own) {
             const size_t o = (size_t)(nth - 1) * P + col;
-            st(lam_out, o, wp);
-            st(lam_out, o + A.plane, wq);
+            st_state<KEEP>(lam_out, o, wp);
+            st_state<KEEP>(lam_out, o + A.plane, wq);
         }
     };
     AdjCot a_oth, b_oth;
@@ -835,6 +835,7 @@ struct TanRow {
     Ang g;        // angular factors of row t (wavefront-uniform)
 };
 
+template <int KEEP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
     lw_tangent_kernel(const double2* __restrict__ u_in, double2* __restrict__ u_out, double2* __restrict__ t_out,
                       const double* __restrict__ rad, const double* __restrict__ rad_da,
@@ -998,8 +999,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
         }
         if (store_ok) {
             const size_t so = (size_t)t * P + col;
-            st(u_out, so, np);
-            st(u_out, so + A.plane, nq);
+            st_state<KEEP>(u_out, so, np);
+            st_state<KEEP>(u_out, so + A.plane, nq);
             st(t_out, so, tp);
             st(t_out, so + A.plane, tq);
         }
@@ -1087,8 +1088,13 @@ hipError_t launch_adjoint(const AdjArgs& a, int waves_per_block, AdjMode mode, h
     size_t lds;
     const bool spin = mode == AdjMode::kSpin;
     adjoint_launch_shape(a.k, waves_per_block, (spin ? 4 : 2) * kNumRad, &grid, &block, &lds);
-    auto kern = spin ? lw_adjoint_kernel<true, false>
-                     : (mode == AdjMode::kTangentDot ? lw_adjoint_kernel<false, true> : lw_adjoint_kernel<false, false>);
+    const bool keep = a.k.keep != 0;
+    auto pick = [&](auto k0, auto k1) { return keep ? k1 : k0; };
+    auto kern = spin ? pick(lw_adjoint_kernel<true, false, 0>, lw_adjoint_kernel<true, false, 1>)
+                     : (mode == AdjMode::kTangentDot ? pick(lw_adjoint_kernel<false, true, 0>,
+                                                            lw_adjoint_kernel<false, true, 1>)
+                                                     : pick(lw_adjoint_kernel<false, false, 0>,
+                                                            lw_adjoint_kernel<false, false, 1>));
     hipLaunchKernelGGL(kern, grid, block, lds, s, a.nu_in, a.u_in, a.lam_out, a.rad, a.rad_da, a.ang, a.slots, a.ext,
                        a.gsample, a.k);
     return hipGetLastError();
@@ -1099,7 +1105,9 @@ hipError_t launch_adjoint2(const AdjArgs& a, const double* gsample_b, const doub
     dim3 grid, block;
     size_t lds;
     adjoint_launch_shape(a.k, waves_per_block, 2 * kNumRad, &grid, &block, &lds);
-    auto kern = a.u_in ? lw_adjoint2_kernel<true> : lw_adjoint2_kernel<false>;
+    const bool keep = a.k.keep != 0;
+    auto kern = a.u_in ? (keep ? lw_adjoint2_kernel<true, 1> : lw_adjoint2_kernel<true, 0>)
+                       : (keep ? lw_adjoint2_kernel<false, 1> : lw_adjoint2_kernel<false, 0>);
     hipLaunchKernelGGL(kern, grid, block, lds, s, a.nu_in, a.lam_out, a.rad, a.ang, a.ext, a.gsample, gsample_b,
                        a.u_in, tan_b, a.slots, a.k);
     return hipGetLastError();
@@ -1110,7 +1118,8 @@ hipError_t launch_tangent(const double2* u_in, double2* u_out, double2* t_out, c
     const int64_t tiles = (int64_t)a.k.n_strips * a.k.n_chunks;
     const dim3 block(kWave * waves_per_block), grid((unsigned)((tiles + waves_per_block - 1) / waves_per_block));
     const size_t lds = (size_t)waves_per_block * 2 * kNumRad * kWave * sizeof(double);
-    hipLaunchKernelGGL(lw_tangent_kernel, grid, block, lds, s, u_in, u_out, t_out, a.rad, a.rad_da, a.ang, a.k);
+    hipLaunchKernelGGL(a.k.keep ? lw_tangent_kernel<1> : lw_tangent_kernel<0>, grid, block, lds, s, u_in, u_out, t_out,
+                       a.rad, a.rad_da, a.ang, a.k);
     return hipGetLastError();
 }
 

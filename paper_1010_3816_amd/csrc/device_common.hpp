@@ -254,7 +254,7 @@ __device__ __forceinline__ cd ld(gin_t p, size_t o) {
 }
 
 // Streaming store of one complex value (16 B, one dwordx4 per lane): the
-// new state is not read again by this launch.
+// value is not read again by this launch and, for a window slot, not soon.
 __device__ __forceinline__ void st(double2* p, size_t o, cd v) {
     v2d w;
     w.x = v.re;
@@ -267,6 +267,37 @@ __device__ __forceinline__ void st(gout_t p, size_t o, cd v) {
     w.x = v.re;
     w.y = v.im;
     __builtin_nontemporal_store(w, p + o);
+}
+
+// Store of a state the next launch reads.  KEEP: an ordinary store, whose
+// line stays in the device's last-level cache, so the next launch reads it
+// from there when the states fit (the host picks the kernel instance);
+// otherwise streaming, which leaves the cache to the input.  The choice is
+// made at compile time: with a run-time branch between the two, the
+// compiler merges them into one store to the same address and drops the
+// non-temporal hint.
+template <int KEEP>
+__device__ __forceinline__ void st_state(double2* p, size_t o, cd v) {
+    if constexpr (KEEP) {
+        v2d w;
+        w.x = v.re;
+        w.y = v.im;
+        *reinterpret_cast<v2d*>(p + o) = w;
+    } else {
+        st(p, o, v);
+    }
+}
+
+template <int KEEP>
+__device__ __forceinline__ void st_state(gout_t p, size_t o, cd v) {
+    if constexpr (KEEP) {
+        v2d w;
+        w.x = v.re;
+        w.y = v.im;
+        p[o] = w;
+    } else {
+        st(p, o, v);
+    }
 }
 
 // All pointers are distinct allocations (restrict): the uniform reads of

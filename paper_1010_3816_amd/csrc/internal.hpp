@@ -64,7 +64,8 @@ struct ExtPoint {
 struct StepScalars {
     int32_t nr, nth, pitch, sigma;
     int32_t rows, n_strips, n_chunks, n_ext;
-    int32_t zero, pad0;         // zero: always 0 (an opaque row offset of LDS reads)
+    int32_t zero;               // always 0 (an opaque row offset of LDS reads)
+    int32_t keep;               // 1: the new state is written with ordinary stores (selects the kernel instance)
     int64_t plane;              // nth * pitch: offset of the Pi plane in a state
     double dt, hdt, dt_dr, hdt_dr;
     double inv_dth2, inv_2dth;  // USER mode scalings
@@ -123,7 +124,9 @@ struct AdjScalars {
     int32_t nr, nth, pitch, sigma;
     int32_t rows, n_strips, n_chunks, zero;  // zero: always 0 (an opaque row offset of LDS reads)
     int64_t plane;                           // nth * pitch: offset of the Pi plane in a state
-    int32_t n_ext, pad;                      // extraction points (fused transposed extraction)
+    int32_t n_ext;                           // extraction points (fused transposed extraction)
+    int32_t keep;                            // 1: lam_out and the tangent step's state with ordinary stores
+                                             // (selects the kernel instance)
     double dt, hdt, dt_dr, hdt_dr;
 };
 
@@ -148,8 +151,9 @@ hipError_t launch_step2(const StepArgs& a, bool kerr, int waves_per_block, hipSt
 // Zero n ints (a fill kernel: usable where a memset node is not).
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 // two = true: two steps per launch (work list of tile_begin2 / n_strips2).
+// keep: the members' next states with ordinary stores (StepScalars::keep).
 hipError_t launch_batch(const BatchMember* members, int n_members, int total_tiles, int parity, int n_blocks,
-                        int waves_per_block, bool two, hipStream_t s);
+                        int waves_per_block, bool two, bool keep, hipStream_t s);
 hipError_t launch_import(const double2* src, double2* u, int f, int nr, int nth, int pitch, hipStream_t s);
 hipError_t launch_export(const double2* u, double2* dst, int f, int nr, int nth, int pitch, hipStream_t s);
 hipError_t launch_extract(const double2* u, int pitch, const ExtPoint* pts, int n, double2* out, hipStream_t s);

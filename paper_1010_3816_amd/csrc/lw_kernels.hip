@@ -50,7 +50,8 @@ struct Row {
 
 // One tile (strip of 64 columns x theta chunk) of one grid.  Inlined into
 // the single-grid kernel and into the batched kernel.
-template <bool KERR, bool SRC = false>
+// KEEP: the cache policy of the new state's stores (0 streaming, 1 keeping).
+template <bool KERR, bool SRC, int KEEP>
 __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __restrict__ u_out, ctab_t rad, ctab_t ang,
                                            ctab_t uci, ctab_t uch, cext_t ext, double2* __restrict__ series,
                                            gout_t __restrict__ win, const StepScalars& A, int strip, int chunk,
@@ -252,8 +253,8 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
         }
         if (store_ok) {
             const size_t o = (size_t)t * P + col;
-            st(u_out, o, np);
-            st(u_out, o + A.plane, nq);
+            st_state<KEEP>(u_out, o, np);
+            st_state<KEEP>(u_out, o + A.plane, nq);
             if (win != nullptr) {  // keep the input state (for the adjoint)
                 st(win, o, cur.p);
                 st(win, o + A.plane, cur.q);
@@ -300,7 +301,7 @@ __device__ __forceinline__ void sweep_tile(gin_t __restrict__ u_in, gout_t __res
 // step n-1) and the intermediate state (sample of step n).
 typedef __attribute__((address_space(3))) double* lds_t;
 
-template <bool KERR, bool SRC = false>
+template <bool KERR, bool SRC, int KEEP>
 __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __restrict__ u_out, ctab_t rad,
                                             ctab_t ang, ctab_t uci, ctab_t uch, cext_t ext,
                                             double2* __restrict__ series_in, double2* __restrict__ series_mid,
@@ -469,7 +470,7 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
         p = ld(u_in, o);
         q = ld(u_in, o + A.plane);
     };
-    auto put = [&](size_t o, cd v) { st(u_out, o, v); };
+    auto put = [&](size_t o, cd v) { st_state<KEEP>(u_out, o, v); };
 
     // ---- prologue: step A completes rows j0-1 (if j0 > 0) and j0; step B
     // takes them as its halo row and its first row ------------------------
@@ -641,7 +642,7 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
 constexpr size_t kRadSliceBytes = 2 * kNumRad * kWave * sizeof(double);
 
 // SRC: the inhomogeneous variant (source profile src_i, src_h; time factors in A.sf).
-template <bool KERR, bool SRC>
+template <bool KERR, bool SRC, int KEEP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4)))
     lw_step2_kernel(const double2* __restrict__ u_in, double2* __restrict__ u_out, const double* __restrict__ rad,
                     const double* __restrict__ ang, const double* __restrict__ uci, const double* __restrict__ uch,
@@ -655,7 +656,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
     const int chunk = tile / A.n_strips;
     extern __shared__ double rad_s[];
     if (chunk >= A.n_chunks) return;  // tiles beyond the last
-    sweep_tile2<KERR, SRC>((gin_t)u_in, (gout_t)u_out, (ctab_t)rad, (ctab_t)ang, (ctab_t)uci, (ctab_t)uch,
+    sweep_tile2<KERR, SRC, KEEP>((gin_t)u_in, (gout_t)u_out, (ctab_t)rad, (ctab_t)ang, (ctab_t)uci, (ctab_t)uch,
                            (cext_t)ext, series_in, series_mid, (gout_t)u_mid,
                            (lds_t)(rad_s + (threadIdx.x / kWave) * 2 * kNumRad * kWave), A, strip, chunk, lane,
                            (gin_t)src_i, (gin_t)src_h);
@@ -666,7 +667,7 @@ __global__ void zero_ints_kernel(int* p, int n) {
     if (i < n) p[i] = 0;
 }
 
-template <bool KERR, bool SRC>
+template <bool KERR, bool SRC, int KEEP>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_WAVES_PER_SIMD, 8)))
     lw_step_kernel(const double2* __restrict__ u_in, double2* __restrict__ u_out, const double* __restrict__ rad,
                    const double* __restrict__ ang, const double* __restrict__ uci, const double* __restrict__ uch,
@@ -692,7 +693,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_W
     const int chunk = tile / A.n_strips;
     if (chunk >= A.n_chunks) return;  // tiles beyond the last
 #endif
-    sweep_tile<KERR, SRC>((gin_t)u_in, (gout_t)u_out, (ctab_t)rad, (ctab_t)ang, (ctab_t)uci, (ctab_t)uch,
+    sweep_tile<KERR, SRC, KEEP>((gin_t)u_in, (gout_t)u_out, (ctab_t)rad, (ctab_t)ang, (ctab_t)uci, (ctab_t)uch,
                           (cext_t)ext, series, (gout_t)win, A, strip, chunk, lane, (gin_t)src_i, (gin_t)src_h);
 }
 
@@ -702,6 +703,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_W
 // same shape (62 columns x `rows` rows, ragged only at a member's edges),
 // so the static stride balances uneven members.  `parity` selects which of
 // each member's two state buffers is the input.
+template <int KEEP>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_WAVES_PER_SIMD, 8)))
     lw_batch_kernel(const BatchMember* __restrict__ members, int n_members, int total_tiles, int parity) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -721,13 +723,14 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_W
         const int local = tile - M.tile_begin;
         const int strip = local % M.k.n_strips;
         const int chunk = local / M.k.n_strips;
-        sweep_tile<true>((gin_t)M.u[parity], (gout_t)M.u[1 - parity], (ctab_t)M.rad, (ctab_t)M.ang, nullptr,
+        sweep_tile<true, false, KEEP>((gin_t)M.u[parity], (gout_t)M.u[1 - parity], (ctab_t)M.rad, (ctab_t)M.ang, nullptr,
                          nullptr, nullptr, nullptr, nullptr, M.k, strip, chunk, lane);
     }
 }
 
 // The batched launch of the two-step pass: as lw_batch_kernel, over the
 // members' two-step tiles.
+template <int KEEP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4)))
     lw_batch2_kernel(const BatchMember* __restrict__ members, int n_members, int total_tiles, int parity) {
     extern __shared__ double rad_s[];
@@ -751,7 +754,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
         k.n_strips = M.n_strips2;
         const int strip = local % k.n_strips;
         const int chunk = local / k.n_strips;
-        sweep_tile2<true>((gin_t)M.u[parity], (gout_t)M.u[1 - parity], (ctab_t)M.rad, (ctab_t)M.ang, nullptr,
+        sweep_tile2<true, false, KEEP>((gin_t)M.u[parity], (gout_t)M.u[1 - parity], (ctab_t)M.rad, (ctab_t)M.ang, nullptr,
                           nullptr, nullptr, nullptr, nullptr, nullptr, rs, k, strip, chunk, lane);
     }
 }
@@ -881,8 +884,12 @@ hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStr
     const int nb = (a.k.n_strips * a.k.n_chunks + waves_per_block - 1) / waves_per_block;
     const dim3 block(kWave * waves_per_block), grid(nb);
     const bool src = a.src_i != nullptr;
-    auto kern = kerr ? (src ? lw_step_kernel<true, true> : lw_step_kernel<true, false>)
-                     : (src ? lw_step_kernel<false, true> : lw_step_kernel<false, false>);
+    const int keep = a.k.keep ? 1 : 0;
+    auto pick = [&](auto k0, auto k1) { return keep ? k1 : k0; };
+    auto kern = kerr ? (src ? pick(lw_step_kernel<true, true, 0>, lw_step_kernel<true, true, 1>)
+                            : pick(lw_step_kernel<true, false, 0>, lw_step_kernel<true, false, 1>))
+                     : (src ? pick(lw_step_kernel<false, true, 0>, lw_step_kernel<false, true, 1>)
+                            : pick(lw_step_kernel<false, false, 0>, lw_step_kernel<false, false, 1>));
     hipLaunchKernelGGL(kern, grid, block, 0, s, a.u_in, a.u_out, a.rad, a.ang, a.uci, a.uch,
                        a.ext, a.series, a.win, a.src_i, a.src_h, a.k);
     return hipGetLastError();
@@ -892,8 +899,12 @@ hipError_t launch_step2(const StepArgs& a, bool kerr, int waves_per_block, hipSt
     const int nb = (a.k.n_strips * a.k.n_chunks + waves_per_block - 1) / waves_per_block;
     const dim3 block(kWave * waves_per_block), grid(nb);
     const bool src = a.src_i != nullptr;
-    auto kern = kerr ? (src ? lw_step2_kernel<true, true> : lw_step2_kernel<true, false>)
-                     : (src ? lw_step2_kernel<false, true> : lw_step2_kernel<false, false>);
+    const int keep = a.k.keep ? 1 : 0;
+    auto pick = [&](auto k0, auto k1) { return keep ? k1 : k0; };
+    auto kern = kerr ? (src ? pick(lw_step2_kernel<true, true, 0>, lw_step2_kernel<true, true, 1>)
+                            : pick(lw_step2_kernel<true, false, 0>, lw_step2_kernel<true, false, 1>))
+                     : (src ? pick(lw_step2_kernel<false, true, 0>, lw_step2_kernel<false, true, 1>)
+                            : pick(lw_step2_kernel<false, false, 0>, lw_step2_kernel<false, false, 1>));
     hipLaunchKernelGGL(kern, grid, block, kerr ? waves_per_block * kRadSliceBytes : 0, s, a.u_in, a.u_out, a.rad, a.ang,
                        a.uci, a.uch, a.ext, a.series, a.series_mid, a.win, a.src_i, a.src_h, a.k);
     return hipGetLastError();
@@ -905,14 +916,14 @@ hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
 }
 
 hipError_t launch_batch(const BatchMember* members, int n_members, int total_tiles, int parity, int n_blocks,
-                        int waves_per_block, bool two, hipStream_t s) {
+                        int waves_per_block, bool two, bool keep, hipStream_t s) {
     if (two) {
         const int w = waves_per_block < 4 ? waves_per_block : 4;
-        hipLaunchKernelGGL(lw_batch2_kernel, dim3(n_blocks), dim3(kWave * w), w * kRadSliceBytes, s, members,
-                           n_members, total_tiles, parity);
+        hipLaunchKernelGGL(keep ? lw_batch2_kernel<1> : lw_batch2_kernel<0>, dim3(n_blocks), dim3(kWave * w),
+                           w * kRadSliceBytes, s, members, n_members, total_tiles, parity);
     } else {
-        hipLaunchKernelGGL(lw_batch_kernel, dim3(n_blocks), dim3(kWave * waves_per_block), 0, s, members, n_members,
-                           total_tiles, parity);
+        hipLaunchKernelGGL(keep ? lw_batch_kernel<1> : lw_batch_kernel<0>, dim3(n_blocks),
+                           dim3(kWave * waves_per_block), 0, s, members, n_members, total_tiles, parity);
     }
     return hipGetLastError();
 }

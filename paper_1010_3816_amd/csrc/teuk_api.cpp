@@ -213,6 +213,7 @@ struct teuk_grid {
     int adj_rows = 32, adj_wpb = 4, adj_chunks = 0, adj_strips = 0;  // spin-gradient and one-step kernels
     int adj2_rows = 32, adj2_chunks = 0;                              // two-step cotangent kernel
     int tan_rows = 32, tan_chunks = 0;                                // step-with-tangent kernel
+    int cache_policy = TEUK_CACHE_AUTO;                               // teuk_set_cache_policy
 
     double2* u(int k) const { return reinterpret_cast<double2*>(ws + L.off_u[k]); }
     template <class T>
@@ -235,6 +236,17 @@ bool fused_extraction_ok(const teuk_grid* g, int strip_cols = kStripCols) {
 void update_fusion(teuk_grid* g) {
     g->fused_ext = fused_extraction_ok(g);
     g->fused_ext2 = fused_extraction_ok(g, kStripCols2);
+}
+
+// Two states (a pass's input and output) up to this size stay in the
+// last-level cache (256 MB on MI355X) with room to spare for the tables.
+constexpr size_t kKeepStatesBytes = (size_t)192 << 20;
+
+// Whether the next state is written with cache-keeping stores.
+bool keeps_states(const teuk_grid* g) {
+    if (g->cache_policy == TEUK_CACHE_KEEP) return true;
+    if (g->cache_policy == TEUK_CACHE_STREAM) return false;
+    return 2 * g->L.state <= kKeepStatesBytes;
 }
 
 StepArgs step_args(const teuk_grid* g) {
@@ -262,6 +274,7 @@ StepArgs step_args(const teuk_grid* g) {
     }
     a.ext = g->at<ExtPoint>(g->L.off_ext);
     k.n_ext = g->fused_ext ? g->p.n_extract : 0;
+    k.keep = keeps_states(g) ? 1 : 0;
     return a;
 }
 
@@ -855,6 +868,21 @@ int teuk_get_steps_per_pass(const teuk_grid* g, int32_t* steps_per_pass) {
     return TEUK_OK;
 }
 
+int teuk_set_cache_policy(teuk_grid* g, int32_t policy) {
+    if (int rc = check_grid(g)) return rc;
+    if (policy != TEUK_CACHE_AUTO && policy != TEUK_CACHE_KEEP && policy != TEUK_CACHE_STREAM)
+        return fail(TEUK_E_INVALID_ARG, "cache policy %d not in {0, 1, 2}", policy);
+    g->cache_policy = policy;
+    return TEUK_OK;
+}
+
+int teuk_get_cache_policy(const teuk_grid* g, int32_t* policy, int32_t* keeps) {
+    if (int rc = check_grid(g)) return rc;
+    if (policy) *policy = g->cache_policy;
+    if (keeps) *keeps = keeps_states(g) ? 1 : 0;
+    return TEUK_OK;
+}
+
 int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per_block) {
     if (int rc = check_grid(g)) return rc;
     if (rows_per_tile) *rows_per_tile = g->rows;
@@ -962,6 +990,7 @@ AdjArgs adjoint_args(const teuk_grid* g) {
     a.k.n_strips = g->adj_strips;
     a.k.n_chunks = g->adj_chunks;
     a.k.zero = 0;
+    a.k.keep = keeps_states(g) ? 1 : 0;
     a.k.plane = (int64_t)nth * g->L.pitch;
     a.k.dt = g->p.dt;
     a.k.hdt = 0.5 * g->p.dt;
@@ -998,15 +1027,20 @@ int teuk_step_n_tangent(teuk_grid* g, int64_t n, void* d_window) {
     return TEUK_OK;
 }
 
-int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi, const void* d_dL_dseries,
-                        const void* d_window, int32_t flags, double* h_dL_da_accum) {
+namespace {
+
+// The reverse of a segment; dL/da goes to the host (h_acc: reduced,
+// copied back, synchronised) or to a device accumulator (d_acc: added on the
+// stream, asynchronous), or nowhere (both NULL: cotangents only).
+int adjoint_impl(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi, const void* d_dL_dseries,
+                 const void* d_window, int32_t flags, double* h_dL_da_accum, double* d_dL_da_accum) {
     if (int rc = check_grid(g)) return rc;
     if (!g->aws) return fail(TEUK_E_STATE, "teuk_enable_adjoint has not been called");
     if (n < 0) return fail(TEUK_E_INVALID_ARG, "n=%lld < 0", (long long)n);
     if (!d_lam_phi || !d_lam_pi) return fail(TEUK_E_INVALID_ARG, "cotangent pointers are NULL");
     // without a dL/da accumulator only the cotangents are computed, and they
     // do not depend on the forward states (the step is linear)
-    const bool spin = h_dL_da_accum != nullptr;
+    const bool spin = h_dL_da_accum != nullptr || d_dL_da_accum != nullptr;
     if (n > 0 && spin && !d_window) return fail(TEUK_E_INVALID_ARG, "window is NULL");
     if (flags & ~(TEUK_ADJ_PROJECT_INITIAL | TEUK_ADJ_TANGENT_WINDOW))
         return fail(TEUK_E_INVALID_ARG, "unknown flags 0x%x", flags);
@@ -1029,7 +1063,7 @@ int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi
     HIP_TRY(launch_import(static_cast<const double2*>(d_lam_pi), lam(c), 1, nr, nth, P, s));
     if (spin) {
         HIP_TRY(hipMemsetAsync(slots, 0, (size_t)nslots * sizeof(double), s));
-        HIP_TRY(hipMemsetAsync(sum, 0, sizeof(double), s));
+        if (!d_dL_da_accum) HIP_TRY(hipMemsetAsync(sum, 0, sizeof(double), s));
     }
     // the sample of the segment's last state
     if (gs && n > 0) HIP_TRY(launch_extract_adjoint(lam(c), P, ext, ne, gs + (n - 1) * ne, s));
@@ -1073,12 +1107,29 @@ int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi
     HIP_TRY(launch_export(lam(c), static_cast<double2*>(d_lam_phi), 0, nr, nth, P, s));
     HIP_TRY(launch_export(lam(c), static_cast<double2*>(d_lam_pi), 1, nr, nth, P, s));
     if (!spin) return TEUK_OK;  // asynchronous
+    if (d_dL_da_accum) {         // asynchronous: added on the stream, in call order
+        HIP_TRY(launch_reduce_slots(slots, nslots, d_dL_da_accum, s));
+        return TEUK_OK;
+    }
     HIP_TRY(launch_reduce_slots(slots, nslots, sum, s));
     double h = 0.0;
     HIP_TRY(hipMemcpyAsync(&h, sum, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     *h_dL_da_accum += h;
     return TEUK_OK;
+}
+
+}  // namespace
+
+int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi, const void* d_dL_dseries,
+                        const void* d_window, int32_t flags, double* h_dL_da_accum) {
+    return adjoint_impl(g, n, d_lam_phi, d_lam_pi, d_dL_dseries, d_window, flags, h_dL_da_accum, nullptr);
+}
+
+int teuk_adjoint_step_n_async(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi, const void* d_dL_dseries,
+                              const void* d_window, int32_t flags, double* d_dL_da_accum) {
+    if (!d_dL_da_accum) return fail(TEUK_E_INVALID_ARG, "the dL/da accumulator is NULL");
+    return adjoint_impl(g, n, d_lam_phi, d_lam_pi, d_dL_dseries, d_window, flags, nullptr, d_dL_da_accum);
 }
 
 /* ---- batched evolutions ------------------------------------------------ */
@@ -1096,6 +1147,7 @@ struct teuk_batch {
     int total_tiles = 0, total_tiles2 = 0;  // single-step and two-step work lists
     int steps_per_pass = 2;
     int parity = 0;                 // which state buffer of every member is the input
+    bool keep = false;              // next states with cache-keeping stores (set by batch_upload)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;  // two launches (parity 0 then 1)
     hipStream_t cap = nullptr;      // private stream the graph is captured on
@@ -1131,6 +1183,11 @@ void batch_drop_graph(teuk_batch* b) {
 int batch_upload(teuk_batch* b) {
     std::vector<BatchMember> d(b->members.size());
     int tiles = 0, tiles2 = 0;
+    // one launch advances every member: their states share the cache
+    size_t states = 0;
+    for (const teuk_grid* g : b->members) states += 2 * g->L.state;
+    const int keep = states <= kKeepStatesBytes ? 1 : 0;
+    b->keep = keep != 0;
     for (size_t k = 0; k < b->members.size(); ++k) {
         teuk_grid* g = b->members[k];
         g->rows = std::min<int>(b->rows, (int)g->p.ntheta);
@@ -1142,6 +1199,7 @@ int batch_upload(teuk_batch* b) {
         M.ang = a.ang;
         M.k = a.k;
         M.k.n_ext = 0;
+        M.k.keep = keep;
         M.tile_begin = tiles;
         tiles += a.k.n_strips * a.k.n_chunks;
         M.n_strips2 = (a.k.nr + kStripCols2 - 1) / kStripCols2;
@@ -1159,7 +1217,7 @@ int batch_upload(teuk_batch* b) {
 int batch_launch(teuk_batch* b, int parity, bool two, hipStream_t s) {
     const hipError_t e =
         launch_batch(reinterpret_cast<const BatchMember*>(b->ws + b->desc_off), (int)b->members.size(),
-                     two ? b->total_tiles2 : b->total_tiles, parity, b->n_blocks, b->wpb, two, s);
+                     two ? b->total_tiles2 : b->total_tiles, parity, b->n_blocks, b->wpb, two, b->keep, s);
     return e == hipSuccess ? TEUK_OK : fail(TEUK_E_HIP, "batched step launch failed: %s", hipGetErrorString(e));
 }
 

@@ -15,7 +15,8 @@ def rel_err(gpu, ref):
     return float(np.max(np.abs(np.asarray(gpu) - ref)) / (scale if scale > 0 else 1.0))
 
 
-def run_gpu(binding, w, phi0, pi0, n, tile=None, coef=None, mode=None, steps_per_pass=None, check_every=None):
+def run_gpu(binding, w, phi0, pi0, n, tile=None, coef=None, mode=None, steps_per_pass=None, check_every=None,
+            cache_policy=None):
     import torch
 
     g = binding.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"],
@@ -29,6 +30,8 @@ def run_gpu(binding, w, phi0, pi0, n, tile=None, coef=None, mode=None, steps_per
         g.set_steps_per_pass(steps_per_pass)
     if check_every is not None:
         g.set_finite_check(check_every)
+    if cache_policy is not None:
+        g.set_cache_policy(cache_policy)
     g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
     ser = g.step(n)
     phi, pi = g.state()

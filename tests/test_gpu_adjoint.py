@@ -135,6 +135,80 @@ def test_tangent_segment_parity(gpu, n, spp, n_ext):
     assert abs(dlda - out[False][2]) <= 1e-12 * abs(dlda)
 
 
+@pytest.mark.parametrize("tangent", [False, True])
+def test_device_accumulated_spin_gradient(gpu, tangent):
+    """teuk_adjoint_step_n_async adds each segment's dL/da to a device
+    accumulator in call order without synchronising: two segments in a row,
+    from a nonzero start, equal bit for bit the host-accumulated route, and the
+    cotangents are the same."""
+    n = 7
+    w = small_case(0.6, -2, 2, 140, 22)
+    phi0, pi0 = inputs.random_state(140, 22, seed=81)
+    lam0 = inputs.random_state(140, 22, seed=82)
+    rng = np.random.default_rng(83)
+    ne = len(w["extract_rstar"])
+    gser = rng.standard_normal((n, ne)) + 1j * rng.standard_normal((n, ne))
+    start = 0.3125
+    res = {}
+    for dev in (False, True):
+        g = _gpu_grid(gpu, w)
+        g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
+        wins = [g.new_window(n), g.new_window(n)]
+        for win in wins:
+            if tangent:
+                g.step_tangent(n, win)
+            else:
+                g.step_store(n, win, series=False)
+        lp = torch.from_numpy(lam0[0].copy()).cuda()
+        lq = torch.from_numpy(lam0[1].copy()).cuda()
+        gs = torch.from_numpy(gser).cuda()
+        if dev:
+            acc = torch.full((), start, dtype=torch.float64, device="cuda")
+            for win in reversed(wins):
+                assert g.adjoint(n, lp, lq, gs, win, tangent=tangent, accum=acc) is None
+            total = float(acc.cpu())
+        else:
+            total = start
+            for win in reversed(wins):
+                total += g.adjoint(n, lp, lq, gs, win, tangent=tangent)
+        torch.cuda.synchronize()
+        res[dev] = (lp.cpu().numpy(), lq.cpu().numpy(), total)
+        if dev:
+            with pytest.raises(ValueError):
+                g.adjoint(n, lp, lq, gs, wins[0], tangent=tangent, accum=torch.zeros(1, dtype=torch.float32,
+                                                                                    device="cuda"))
+        g.close()
+    assert res[True][2] == res[False][2]
+    assert np.array_equal(res[True][0], res[False][0]) and np.array_equal(res[True][1], res[False][1])
+
+
+def test_cache_policies_bit_identical_adjoint(gpu):
+    """The tangent step (its next state) and the adjoint (its cotangents)
+    with cache-keeping and with streaming stores: same window, cotangents
+    and dL/da, bit for bit."""
+    n = 6
+    w = small_case(0.8, -2, 1, 170, 26)
+    phi0, pi0 = inputs.random_state(170, 26, seed=91)
+    lam0 = inputs.random_state(170, 26, seed=92)
+    gser = np.random.default_rng(93).standard_normal((n, 1)) + 0j
+    out = []
+    for policy in (gpu.TEUK_CACHE_KEEP, gpu.TEUK_CACHE_STREAM):
+        g = _gpu_grid(gpu, w)
+        g.set_cache_policy(policy)
+        g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
+        win = g.new_window(n)
+        g.step_tangent(n, win)
+        lp = torch.from_numpy(lam0[0].copy()).cuda()
+        lq = torch.from_numpy(lam0[1].copy()).cuda()
+        dlda = g.adjoint(n, lp, lq, torch.from_numpy(gser).cuda(), win, tangent=True)
+        res = [t.cpu().numpy() for t in (*g.state(), *g.window_slot(win, n - 1), lp, lq)]
+        out.append((res, dlda))
+        g.close()
+    for x, y in zip(out[0][0], out[1][0]):
+        assert np.array_equal(x, y)
+    assert out[0][1] == out[1][1]
+
+
 def test_dot_product_identity_gpu(gpu):
     """Re <A v, w> = Re <v, A^H w> with A the GPU step and A^H the GPU adjoint."""
     w = small_case(0.8, -2, 1, 200, 33, ext=())

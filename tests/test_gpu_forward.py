@@ -208,6 +208,28 @@ def test_two_step_passes_bit_identical(gpu, a, s, m, nr, nth, n, tile):
     assert rel_err(two[2], o[2]) <= TOL
 
 
+@pytest.mark.parametrize("spp", [1, 2])
+def test_cache_policies_bit_identical(gpu, spp):
+    """Cache-keeping and streaming stores of the next state give the same
+    results bit for bit, and the default policy keeps the states of a grid
+    whose two states fit in 192 MiB and streams those of a larger one."""
+    w = small_case(0.7, -2, 2, 190, 30, ext=((20.0, math.pi / 2),))
+    phi0, pi0 = inputs.random_state(190, 30, seed=97)
+    keep = run_gpu(gpu, w, phi0, pi0, 9, steps_per_pass=spp, cache_policy=gpu.TEUK_CACHE_KEEP)
+    stream = run_gpu(gpu, w, phi0, pi0, 9, steps_per_pass=spp, cache_policy=gpu.TEUK_CACHE_STREAM)
+    auto = run_gpu(gpu, w, phi0, pi0, 9, steps_per_pass=spp)
+    for k in range(3):
+        assert np.array_equal(keep[k], stream[k]) and np.array_equal(auto[k], keep[k]), k
+    for (nr, nth), kept in (((6400, 256), True), ((6400, 512), False)):
+        g = gpu.TeukGrid(0.5, -2, 2, nr, nth, -100.0, 600.0, 0.01)
+        assert g.cache_policy() == (gpu.TEUK_CACHE_AUTO, kept)
+        g.set_cache_policy(gpu.TEUK_CACHE_KEEP)
+        assert g.cache_policy() == (gpu.TEUK_CACHE_KEEP, True)
+        with pytest.raises(RuntimeError):
+            g.set_cache_policy(3)
+        g.close()
+
+
 def test_two_step_extraction_fallback(gpu):
     """Two extraction points in one two-step tile: the pairs of steps fall
     back to single steps with the separate extraction pass."""
