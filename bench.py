@@ -265,10 +265,17 @@ def workload_leg(name):
 
 
 def adjoint_leg(n_steps=None, checkpoint_every=None):
-    """Forward (with checkpoints) and backward (recompute + adjoint) of the
-    waveform misfit on the adjoint workload: 6400 x 256, a = 0.7, 8000 steps,
-    a checkpoint every 100 steps, target = series of the perturbed run
-    (a + 0.01, centre + 0.5).  ratio = backward / forward wall time."""
+    """Loss and gradients of the waveform misfit on the adjoint workload:
+    6400 x 256, a = 0.7, 8000 steps, target = series of the perturbed run
+    (a + 0.01, centre + 0.5), gradients with respect to the initial data and
+    the spin.  Routes for the spin: carried forward (the default: the
+    forward pass advances du/da too, the backward is one cotangent sweep),
+    and the checkpointed adjoint (a checkpoint every 100 steps; recompute of
+    the step tangents or of the states).  plain_forward_ms: the same loss
+    without gradients.  ratio = (forward + backward - plain forward) /
+    plain forward, the gradient's cost beyond the forward pass in forward
+    passes (for the checkpointed route, whose forward is the plain one plus
+    checkpoint copies, about backward / forward)."""
     import torch
 
     from paper_1010_3816_amd import inputs
@@ -288,12 +295,13 @@ def adjoint_leg(n_steps=None, checkpoint_every=None):
     P = torch.from_numpy(p0).cuda().requires_grad_(True)
     Q = torch.from_numpy(q0).cuda().requires_grad_(True)
     A = torch.tensor(w["a"], dtype=torch.float64, device="cuda", requires_grad=True)
-    def timed(tangent):
+
+    def timed(a, **kw):
         times = []
         for _ in range(2):  # the first pass warms up
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            ser = evolve(P, Q, A, cfg, n_steps, checkpoint_every, tangent=tangent)
+            ser = evolve(P, Q, a, cfg, n_steps, checkpoint_every, **kw)
             L = ((ser - target).abs() ** 2).sum()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -301,35 +309,37 @@ def adjoint_leg(n_steps=None, checkpoint_every=None):
             torch.cuda.synchronize()
             t2 = time.perf_counter()
             times.append((t1 - t0, t2 - t1))
-            dlda = float(A.grad)
+            dlda = float(A.grad) if a is A else None
             P.grad = Q.grad = A.grad = None
-        return times[-1], L, dlda
+        return times[-1][0] * 1e3, times[-1][1] * 1e3, float(L.detach()), dlda
 
-    (fwd_s, bwd_s), _, dlda_s = timed(False)
-    (fwd, bwd), L, dlda = timed(True)
-    # the same loss, gradients with respect to the initial data only: no
-    # checkpoints, one cotangent sweep (nothing to recompute)
-    A0 = A.detach()
-    times0 = []
+    # the plain forward: the same loss with no gradient at all
+    plain = []
     for _ in range(2):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ser = evolve(P, Q, A0, cfg, n_steps, checkpoint_every)
-        L0 = ((ser - target).abs() ** 2).sum()
+        with torch.no_grad():
+            L = ((evolve(P.detach(), Q.detach(), A.detach(), cfg, n_steps, checkpoint_every) - target).abs() ** 2).sum()
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        L0.backward()
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        times0.append((t1 - t0, t2 - t1))
-        P.grad = Q.grad = None
-    fwd0, bwd0 = times0[-1]
+        plain.append((time.perf_counter() - t0) * 1e3)
+    plain_ms = plain[-1]
+
+    def route(fwd, bwd, loss, dlda, name):
+        return {"route": name, "forward_ms": fwd, "backward_ms": bwd, "backward_over_forward": bwd / fwd,
+                "ratio": (fwd + bwd - plain_ms) / plain_ms, "loss": loss, "dL_da": dlda}
+
+    fw = route(*timed(A, spin="forward"), "spin derivative carried forward")
+    rt = route(*timed(A, spin="reverse", tangent=True), "checkpointed adjoint, stored step tangents")
+    rs = route(*timed(A, spin="reverse", tangent=False), "checkpointed adjoint, stored states")
+    # gradients with respect to the initial data only: one cotangent sweep
+    f0, b0, _, _ = timed(A.detach())
     return {"workload": "adjoint_a0.7_6400x256", "steps": n_steps, "checkpoint_every": checkpoint_every,
-            "extract": [w["extract_rstar"][0], w["extract_theta"][0]], "loss": float(L.detach()), "dL_da": dlda,
-            "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3, "ratio": bwd / fwd, "route": "stored step tangents",
-            "state_route": {"forward_ms": fwd_s * 1e3, "backward_ms": bwd_s * 1e3, "ratio": bwd_s / fwd_s,
-                            "dL_da": dlda_s},
-            "initial_data_only": {"forward_ms": fwd0 * 1e3, "backward_ms": bwd0 * 1e3, "ratio": bwd0 / fwd0}}
+            "extract": [w["extract_rstar"][0], w["extract_theta"][0]], "loss": fw["loss"], "dL_da": fw["dL_da"],
+            "plain_forward_ms": plain_ms, "forward_ms": fw["forward_ms"], "backward_ms": fw["backward_ms"],
+            "ratio": fw["ratio"],
+            "ratio_definition": "(forward + backward - plain forward) / plain forward, spin carried forward",
+            "route": fw["route"], "reverse_tangent_route": rt, "reverse_state_route": rs,
+            "initial_data_only": {"forward_ms": f0, "backward_ms": b0, "backward_over_forward": b0 / f0}}
 
 
 def main():

@@ -346,6 +346,44 @@ int teuk_adjoint_step_n(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi
 int teuk_adjoint_step_n_async(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_lam_pi, const void* d_dL_dseries,
                               const void* d_window, int32_t flags, double* d_dL_da_accum);
 
+/* ---- Forward-mode spin derivative ---------------------------------------
+ * For the one scalar parameter a, the derivative of the evolution can run
+ * forward beside it: v = du/da obeys the tangent-linear step of
+ * Eqs. (lw1)-(lw2),
+ *     v^{k+1} = A v^k + (dA/da) u^k     (T_k of teuk_step_n_tangent),
+ * and the samples of v are ds/da, so for a loss of the series
+ * dL/da = sum_k Re <dL/ds_k, ds_k/da> with no reverse sweep and no stored
+ * states.  teuk_spin_tangent_workspace_bytes: the bytes of the two buffers
+ * of v.  teuk_enable_spin_tangent: needs teuk_enable_adjoint first (it holds
+ * the a-derivative tables; TEUK_E_STATE otherwise); d_workspace as the grid
+ * workspace (TEUK_E_WORKSPACE if too small or misaligned); sets v = 0.
+ * teuk_set_spin_tangent: v from caller arrays (complex128 [ntheta][nr],
+ * radial boundary columns ignored, as teuk_set_initial_data), or v = 0 for
+ * two NULL pointers; teuk_set_initial_data does not touch v.
+ * teuk_get_spin_tangent: the current v into caller arrays. */
+size_t teuk_spin_tangent_workspace_bytes(const teuk_grid* g);
+int teuk_enable_spin_tangent(teuk_grid* g, void* d_workspace, size_t bytes);
+int teuk_set_spin_tangent(teuk_grid* g, const void* d_vphi, const void* d_vpi);
+int teuk_get_spin_tangent(teuk_grid* g, void* d_vphi, void* d_vpi);
+
+/* n >= 0 steps of u and v together, one kernel pass per step (the tiles of
+ * teuk_set_adjoint_tile).  d_series and d_tseries (complex128
+ * [n][n_extract], or NULL): the samples of u and of v after each step, as
+ * teuk_step_n writes its series.  The states u equal those of teuk_step_n
+ * bit for bit; teuk_set_finite_check applies (to u).  Asynchronous unless
+ * the finite check is on.  TEUK_E_STATE before teuk_enable_spin_tangent. */
+int teuk_step_n_spin_tangent(teuk_grid* g, int64_t n, void* d_series, void* d_tseries);
+
+/* dL/da from the samples of v: adds sum over the n rows and n_extract
+ * points of Re(conj(g) t), with g = d_dL_dseries (the gradient of L with
+ * respect to the series of u, complex128 [n][n_extract], PyTorch's complex
+ * convention) and t = d_tseries (the series of v of the same call), to the
+ * device double *d_dL_da_accum, on the grid's stream without synchronising
+ * (one workgroup, a fixed summation order).  TEUK_E_INVALID_ARG for NULL
+ * pointers (the series may be NULL when n * n_extract is 0). */
+int teuk_spin_gradient(teuk_grid* g, int64_t n, const void* d_dL_dseries, const void* d_tseries,
+                       double* d_dL_da_accum);
+
 /* ---- Batched evolutions ------------------------------------------------
  * Many independent grids (each its own a, s, m, nr, ntheta, r* range, dt
  * and extraction points; TEUK_COEF_KERR) advanced together: one persistent

@@ -287,6 +287,29 @@ class OracleGrid:
         self._lib.orc_tangent_a(self._h, _ptr(phi), _ptr(pi), _ptr(tp), _ptr(tq))
         return tp, tq
 
+    def evolve_spin_tangent(self, phi, pi, vphi, vpi, n, ext_rstar=(), ext_theta=()):
+        """n steps of the state u and of its spin derivative v = du/da by the
+        tangent-linear step of Eqs. (lw1)-(lw2): v <- A v + (dA/da) u, with u
+        the state before the step, then u <- A u.  Returns
+        (phi, pi, vphi, vpi, series, tseries): the samples of Phi and of its
+        a-derivative after each step, shape (n, n_ext).  A composition of
+        step, tangent_a and extract, step by step."""
+        p, q = _c128(phi, self.shape).copy(), _c128(pi, self.shape).copy()
+        vp, vq = _c128(vphi, self.shape).copy(), _c128(vpi, self.shape).copy()
+        er = np.ascontiguousarray(ext_rstar, dtype=np.float64).ravel()
+        et = np.ascontiguousarray(ext_theta, dtype=np.float64).ravel()
+        series = np.zeros((int(n), er.size), dtype=np.complex128)
+        tseries = np.zeros_like(series)
+        for k in range(int(n)):
+            tp, tq = self.tangent_a(p, q)
+            vp, vq = self.step(vp, vq, 1)
+            vp, vq = vp + tp, vq + tq
+            p, q = self.step(p, q, 1)
+            for e in range(er.size):
+                series[k, e] = self.extract(p, er[e], et[e])
+                tseries[k, e] = self.extract(vp, er[e], et[e])
+        return p, q, vp, vq, series, tseries
+
     def extract_adjoint(self, lam_phi, rstar, theta, gval):
         lp = _c128(lam_phi, self.shape).copy()
         g = np.array([gval], dtype=np.complex128)

@@ -1,8 +1,16 @@
 """Differentiable evolution: extraction series as a function of the initial
-data (Phi0, Pi0) and of the spin a, with checkpoint/recompute.
+data (Phi0, Pi0) and of the spin a.
 
-Forward: the state is copied to a checkpoint every K steps while the
-library advances the grid (teuk_step_n).  Backward, for each segment from the
+The spin is one scalar, so its derivative can also run forward: with
+spin="forward" (the default) the library advances v = du/da beside the
+state by the tangent-linear step (teuk_step_n_spin_tangent) and keeps the
+samples of v, ds/da; the backward forms dL/da = sum Re <dL/ds, ds/da>
+(teuk_spin_gradient), and the initial-data gradients come from one adjoint
+sweep over all steps without forward states.  No checkpoints, no recompute.
+
+With spin="reverse", checkpoint/recompute.  Forward: the state is copied
+to a checkpoint every K steps while the library advances the grid
+(teuk_step_n).  Backward, for each segment from the
 last to the first: restore its checkpoint, recompute its K steps while the
 library keeps, for each step k, its derivative with respect to the spin at
 fixed input, T_k = (dA/da) u^k, in a window (teuk_step_n_tangent), and run the
@@ -102,20 +110,24 @@ def _reverse_overlapped(grid, a, cfg, ckpts, segs, K, gseries, lam_phi, lam_pi, 
 
 
 class TeukEvolve(torch.autograd.Function):
-    """series = TeukEvolve.apply(phi0, pi0, a, cfg, n_steps, checkpoint_every, overlap, tangent)
+    """series = TeukEvolve.apply(phi0, pi0, a, cfg, n_steps, checkpoint_every, overlap, tangent, spin)
 
     phi0, pi0: complex128 (ntheta, nr) on the GPU; a: 0-dim float64 tensor;
     cfg: dict with s, m, nr, ntheta, rstar_min, rstar_max, dt, extract_rstar,
     extract_theta.  Returns the extraction series, complex128 (n_steps, n_extract).
     overlap: run the recompute of the next segment beside the adjoint of the
     current one (same results).  tangent: the recompute stores the step
-    tangents (default) or the states (the same gradient, by another route)."""
+    tangents (default) or the states (the same gradient, by another route).
+    spin: "forward" (the spin derivative carried forward; checkpoint_every,
+    overlap and tangent unused) or "reverse" (checkpointed adjoint)."""
 
     @staticmethod
-    def forward(ctx, phi0, pi0, a, cfg, n_steps, checkpoint_every, overlap=True, tangent=True):
+    def forward(ctx, phi0, pi0, a, cfg, n_steps, checkpoint_every, overlap=True, tangent=True, spin="forward"):
         n, K = int(n_steps), int(checkpoint_every)
         if n < 1 or K < 1:
             raise ValueError("need n_steps >= 1 and checkpoint_every >= 1")
+        if spin not in ("forward", "reverse"):
+            raise ValueError("spin must be 'forward' or 'reverse'")
         grid = _make_grid(float(a), cfg)
         if grid.n_extract < 1:
             raise ValueError("the loss is a function of the extraction series: give extraction points")
@@ -123,7 +135,12 @@ class TeukEvolve(torch.autograd.Function):
         series = torch.empty((n, grid.n_extract), dtype=torch.complex128, device=grid.device)
         need_a = ctx.needs_input_grad[2]
         ckpts = []
-        if need_a:
+        ctx.tseries = None
+        if need_a and spin == "forward":
+            grid.set_spin_tangent()  # v = du/da = 0: the initial data do not depend on a
+            ctx.tseries = torch.empty_like(series)
+            binding.teuk_step_n_spin_tangent(grid.handle, n, series, ctx.tseries)
+        elif need_a:
             for k in range(0, n, K):
                 m = min(K, n - k)
                 ckpts.append(grid.state())
@@ -132,6 +149,7 @@ class TeukEvolve(torch.autograd.Function):
             binding.teuk_step_n(grid.handle, n, series)
         ctx.grid, ctx.ckpts, ctx.n, ctx.K, ctx.need_a = grid, ckpts, n, K, need_a
         ctx.cfg, ctx.overlap, ctx.a_val, ctx.tangent = cfg, bool(overlap), float(a), bool(tangent)
+        ctx.spin = spin
         ctx.a_meta = (a.dtype, a.device, a.shape)
         return series
 
@@ -143,25 +161,32 @@ class TeukEvolve(torch.autograd.Function):
         lam_phi = torch.zeros(grid.shape, dtype=torch.complex128, device=grid.device)
         lam_pi = torch.zeros_like(lam_phi)
         grad_a = None
-        if ctx.need_a:
+        dtype, device, shape = ctx.a_meta
+        if ctx.need_a and ctx.spin == "forward":
+            dlda = torch.zeros((), dtype=torch.float64, device=grid.device)
+            binding.teuk_spin_gradient(grid.handle, n, gseries, ctx.tseries, dlda)
+            grad_a = dlda.to(dtype=dtype, device=device).reshape(shape)
+            if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
+                grid.adjoint(n, lam_phi, lam_pi, gseries, None, project_initial=True, spin=False)
+            ctx.tseries = None
+        elif ctx.need_a:
             segs = [(k, min(K, n - k)) for k in range(0, n, K)]
             if ctx.overlap and len(segs) > 1:
                 dlda = _reverse_overlapped(grid, ctx.a_val, ctx.cfg, ctx.ckpts, segs, min(K, n), gseries, lam_phi,
                                            lam_pi, ctx.tangent)
             else:
                 dlda = _reverse_sequential(grid, ctx.ckpts, segs, min(K, n), gseries, lam_phi, lam_pi, ctx.tangent)
-            dtype, device, shape = ctx.a_meta
             grad_a = dlda.to(dtype=dtype, device=device).reshape(shape)
         else:
             grid.adjoint(n, lam_phi, lam_pi, gseries, None, project_initial=True, spin=False)
         ctx.grid = None
         ctx.ckpts = None
         grid.close()
-        return lam_phi, lam_pi, grad_a, None, None, None, None, None
+        return lam_phi, lam_pi, grad_a, None, None, None, None, None, None
 
 
-def evolve(phi0, pi0, a, cfg, n_steps, checkpoint_every=100, overlap=True, tangent=True):
+def evolve(phi0, pi0, a, cfg, n_steps, checkpoint_every=100, overlap=True, tangent=True, spin="forward"):
     """Extraction series of an n-step evolution, differentiable in phi0, pi0 and a."""
     if not torch.is_tensor(a):
         a = torch.tensor(float(a), dtype=torch.float64, device=phi0.device)
-    return TeukEvolve.apply(phi0, pi0, a, cfg, n_steps, checkpoint_every, overlap, tangent)
+    return TeukEvolve.apply(phi0, pi0, a, cfg, n_steps, checkpoint_every, overlap, tangent, spin)

@@ -72,6 +72,12 @@ def _load():
         "teuk_set_steps_per_pass": (ctypes.c_int, [V, I32]),
         "teuk_get_steps_per_pass": (ctypes.c_int, [V, ctypes.POINTER(I32)]),
         "teuk_set_cache_policy": (ctypes.c_int, [V, I32]),
+        "teuk_spin_tangent_workspace_bytes": (ctypes.c_size_t, [V]),
+        "teuk_enable_spin_tangent": (ctypes.c_int, [V, V, ctypes.c_size_t]),
+        "teuk_set_spin_tangent": (ctypes.c_int, [V, V, V]),
+        "teuk_get_spin_tangent": (ctypes.c_int, [V, V, V]),
+        "teuk_step_n_spin_tangent": (ctypes.c_int, [V, I64, V, V]),
+        "teuk_spin_gradient": (ctypes.c_int, [V, I64, V, V, V]),
         "teuk_get_cache_policy": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "teuk_set_finite_check": (ctypes.c_int, [V, I64]),
         "teuk_set_adjoint_tile": (ctypes.c_int, [V, I32, I32]),
@@ -126,7 +132,9 @@ EXPORTED = ("teuk_workspace_bytes", "teuk_init_grid", "teuk_set_coefficients", "
             "teuk_batch_set_steps_per_pass", "teuk_batch_extract", "teuk_batch_n_extract", "teuk_radius",
             "teuk_assemble_modes", "teuk_set_finite_check", "teuk_extract_noalloc",
             "teuk_step_n_tangent", "teuk_get_window_slot", "teuk_source_workspace_bytes", "teuk_set_source",
-            "teuk_step_n_source", "teuk_adjoint_step_n_async")
+            "teuk_step_n_source", "teuk_adjoint_step_n_async", "teuk_spin_tangent_workspace_bytes",
+            "teuk_enable_spin_tangent", "teuk_set_spin_tangent", "teuk_get_spin_tangent", "teuk_step_n_spin_tangent",
+            "teuk_spin_gradient")
 
 
 def _check(rc):
@@ -295,6 +303,31 @@ def teuk_step_n_tangent(h, n, window):
     return _check(_lib.teuk_step_n_tangent(h, int(n), _dptr(window)))
 
 
+def teuk_spin_tangent_workspace_bytes(h):
+    return int(_lib.teuk_spin_tangent_workspace_bytes(h))
+
+
+def teuk_enable_spin_tangent(h, workspace):
+    return _check(_lib.teuk_enable_spin_tangent(h, _dptr(workspace), workspace.numel() * workspace.element_size()))
+
+
+def teuk_set_spin_tangent(h, vphi, vpi):
+    return _check(_lib.teuk_set_spin_tangent(h, _dptr(vphi), _dptr(vpi)))
+
+
+def teuk_get_spin_tangent(h, vphi, vpi):
+    return _check(_lib.teuk_get_spin_tangent(h, _dptr(vphi), _dptr(vpi)))
+
+
+def teuk_step_n_spin_tangent(h, n, series, tseries):
+    return _check(_lib.teuk_step_n_spin_tangent(h, int(n), _dptr(series), _dptr(tseries)))
+
+
+def teuk_spin_gradient(h, n, dseries, tseries, accum):
+    """accum (one-element float64 device tensor) += sum Re(conj(dseries) tseries); asynchronous."""
+    return _check(_lib.teuk_spin_gradient(h, int(n), _dptr(dseries), _dptr(tseries), _dptr(accum)))
+
+
 def teuk_get_window_slot(h, window, k, phi, pi):
     return _check(_lib.teuk_get_window_slot(h, _dptr(window), int(k), _dptr(phi), _dptr(pi)))
 
@@ -378,6 +411,7 @@ class TeukGrid:
         nbytes = teuk_workspace_bytes(self.params)
         self.workspace = _aligned_bytes(torch, nbytes, self.device)
         self.adjoint_workspace = None
+        self.spin_tangent_workspace = None
         with torch.cuda.device(self.device):
             self.handle = teuk_init_grid(self.params, self.stream.cuda_stream, self.workspace)
 
@@ -438,6 +472,44 @@ class TeukGrid:
             ws = _aligned_bytes(self.torch, teuk_adjoint_workspace_bytes(self.handle), self.device)
             teuk_enable_adjoint(self.handle, ws)
             self.adjoint_workspace = ws
+
+    def enable_spin_tangent(self):
+        """Carry v = du/da beside the state (forward-mode spin derivative); v = 0."""
+        self.enable_adjoint()
+        if self.spin_tangent_workspace is None:
+            ws = _aligned_bytes(self.torch, teuk_spin_tangent_workspace_bytes(self.handle), self.device)
+            teuk_enable_spin_tangent(self.handle, ws)
+            self.spin_tangent_workspace = ws
+
+    def set_spin_tangent(self, vphi=None, vpi=None):
+        """v from (ntheta, nr) complex128 tensors, or v = 0."""
+        self.enable_spin_tangent()
+        if vphi is None and vpi is None:
+            teuk_set_spin_tangent(self.handle, None, None)
+            return
+        vphi = self.torch.as_tensor(vphi, dtype=self.torch.complex128, device=self.device).contiguous()
+        vpi = self.torch.as_tensor(vpi, dtype=self.torch.complex128, device=self.device).contiguous()
+        if tuple(vphi.shape) != self.shape or tuple(vpi.shape) != self.shape:
+            raise ValueError(f"v must have shape {self.shape}")
+        self._v_keep = (vphi, vpi)  # until the stream has read them
+        teuk_set_spin_tangent(self.handle, vphi, vpi)
+
+    def spin_tangent(self):
+        """The current v as (phi, pi) tensors of shape (ntheta, nr)."""
+        phi = self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
+        pi = self.torch.empty_like(phi)
+        teuk_get_spin_tangent(self.handle, phi, pi)
+        return phi, pi
+
+    def step_spin_tangent(self, n, series=True):
+        """n steps of u and v; returns (series of u, series of v), each (n, n_extract)
+        complex128 (None without extraction points or with series=False)."""
+        s = t = None
+        if series and self.n_extract > 0:
+            s = self.torch.empty((int(n), self.n_extract), dtype=self.torch.complex128, device=self.device)
+            t = self.torch.empty_like(s)
+        teuk_step_n_spin_tangent(self.handle, n, s, t)
+        return s, t
 
     def new_window(self, n):
         """Device buffer for n stored states."""

@@ -180,6 +180,15 @@ hipError_t launch_adjoint2(const AdjArgs& a, const double* gsample_b, const doub
 // a.k: kStripCols-column strips, a.k.rows rows; a.rad_da the a-derivative tables).
 hipError_t launch_tangent(const double2* u_in, double2* u_out, double2* t_out, const AdjArgs& a, int waves_per_block,
                           hipStream_t s);
+// One step of the state and of its a-derivative v (u_in, v_in -> u_out,
+// v_out; tiles as launch_tangent), with the samples of u_in and v_in at the
+// first a.k.n_ext extraction points (at most one per tile; series_u/v may be
+// nullptr).
+hipError_t launch_spin_tangent(const double2* u_in, const double2* v_in, double2* u_out, double2* v_out,
+                               double2* series_u, double2* series_v, const AdjArgs& a, int waves_per_block,
+                               hipStream_t s);
+// *out += sum Re(conj(g_i) t_i) over count complex values (stream order).
+hipError_t launch_series_dot(const double2* g, const double2* t, int64_t count, double* out, hipStream_t s);
 hipError_t launch_extract_adjoint(double2* lam, int pitch, const ExtPoint* pts, int n, const double2* g,
                                   hipStream_t s);
 hipError_t launch_reduce_slots(const double* slots, int n, double* out, hipStream_t s);

@@ -214,8 +214,12 @@ struct teuk_grid {
     int adj2_rows = 32, adj2_chunks = 0;                              // two-step cotangent kernel
     int tan_rows = 32, tan_chunks = 0;                                // step-with-tangent kernel
     int cache_policy = TEUK_CACHE_AUTO;                               // teuk_set_cache_policy
+    // forward-mode spin derivative (teuk_enable_spin_tangent): v = du/da in two buffers
+    char* tws = nullptr;
+    int vcur = 0;
 
     double2* u(int k) const { return reinterpret_cast<double2*>(ws + L.off_u[k]); }
+    double2* v(int k) const { return reinterpret_cast<double2*>(tws + (size_t)k * L.state); }
     template <class T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
@@ -224,11 +228,12 @@ namespace {
 
 // Fused extraction handles at most one point per tile (its state is held
 // in scalar registers of the tile's wavefront).
-bool fused_extraction_ok(const teuk_grid* g, int strip_cols = kStripCols) {
+bool fused_extraction_ok(const teuk_grid* g, int strip_cols = kStripCols, int rows = 0) {
     const auto& E = g->ext;
+    if (rows <= 0) rows = g->rows;
     for (size_t i = 0; i < E.size(); ++i)
         for (size_t k = i + 1; k < E.size(); ++k)
-            if (E[i].col / strip_cols == E[k].col / strip_cols && E[i].rowa / g->rows == E[k].rowa / g->rows)
+            if (E[i].col / strip_cols == E[k].col / strip_cols && E[i].rowa / rows == E[k].rowa / rows)
                 return false;
     return true;
 }
@@ -548,6 +553,45 @@ int teuk_set_initial_data(teuk_grid* g, const void* d_phi, const void* d_pi) {
 
 namespace {
 
+// Optional device check of the state every check_every steps (at the first
+// pass boundary at or after each multiple) and at the end of a call: the
+// first check that finds a non-finite value records its step count on the
+// device; the call reads it once, at its end.
+struct InLoopCheck {
+    teuk_grid* g;
+    long long* first_bad;
+    int64_t start, last_check, next_check;
+    explicit InLoopCheck(teuk_grid* grid)
+        : g(grid), first_bad(first_nonfinite(grid)), start(grid->steps), last_check(grid->steps),
+          next_check(grid->steps + grid->check_every) {}
+    int check(const double2* u) {
+        HIP_TRY(launch_nonfinite_step(u, (int)g->p.nr, (int)g->p.ntheta, g->L.pitch, first_bad, g->steps,
+                                      g->stream));
+        last_check = g->steps;
+        return TEUK_OK;
+    }
+    int maybe(const double2* u) {
+        if (g->check_every <= 0 || g->steps < next_check) return TEUK_OK;
+        next_check = start + ((g->steps - start) / g->check_every + 1) * g->check_every;
+        return check(u);
+    }
+    // u: the state after the call's last step
+    int finish(const double2* u) {
+        if (g->check_every <= 0) return TEUK_OK;
+        if (last_check != g->steps)
+            if (int rc = check(u)) return rc;
+        long long bad = 0;
+        HIP_TRY(hipMemcpyAsync(&bad, first_bad, sizeof(bad), hipMemcpyDeviceToHost, g->stream));
+        HIP_TRY(hipStreamSynchronize(g->stream));
+        if (bad) {
+            HIP_TRY(launch_zero_ints(reinterpret_cast<int*>(first_bad), 2, g->stream));
+            return fail(TEUK_E_NONFINITE, "the state holds a non-finite value, first seen by the check after step %lld",
+                        bad);
+        }
+        return TEUK_OK;
+    }
+};
+
 // n steps; optional extraction series and optional window of input states
 // (slot k = the state before step k, stride L.state bytes); h_f: the time
 // factors of the source term for the n steps (4 doubles per step), or
@@ -600,24 +644,7 @@ int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window, const d
     // state); otherwise a separate pass samples each new state.
     const bool fused = g->fused_ext;
     int64_t sampled = 0;
-    // Optional device check of the state every check_every steps (at the
-    // first pass boundary at or after each multiple) and at the end of the
-    // call: the first check that finds a non-finite value records its step
-    // count on the device; the call reads it once, at its end.
-    long long* first_bad = first_nonfinite(g);
-    const int64_t start = g->steps;
-    int64_t last_check = start, next_check = start + g->check_every;
-    auto check_state = [&](const double2* u) -> int {
-        HIP_TRY(launch_nonfinite_step(u, (int)g->p.nr, (int)g->p.ntheta, g->L.pitch, first_bad, g->steps,
-                                      g->stream));
-        last_check = g->steps;
-        return TEUK_OK;
-    };
-    auto maybe_check = [&](const double2* u) -> int {
-        if (g->check_every <= 0 || g->steps < next_check) return TEUK_OK;
-        next_check = start + ((g->steps - start) / g->check_every + 1) * g->check_every;
-        return check_state(u);
-    };
+    InLoopCheck chk(g);
     auto extract_state = [&](const double2* u, int64_t j) -> int {
         HIP_TRY(launch_extract(u, g->L.pitch, ext, ne, series + (j - 1) * ne, g->stream));
         sampled = j;
@@ -637,7 +664,7 @@ int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window, const d
             advance(out);
             k += 2;
             g->steps += 2;
-            if (int rc = maybe_check(in)) return rc;
+            if (int rc = chk.maybe(in)) return rc;
         } else {
             if (series && !fused && k > sampled)
                 if (int rc = extract_state(in, k)) return rc;
@@ -654,25 +681,13 @@ int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window, const d
             g->steps += 1;
             if (series && !fused)
                 if (int rc = extract_state(out, k)) return rc;
-            if (int rc = maybe_check(in)) return rc;
+            if (int rc = chk.maybe(in)) return rc;
         }
     }
     if (series && sampled < n)
         if (int rc = extract_state(in, n)) return rc;
     g->cur = win ? 1 - cur0 : cur;
-    if (g->check_every > 0) {
-        if (last_check != g->steps)
-            if (int rc = check_state(in)) return rc;
-        long long bad = 0;
-        HIP_TRY(hipMemcpyAsync(&bad, first_bad, sizeof(bad), hipMemcpyDeviceToHost, g->stream));
-        HIP_TRY(hipStreamSynchronize(g->stream));
-        if (bad) {
-            HIP_TRY(launch_zero_ints(reinterpret_cast<int*>(first_bad), 2, g->stream));
-            return fail(TEUK_E_NONFINITE, "the state holds a non-finite value, first seen by the check after step %lld",
-                        bad);
-        }
-    }
-    return TEUK_OK;
+    return chk.finish(in);
 }
 
 }  // namespace
@@ -1130,6 +1145,114 @@ int teuk_adjoint_step_n_async(teuk_grid* g, int64_t n, void* d_lam_phi, void* d_
                               const void* d_window, int32_t flags, double* d_dL_da_accum) {
     if (!d_dL_da_accum) return fail(TEUK_E_INVALID_ARG, "the dL/da accumulator is NULL");
     return adjoint_impl(g, n, d_lam_phi, d_lam_pi, d_dL_dseries, d_window, flags, nullptr, d_dL_da_accum);
+}
+
+/* ---- forward-mode spin derivative ------------------------------------- */
+
+size_t teuk_spin_tangent_workspace_bytes(const teuk_grid* g) {
+    if (!g) {
+        fail(TEUK_E_INVALID_ARG, "grid handle is NULL");
+        return 0;
+    }
+    return 2 * g->L.state;
+}
+
+int teuk_enable_spin_tangent(teuk_grid* g, void* d_workspace, size_t bytes) {
+    if (int rc = check_grid(g)) return rc;
+    if (!g->aws) return fail(TEUK_E_STATE, "teuk_enable_adjoint has not been called (it builds the a-derivative tables)");
+    if (!d_workspace) return fail(TEUK_E_INVALID_ARG, "spin-tangent workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign)
+        return fail(TEUK_E_WORKSPACE, "spin-tangent workspace not %zu-byte aligned", kAlign);
+    if (bytes < 2 * g->L.state)
+        return fail(TEUK_E_WORKSPACE, "spin-tangent workspace has %zu bytes, needs %zu", bytes, 2 * g->L.state);
+    if (int rc = set_device(g)) return rc;
+    g->tws = static_cast<char*>(d_workspace);
+    g->vcur = 0;
+    HIP_TRY(hipMemsetAsync(g->tws, 0, 2 * g->L.state, g->stream));
+    return TEUK_OK;
+}
+
+int teuk_set_spin_tangent(teuk_grid* g, const void* d_vphi, const void* d_vpi) {
+    if (int rc = check_grid(g)) return rc;
+    if (!g->tws) return fail(TEUK_E_STATE, "teuk_enable_spin_tangent has not been called");
+    if ((d_vphi == nullptr) != (d_vpi == nullptr)) return fail(TEUK_E_INVALID_ARG, "give both planes or neither");
+    if (int rc = set_device(g)) return rc;
+    g->vcur = 0;
+    if (!d_vphi) {
+        HIP_TRY(hipMemsetAsync(g->v(0), 0, g->L.state, g->stream));
+        return TEUK_OK;
+    }
+    const int nr = (int)g->p.nr, nth = (int)g->p.ntheta;
+    HIP_TRY(launch_import(static_cast<const double2*>(d_vphi), g->v(0), 0, nr, nth, g->L.pitch, g->stream));
+    HIP_TRY(launch_import(static_cast<const double2*>(d_vpi), g->v(0), 1, nr, nth, g->L.pitch, g->stream));
+    return TEUK_OK;
+}
+
+int teuk_get_spin_tangent(teuk_grid* g, void* d_vphi, void* d_vpi) {
+    if (int rc = check_grid(g)) return rc;
+    if (!g->tws) return fail(TEUK_E_STATE, "teuk_enable_spin_tangent has not been called");
+    if (!d_vphi || !d_vpi) return fail(TEUK_E_INVALID_ARG, "output pointers are NULL");
+    if (int rc = set_device(g)) return rc;
+    const int nr = (int)g->p.nr, nth = (int)g->p.ntheta;
+    HIP_TRY(launch_export(g->v(g->vcur), static_cast<double2*>(d_vphi), 0, nr, nth, g->L.pitch, g->stream));
+    HIP_TRY(launch_export(g->v(g->vcur), static_cast<double2*>(d_vpi), 1, nr, nth, g->L.pitch, g->stream));
+    return TEUK_OK;
+}
+
+int teuk_step_n_spin_tangent(teuk_grid* g, int64_t n, void* d_series, void* d_tseries) {
+    if (int rc = check_grid(g)) return rc;
+    if (!g->tws) return fail(TEUK_E_STATE, "teuk_enable_spin_tangent has not been called");
+    if (n < 0) return fail(TEUK_E_INVALID_ARG, "n=%lld < 0", (long long)n);
+    if (n == 0) return TEUK_OK;
+    if (int rc = set_device(g)) return rc;
+    const int nr = (int)g->p.nr;
+    const int ne = g->p.n_extract;
+    double2* series = (ne > 0) ? static_cast<double2*>(d_series) : nullptr;
+    double2* tseries = (ne > 0) ? static_cast<double2*>(d_tseries) : nullptr;
+    const ExtPoint* ext = g->at<ExtPoint>(g->L.off_ext);
+    AdjArgs a = adjoint_args(g);
+    a.k.rows = g->tan_rows;
+    a.k.n_strips = (nr + kStripCols - 1) / kStripCols;
+    a.k.n_chunks = g->tan_chunks;
+    // the launches sample their input (row k-1 of a series: the state after
+    // step k); the call's last state, or every state when two extraction
+    // points share a tile, by a separate pass
+    const bool fused = fused_extraction_ok(g, kStripCols, g->tan_rows);
+    a.k.n_ext = fused ? ne : 0;
+    auto extract = [&](int64_t j) -> int {
+        if (series) HIP_TRY(launch_extract(g->u(g->cur), g->L.pitch, ext, ne, series + (j - 1) * ne, g->stream));
+        if (tseries) HIP_TRY(launch_extract(g->v(g->vcur), g->L.pitch, ext, ne, tseries + (j - 1) * ne, g->stream));
+        return TEUK_OK;
+    };
+    InLoopCheck chk(g);
+    for (int64_t k = 0; k < n; ++k) {
+        if (!fused && k > 0)
+            if (int rc = extract(k)) return rc;
+        double2* su = (series && fused && k > 0) ? series + (k - 1) * ne : nullptr;
+        double2* sv = (tseries && fused && k > 0) ? tseries + (k - 1) * ne : nullptr;
+        HIP_TRY(launch_spin_tangent(g->u(g->cur), g->v(g->vcur), g->u(1 - g->cur), g->v(1 - g->vcur), su, sv, a,
+                                    g->adj_wpb, g->stream));
+        g->cur = 1 - g->cur;
+        g->vcur = 1 - g->vcur;
+        g->steps += 1;
+        if (int rc = chk.maybe(g->u(g->cur))) return rc;
+    }
+    if (int rc = extract(n)) return rc;
+    return chk.finish(g->u(g->cur));
+}
+
+int teuk_spin_gradient(teuk_grid* g, int64_t n, const void* d_dL_dseries, const void* d_tseries,
+                       double* d_dL_da_accum) {
+    if (int rc = check_grid(g)) return rc;
+    if (n < 0) return fail(TEUK_E_INVALID_ARG, "n=%lld < 0", (long long)n);
+    if (!d_dL_da_accum) return fail(TEUK_E_INVALID_ARG, "the dL/da accumulator is NULL");
+    const int64_t count = n * g->p.n_extract;
+    if (count == 0) return TEUK_OK;
+    if (!d_dL_dseries || !d_tseries) return fail(TEUK_E_INVALID_ARG, "series pointers are NULL");
+    if (int rc = set_device(g)) return rc;
+    HIP_TRY(launch_series_dot(static_cast<const double2*>(d_dL_dseries), static_cast<const double2*>(d_tseries),
+                              count, d_dL_da_accum, g->stream));
+    return TEUK_OK;
 }
 
 /* ---- batched evolutions ------------------------------------------------ */

@@ -249,21 +249,22 @@ def _cfg(w):
                               "extract_theta")}
 
 
-def _gpu_loss_and_grads(w, phi0, pi0, target, n, K, a=None, overlap=True, tangent=True):
+def _gpu_loss_and_grads(w, phi0, pi0, target, n, K, a=None, overlap=True, tangent=True, spin="reverse"):
     from paper_1010_3816_amd.autograd import evolve
 
     P = torch.from_numpy(phi0).cuda().requires_grad_(True)
     Q = torch.from_numpy(pi0).cuda().requires_grad_(True)
     A = torch.tensor(w["a"] if a is None else a, dtype=torch.float64, device="cuda", requires_grad=True)
-    ser = evolve(P, Q, A, _cfg(w), n, K, overlap=overlap, tangent=tangent)
+    ser = evolve(P, Q, A, _cfg(w), n, K, overlap=overlap, tangent=tangent, spin=spin)
     L = ((ser - torch.from_numpy(target).cuda()).abs() ** 2).sum()
     L.backward()
     return float(L.detach()), P.grad.cpu().numpy(), Q.grad.cpu().numpy(), float(A.grad), ser.detach().cpu().numpy()
 
 
-def test_autograd_against_oracle_reverse_pass(gpu):
+@pytest.mark.parametrize("spin", ["reverse", "forward"])
+def test_autograd_against_oracle_reverse_pass(gpu, spin):
     w, phi0, pi0, target, n = _train_case()
-    L, gp, gq, ga, ser = _gpu_loss_and_grads(w, phi0, pi0, target, n, K=17)
+    L, gp, gq, ga, ser = _gpu_loss_and_grads(w, phi0, pi0, target, n, K=17, spin=spin)
     o = oracle.OracleGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"])
     p, q = o.project(phi0, pi0)
     _, _, oser = o.evolve(p, q, n, w["extract_rstar"], w["extract_theta"])
@@ -285,6 +286,33 @@ def test_autograd_tangent_and_state_routes_agree(gpu, overlap):
     assert r_t[0] == r_s[0]
     assert np.array_equal(r_t[1], r_s[1]) and np.array_equal(r_t[2], r_s[2])
     assert abs(r_t[3] - r_s[3]) <= 1e-12 * abs(r_s[3]), (r_t[3], r_s[3])
+
+
+def test_forward_and_reverse_spin_routes_agree(gpu):
+    """The spin derivative carried forward and the checkpointed adjoint: the
+    same loss and initial-data gradients bit for bit (both sweep the
+    cotangents with the same kernels), dL/da within 1e-10 (two exact routes
+    whose rounding differs)."""
+    w, phi0, pi0, target, n = _train_case(50)
+    r_f = _gpu_loss_and_grads(w, phi0, pi0, target, n, K=9, spin="forward")
+    r_r = _gpu_loss_and_grads(w, phi0, pi0, target, n, K=9, spin="reverse")
+    assert r_f[0] == r_r[0]
+    assert np.array_equal(r_f[1], r_r[1]) and np.array_equal(r_f[2], r_r[2])
+    assert abs(r_f[3] - r_r[3]) <= 1e-10 * abs(r_r[3]), (r_f[3], r_r[3])
+
+
+def test_forward_spin_route_spin_only(gpu):
+    """Only the spin needs a gradient: no adjoint sweep, dL/da as with the
+    initial data too."""
+    from paper_1010_3816_amd.autograd import evolve
+
+    w, phi0, pi0, target, n = _train_case(30)
+    full = _gpu_loss_and_grads(w, phi0, pi0, target, n, K=10, spin="forward")
+    A = torch.tensor(w["a"], dtype=torch.float64, device="cuda", requires_grad=True)
+    ser = evolve(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda(), A, _cfg(w), n, 10)
+    L = ((ser - torch.from_numpy(target).cuda()).abs() ** 2).sum()
+    L.backward()
+    assert float(L.detach()) == full[0] and float(A.grad) == full[3]
 
 
 def test_checkpoint_interval_independence(gpu):
@@ -361,12 +389,13 @@ def test_full_size_adjoint_segment(gpu, tangent):
     g.close()
 
 
-def test_full_workload_gradients_against_finite_differences(gpu):
+@pytest.mark.parametrize("spin", ["forward", "reverse"])
+def test_full_workload_gradients_against_finite_differences(gpu, spin):
     """The whole adjoint workload (6400 x 256, a = 0.7, 8000 steps, a
-    checkpoint every 100 steps, target from the perturbed run): the
-    checkpointed adjoint gradient against central differences of the GPU
-    forward loss, along a random direction of the initial data and in the
-    spin.  Bar: 1e-6 relative."""
+    checkpoint every 100 steps, target from the perturbed run): the gradient
+    (spin derivative carried forward, or the checkpointed adjoint) against
+    central differences of the GPU forward loss, along a random direction of
+    the initial data and in the spin.  Bar: 1e-6 relative."""
     from paper_1010_3816_amd.autograd import evolve
 
     w = inputs.workload("adjoint_a0.7_6400x256")
@@ -379,7 +408,7 @@ def test_full_workload_gradients_against_finite_differences(gpu):
     P = p0.clone().requires_grad_(True)
     Q = q0.clone().requires_grad_(True)
     A = torch.tensor(w["a"], dtype=torch.float64, device="cuda", requires_grad=True)
-    L = ((evolve(P, Q, A, cfg, n, K) - target).abs() ** 2).sum()
+    L = ((evolve(P, Q, A, cfg, n, K, spin=spin) - target).abs() ** 2).sum()
     L.backward()
     assert float(L.detach()) > 0 and float(A.grad) != 0.0
 

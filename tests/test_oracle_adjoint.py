@@ -8,7 +8,10 @@
 * the whole reverse pass against finite differences of a loss
   L = sum_n |E Phi^n - y_n|^2: central differences in the initial data are
   exact up to rounding (L is quadratic in the data), differences in a are
-  Richardson-extrapolated.
+  Richardson-extrapolated;
+* the forward-mode evolution of v = du/da: its series derivative against
+  Richardson-extrapolated differences of the series in a, and its dL/da
+  against the reverse pass (two exact routes to one number).
 """
 import math
 
@@ -119,3 +122,44 @@ def test_reverse_pass_spin_gradient():
     h = 1e-3
     rich = (4 * cd(h / 2) - cd(h)) / 3
     assert abs(rich - dLda) <= 1e-6 * abs(dLda), (rich, dLda)
+
+
+def test_forward_mode_spin_derivative():
+    """v = du/da carried forward: ds/da matches Richardson differences of the
+    series in a, dL/da = sum Re(conj(dL/ds) ds/da) matches the reverse pass,
+    and the state and series are those of evolve()."""
+    w, phi0, pi0, target = _loss_and_grad_setup()
+    L0, ser = _loss(w, w["a"], phi0, pi0, target)
+    g = oracle.OracleGrid(w["a"], w["s"], w["m"], w["nr"], w["nth"], w["rmin"], w["rmax"], w["dt"])
+    p, q = g.project(phi0, pi0)
+    z = np.zeros_like(p)
+    p1, q1, vp, vq, ser_f, tser = g.evolve_spin_tangent(p, q, z, z, w["n"], w["er"], w["et"])
+    p2, q2, ser2 = g.evolve(p, q, w["n"], w["er"], w["et"])
+    assert np.array_equal(p1, p2) and np.array_equal(q1, q2) and np.array_equal(ser_f, ser2)
+
+    def ser_at(a):
+        o = oracle.OracleGrid(a, w["s"], w["m"], w["nr"], w["nth"], w["rmin"], w["rmax"], w["dt"])
+        pp, qq = o.project(phi0, pi0)
+        return o.evolve(pp, qq, w["n"], w["er"], w["et"])[2]
+
+    h = 1e-3
+    c1 = (ser_at(w["a"] + h) - ser_at(w["a"] - h)) / (2 * h)
+    c2 = (ser_at(w["a"] + h / 2) - ser_at(w["a"] - h / 2)) / h
+    rich = (4 * c2 - c1) / 3
+    assert np.max(np.abs(rich - tser)) <= 1e-7 * np.max(np.abs(tser))
+
+    gser = 2.0 * (ser - target)
+    _, _, dlda_rev = g.adjoint_evolve(phi0, pi0, w["n"], w["er"], w["et"], gser)
+    dlda_fwd = float(np.sum(gser.real * tser.real + gser.imag * tser.imag))
+    assert abs(dlda_fwd - dlda_rev) <= 1e-12 * abs(dlda_rev), (dlda_fwd, dlda_rev)
+
+
+def test_forward_mode_carries_v():
+    """A nonzero v^0 is carried by the homogeneous part: with u^0 = 0 the
+    tangent term vanishes and v evolves by the step itself."""
+    g = oracle.OracleGrid(0.7, -2, 2, 40, 8, -20.0, 30.0, 0.03)
+    v = g.project(*inputs.random_state(40, 8, 21))
+    z = np.zeros_like(v[0])
+    _, _, vp, vq, _, _ = g.evolve_spin_tangent(z, z, v[0], v[1], 5)
+    ep, eq = g.step(v[0], v[1], 5)
+    assert np.array_equal(vp, ep) and np.array_equal(vq, eq)
