@@ -87,15 +87,13 @@ inline bool tortoise_inverse(double a, double rstar, double* x_out) {
     return std::isfinite(x) && x > 0.0 && fx < 1e-9 * std::fmax(1.0, std::fabs(rstar));
 }
 
-// x(r*; a) with its spin derivative at fixed r*: dx/da = -(dr*/da)|_x / (dr*/dx)|_a.
-inline bool tortoise_inverse_dual(double a, double rstar, Dual* x_out) {
-    double x;
-    if (!tortoise_inverse(a, rstar, &x)) return false;
+// x(r*; a) with its spin derivative at fixed r*, from the solved x:
+// dx/da = -(dr*/da)|_x / (dr*/dx)|_a.
+inline Dual tortoise_x_dual(double a, double x) {
     const double q = std::sqrt(1.0 - a * a), r = 1.0 + q + x;
     const double dr_da = tortoise(Dual(a, 1.0), Dual(x, 0.0)).d;
     const double dr_dx = (r * r + a * a) / (x * (x + 2.0 * q));
-    *x_out = Dual(x, -dr_da / dr_dx);
-    return true;
+    return Dual(x, -dr_da / dr_dx);
 }
 
 // The radial factors of RadField at one position.

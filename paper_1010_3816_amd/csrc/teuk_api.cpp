@@ -214,6 +214,7 @@ struct teuk_grid {
     int adj2_rows = 32, adj2_chunks = 0;                              // two-step cotangent kernel
     int tan_rows = 32, tan_chunks = 0;                                // step-with-tangent kernel
     int cache_policy = TEUK_CACHE_AUTO;                               // teuk_set_cache_policy
+    std::vector<double> x_tab;  // x = r - r_+ at the integer [0][nr] and half [1][nr] positions (KERR)
     // forward-mode spin derivative (teuk_enable_spin_tangent): v = du/da in two buffers
     char* tws = nullptr;
     int vcur = 0;
@@ -444,10 +445,12 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
     const double dr = (p->rstar_max - p->rstar_min) / (double)(nr - 1);
     const double dth = M_PI / nth;
 
-    // 1-D tables on the host
-    std::vector<double> rad, ang((size_t)kNumAng * nth);
+    // 1-D tables on the host; x at each position is kept for the
+    // a-derivative tables (teuk_enable_adjoint)
+    std::vector<double> rad, ang((size_t)kNumAng * nth), xs;
     if (p->coef_mode == TEUK_COEF_KERR) {
         rad.assign((size_t)kNumRad * 2 * L.pitch, 0.0);
+        xs.assign((size_t)2 * nr, 0.0);
         for (int kind = 0; kind < 2; ++kind) {
             const int npos = kind == 0 ? nr : nr - 1;
             for (int i = 0; i < npos; ++i) {
@@ -455,6 +458,7 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
                 double x;
                 if (!tortoise_inverse(p->a, rs, &x))
                     return fail(TEUK_E_INVALID_ARG, "tortoise inversion failed at r*=%g", rs);
+                xs[(size_t)kind * nr + i] = x;
                 double R[kNumRad];
                 radial_fields<double>(p->a, p->s, p->m, x, dth, R);
                 for (int f = 0; f < kNumRad; ++f) rad[((size_t)f * 2 + kind) * L.pitch + i] = R[f];
@@ -471,6 +475,7 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
     g->p = *p;
     g->p.dt = dt;
     g->L = L;
+    g->x_tab = std::move(xs);
     g->stream = reinterpret_cast<hipStream_t>(hip_stream);
     g->ws = reinterpret_cast<char*>(d_workspace);
     g->dr = dr;
@@ -966,16 +971,14 @@ int teuk_enable_adjoint(teuk_grid* g, void* d_adj_workspace, size_t bytes) {
     adjoint_layout(g, &total);
     if (bytes < total) return fail(TEUK_E_WORKSPACE, "adjoint workspace has %zu bytes, needs %zu", bytes, total);
     // a-derivatives of the radial tables at fixed r* (dual numbers through
-    // the tortoise inversion and every radial factor)
+    // the tortoise inversion and every radial factor), from the x that
+    // teuk_init_grid solved for at each position
     const int nr = (int)g->p.nr;
     std::vector<double> da((size_t)kNumRad * 2 * g->L.pitch, 0.0);
     for (int kind = 0; kind < 2; ++kind) {
         const int npos = kind == 0 ? nr : nr - 1;
         for (int i = 0; i < npos; ++i) {
-            const double rs = g->p.rstar_min + (i + 0.5 * kind) * g->dr;
-            Dual x;
-            if (!tortoise_inverse_dual(g->p.a, rs, &x))
-                return fail(TEUK_E_INVALID_ARG, "tortoise inversion failed at r*=%g", rs);
+            const Dual x = tortoise_x_dual(g->p.a, g->x_tab[(size_t)kind * nr + i]);
             Dual R[kNumRad];
             radial_fields<Dual>(Dual(g->p.a, 1.0), g->p.s, g->p.m, x, g->dth, R);
             for (int f = 0; f < kNumRad; ++f) da[((size_t)f * 2 + kind) * g->L.pitch + i] = R[f].d;
