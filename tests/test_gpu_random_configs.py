@@ -12,7 +12,10 @@ Forward: one and two steps per pass bit-identical; state and series within
 cotangents within 1e-11 of the oracle's transposed steps and dL/da within
 1e-10; the cotangent-only paths (one and two steps per pass) and the
 stored-tangent route bit-identical to the spin path's cotangents, the
-tangent route's dL/da within 1e-10 of the oracle.  Batch: random member sets
+tangent route's dL/da within 1e-10 of the oracle.  Spin derivative carried
+forward: u, v and both sample series within 1e-11 of the oracle's forward-mode
+evolution from random u and v, u and its series bit-identical to the forward
+path.  Batch: random member sets
 and persistent launch shapes bit-identical to single-grid evolutions and
 extractions.
 """
@@ -114,6 +117,35 @@ def test_random_adjoint(gpu, case):
     assert rel_err(outs[0][0], ref_p) <= TOL and rel_err(outs[0][1], ref_q) <= TOL, c
     assert abs(outs[0][2] - ref_dlda) <= 1e-10 * abs(ref_dlda), (c, outs[0][2], ref_dlda)
     assert abs(outs[3][2] - ref_dlda) <= 1e-10 * abs(ref_dlda), (c, outs[3][2], ref_dlda)
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_random_spin_tangent(gpu, case):
+    c = _draw(11000 + case, 10, 0)
+    nr, nth, n = c["nr"], c["nth"], c["n"]
+    w = small_case(c["a"], c["s"], c["m"], nr, nth, ext=c["ext"])
+    u0 = inputs.random_state(nr, nth, seed=12000 + case)
+    v0 = inputs.random_state(nr, nth, seed=13000 + case)
+    g = gpu.TeukGrid(w["a"], w["s"], w["m"], nr, nth, w["rstar_min"], w["rstar_max"], w["dt"],
+                     extract_rstar=w["extract_rstar"], extract_theta=w["extract_theta"])
+    g.set_adjoint_tile(c["rows"], c["wpb"])
+    g.set_initial_data(torch.from_numpy(u0[0]).cuda(), torch.from_numpy(u0[1]).cuda())
+    g.set_spin_tangent(torch.from_numpy(v0[0]).cuda(), torch.from_numpy(v0[1]).cuda())
+    su, sv = g.step_spin_tangent(n)
+    got = [x.cpu().numpy() for x in (*g.state(), *g.spin_tangent())]
+    g.close()
+    o = oracle.OracleGrid(c["a"], c["s"], c["m"], nr, nth, w["rstar_min"], w["rstar_max"], w["dt"])
+    p, q = o.project(*u0)
+    vp, vq = o.project(*v0)
+    ref = o.evolve_spin_tangent(p, q, vp, vq, n, w["extract_rstar"], w["extract_theta"])
+    for k in range(4):
+        assert rel_err(got[k], ref[k]) <= TOL, (c, k)
+    if c["ext"]:
+        assert rel_err(su.cpu().numpy(), ref[4]) <= TOL and rel_err(sv.cpu().numpy(), ref[5]) <= TOL, c
+    fwd = run_gpu(gpu, w, u0[0], u0[1], n, steps_per_pass=1)
+    assert np.array_equal(fwd[0], got[0]) and np.array_equal(fwd[1], got[1]), c
+    if c["ext"]:
+        assert np.array_equal(fwd[2], su.cpu().numpy()), c
 
 
 @pytest.mark.parametrize("case", range(8))
