@@ -491,6 +491,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     lds_cptr rvh = (lds_cptr)(slice + 1 * kNumRad * kWave);
 
     const bool own = (lane >= 2) && (lane <= kWave - 3) && (col < nr);
+    // Owned rows are stored through row resources (the lane's byte offset,
+    // or none) without DOT; with DOT, whose tangent rows need the registers,
+    // by plain stores under the lane mask (measured: the row resources spill
+    // there).
+    const int32_t row_bytes = P * (int32_t)sizeof(double2);
+    const uint32_t st_off = own ? (uint32_t)col * sizeof(double2) : kOffNone;
+    auto put_row = [&](int t, cd wp, cd wq) {
+        if constexpr (DOT) {
+            if (own) {
+                const size_t o = (size_t)t * P + col;
+                st_state<KEEP>(lam_out, o, wp);
+                st_state<KEEP>(lam_out, o + A.plane, wq);
+            }
+        } else {
+            const size_t o = (size_t)t * P;
+            st_row<KEEP>(row_rsrc(lam_out + o, row_bytes), st_off, wp);
+            st_row<KEEP>(row_rsrc(lam_out + o + A.plane, row_bytes), st_off, wq);
+        }
+    };
     const int j0 = chunk * A.rows;
     const int j1 = min(j0 + A.rows, nth);
     const int aE = min(j1, nth - 1);        // last row sweep A completes
@@ -696,11 +715,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
         finish(r - 1, bc, b_below, b_below_h, bn.dn, bn.dnh, gsample_b, wp, wq, ki, kh);
         dot(bc, tbr);
         load_tan(tan_b, r, tbr);
-        if (own) {
-            const size_t o = (size_t)(r - 1) * P + col;
-            st_state<KEEP>(lam_out, o, wp);
-            st_state<KEEP>(lam_out, o + A.plane, wq);
-        }
+        put_row(r - 1, wp, wq);
         b_below = bc.up;
         b_below_h = bc.uph;
     };
@@ -709,14 +724,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
         Coef ki, kh;
         finish(nth - 1, bc, b_below, b_below_h, cscale(sg, bc.up), cscale(sg, bc.uph), gsample_b, wp, wq, ki, kh);
         dot(bc, tbr);
-        if (own) {
-            const size_t o = (size_t)(nth - 1) * P + col;
-            st_state<KEEP>(lam_out, o, wp);
-            st_state<KEEP>(lam_out, o + A.plane, wq);
-        }
+        put_row(nth - 1, wp, wq);
     };
     AdjCot a_oth, b_oth;
     int r0 = j0 + 1;
+    // Without DOT, enter the row loop as its iterations end: the ring's first
+    // row loaded, its second still in flight, so that the compiler's wait at
+    // the loop head, which must suit both ways in, does not drain the ring.
+    if constexpr (!DOT) __builtin_amdgcn_s_waitcnt(waitcnt_vm(2));
     for (; r0 + 1 <= aE; r0 += 2) {
         step_row(r0, rp[0], rq[0], a_cur, a_oth, b_cur, b_oth, ta, tb);
         step_row(r0 + 1, rp[1], rq[1], a_oth, a_cur, b_oth, b_cur, ta, tb);

@@ -300,6 +300,44 @@ __device__ __forceinline__ void st_state(gout_t p, size_t o, cd v) {
     }
 }
 
+// Row access through buffer resources.  A resource describes one row of one
+// plane: its base address sits in scalar registers and each lane addresses
+// its column by a fixed byte offset, so moving to another row costs scalar
+// arithmetic only.  The hardware checks every lane's offset against the
+// resource's size and drops a store that falls outside it: a lane that must
+// not write gets the offset kOffNone, so stores need no branch on the lane
+// mask, and the compiler's waits on the memory counter, which count every
+// store on every path, stay as loose as the loads allow.
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+constexpr int kRsrcWord3 = 0x00020000;      // raw buffer, 32-bit data format
+constexpr uint32_t kOffNone = 0x80000000u;  // past the end of any row (at most 2^24 columns, 256 MiB)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(gin_t row, int32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)row, (short)0, bytes, kRsrcWord3);
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const double2* row, int32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double2*>(row), (short)0, bytes, kRsrcWord3);
+}
+
+__device__ __forceinline__ cd ld_row(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    const v2d v = __builtin_bit_cast(v2d, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    return {v.x, v.y};
+}
+
+// Immediate of s_waitcnt (gfx9 encoding: vmcnt in bits 3:0 and 15:14,
+// expcnt 6:4, lgkmcnt 11:8) that waits until at most n vector memory
+// operations are outstanding and leaves the other counters alone.
+constexpr int waitcnt_vm(int n) { return (n & 0xF) | (0x7 << 4) | (0xF << 8) | ((n >> 4) << 14); }
+
+// KEEP as in st_state: 0 streaming (non-temporal), 1 an ordinary store.
+template <int KEEP>
+__device__ __forceinline__ void st_row(__amdgpu_buffer_rsrc_t r, uint32_t off, cd v) {
+    v2d w;
+    w.x = v.re;
+    w.y = v.im;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, w), r, off, 0, KEEP ? 0 : 2);
+}
+
 // All pointers are distinct allocations (restrict): the uniform reads of
 // the angular tables and extraction descriptors become scalar loads.
 }  // namespace

@@ -456,21 +456,28 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
         }
     };
 
+    // Rows are read and written through row resources (device_common.hpp):
+    // lane byte offsets of the clamped column (loads) and of the owned
+    // column, or none (stores).
+    const int32_t row_bytes = P * (int32_t)sizeof(v2d);
+    const uint32_t ld_off = (uint32_t)ci * sizeof(v2d);
+    const uint32_t st_off = store_ok ? (uint32_t)col * sizeof(v2d) : kOffNone;
+    auto put_row = [&](gout_t base, int t, cd vp, cd vq, auto keep) {
+        const gout_t b = base + (size_t)t * P;
+        st_row<decltype(keep)::value>(row_rsrc(b, row_bytes), st_off, vp);
+        st_row<decltype(keep)::value>(row_rsrc(b + A.plane, row_bytes), st_off, vq);
+    };
+
     // the intermediate state, kept for the adjoint (owned rows and columns)
     auto store_mid = [&](int t, cd vp, cd vq) {
-        if (u_mid != nullptr && t >= j0 && t < j1 && store_ok) {
-            const size_t o = (size_t)t * P + col;
-            st(u_mid, o, vp);
-            st(u_mid, o + A.plane, vq);
-        }
+        if (u_mid != nullptr && t >= j0 && t < j1) put_row(u_mid, t, vp, vq, std::integral_constant<int, 0>{});
     };
 
     auto load_row = [&](int t, cd& p, cd& q) {
-        const size_t o = (size_t)min(max(t, 0), lastA) * P + ci;
-        p = ld(u_in, o);
-        q = ld(u_in, o + A.plane);
+        const gin_t b = u_in + (size_t)min(max(t, 0), lastA) * P;
+        p = ld_row(row_rsrc(b, row_bytes), ld_off);
+        q = ld_row(row_rsrc(b + A.plane, row_bytes), ld_off);
     };
-    auto put = [&](size_t o, cd v) { st_state<KEEP>(u_out, o, v); };
 
     // ---- prologue: step A completes rows j0-1 (if j0 > 0) and j0; step B
     // takes them as its halo row and its first row ------------------------
@@ -593,27 +600,25 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
         sample(r, bn.p, acc_mid);
         cd wp, wq;
         out_row(r - 1, bc, kic, b_hbp_m, bn.ubp, bn.hbp, wp, wq, 1);
-        if (store_ok) {
-            const size_t o = (size_t)(r - 1) * P + col;
-            put(o, wp);
-            put(o + A.plane, wq);
-        }
+        put_row(u_out, r - 1, wp, wq, std::integral_constant<int, KEEP>{});
         b_hbp_m = bc.hbp;
     };
     // the grid's last row: step B with the pole ghost row
     auto last_row = [&](const Row& bc, const Coef& kic) {
         cd wp, wq;
         out_row(nth - 1, bc, kic, b_hbp_m, cscale(sg, bc.ubp), cscale(sg, bc.hbp), wp, wq, 1);
-        if (store_ok) {
-            const size_t o = (size_t)(nth - 1) * P + col;
-            put(o, wp);
-            put(o + A.plane, wq);
-        }
+        put_row(u_out, nth - 1, wp, wq, std::integral_constant<int, KEEP>{});
     };
 
     Row a_oth, b_oth;
     Coef kh_oth, ki_oth;
     int r0 = j0 + 1;
+    // Enter the row loop as each of its iterations ends: the ring's first
+    // row loaded, its second still in flight.  The compiler's waits at the
+    // loop head must suit both ways in; without this they drain the ring in
+    // every iteration.  (Unconditional: a wait under the loop's own guard is
+    // not seen as one by the compiler.)
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(2));
     for (; r0 + 1 <= aE; r0 += 2) {
         step_row(r0, bp[0], bq[0], a_cur, a_oth, b_cur, b_oth, kh_a, kh_oth, ki_b, ki_oth, true);
         step_row(r0 + 1, bp[1], bq[1], a_oth, a_cur, b_oth, b_cur, kh_oth, kh_a, ki_oth, ki_b, true);

@@ -73,6 +73,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
 
     const bool store_ok = (lane >= 1) && (lane <= kWave - 2) && (col < nr);
     const bool boundary = (col == 0) || (col == nr - 1);
+    // rows through row resources (lane byte offsets: the clamped column for
+    // loads; the owned column, or none, for stores)
+    const int32_t row_bytes = P * (int32_t)sizeof(double2);
+    const uint32_t st_off = store_ok ? (uint32_t)col * sizeof(double2) : kOffNone;
+    auto load_row = [&](int t, cd& p, cd& q, cd& vp, cd& vq) {
+        const size_t o = (size_t)t * P + ci;
+        p = ld(u_in, o);
+        q = ld(u_in, o + A.plane);
+        vp = ld(v_in, o);
+        vq = ld(v_in, o + A.plane);
+    };
     const int j0 = chunk * A.rows;
     const int j1 = min(j0 + A.rows, nth);
     const double sg = (double)A.sigma;
@@ -164,17 +175,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     {
         cd ubp_prev = {0.0, 0.0}, ubv_prev = {0.0, 0.0};
         if (j0 > 0) {
-            const size_t o = (size_t)(j0 - 1) * P + ci;
-            const FtRow rm = fresh(j0 - 1, ld(u_in, o), ld(u_in, o + A.plane), ld(v_in, o), ld(v_in, o + A.plane),
-                                   ubp_prev, ubv_prev, ang_row(j0 - 1));
+            cd p, q, vp, vq;
+            load_row(j0 - 1, p, q, vp, vq);
+            const FtRow rm = fresh(j0 - 1, p, q, vp, vq, ubp_prev, ubv_prev, ang_row(j0 - 1));
             ubp_prev = rm.ubp;
             ubv_prev = rm.ubv;
             hbp_m = rm.hbp;
             wbp_m = rm.wbp;
         }
-        const size_t o = (size_t)j0 * P + ci;
-        cur = fresh(j0, ld(u_in, o), ld(u_in, o + A.plane), ld(v_in, o), ld(v_in, o + A.plane), ubp_prev, ubv_prev,
-                    ang_row(j0));
+        cd p, q, vp, vq;
+        load_row(j0, p, q, vp, vq);
+        cur = fresh(j0, p, q, vp, vq, ubp_prev, ubv_prev, ang_row(j0));
         if (j0 == 0) {
             hbp_m = cscale(sg, cur.hbp);
             wbp_m = cscale(sg, cur.wbp);
@@ -183,13 +194,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     Ang g_next = ang_row(j0 + 1);
     cd bp[2], bq[2], bvp[2], bvq[2];  // rows j0+1 .. j0+kFtRing of u and v in flight
 #pragma unroll
-    for (int k = 0; k < kFtRing; ++k) {
-        const size_t o = (size_t)min(j0 + 1 + k, last) * P + ci;
-        bp[k] = ld(u_in, o);
-        bq[k] = ld(u_in, o + A.plane);
-        bvp[k] = ld(v_in, o);
-        bvq[k] = ld(v_in, o + A.plane);
-    }
+    for (int k = 0; k < kFtRing; ++k) load_row(min(j0 + 1 + k, last), bp[k], bq[k], bvp[k], bvq[k]);
 
     auto finish_row = [&](int t, FtRow& cur, FtRow& nxt, cd& rp, cd& rq, cd& rvp, cd& rvq) {
         cd ubp_p, ubv_p, hbp_p, wbp_p;
@@ -208,13 +213,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
             wbp_p = cscale(sg, cur.wbp);
             nxt = cur;  // unused: the sweep ends with this row
         }
-        {
-            const size_t o = (size_t)min(t + 1 + kFtRing, last) * P + ci;
-            rp = ld(u_in, o);
-            rq = ld(u_in, o + A.plane);
-            rvp = ld(v_in, o);
-            rvq = ld(v_in, o + A.plane);
-        }
+        load_row(min(t + 1 + kFtRing, last), rp, rq, rvp, rvq);
 #if TEUK_SPIN_TANGENT_SCHED_BARRIER
         __builtin_amdgcn_sched_barrier(0);
 #endif
@@ -253,12 +252,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
             nvp = {0.0, 0.0};
             nvq = {0.0, 0.0};
         }
-        if (store_ok) {
-            const size_t so = (size_t)t * P + col;
-            st_state<KEEP>(u_out, so, np);
-            st_state<KEEP>(u_out, so + A.plane, nq);
-            st_state<KEEP>(v_out, so, nvp);
-            st_state<KEEP>(v_out, so + A.plane, nvq);
+        {
+            const size_t o = (size_t)t * P;
+            st_row<KEEP>(row_rsrc(u_out + o, row_bytes), st_off, np);
+            st_row<KEEP>(row_rsrc(u_out + o + A.plane, row_bytes), st_off, nq);
+            st_row<KEEP>(row_rsrc(v_out + o, row_bytes), st_off, nvp);
+            st_row<KEEP>(row_rsrc(v_out + o + A.plane, row_bytes), st_off, nvq);
         }
         hbp_m = cur.hbp;
         wbp_m = cur.wbp;
@@ -267,6 +266,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     FtRow other;
     int t0 = j0;
     constexpr int s1 = kFtRing - 1;  // ring slot of the pair's second row
+    // Enter the row loop with the ring loaded, as each iteration leaves it
+    // apart from its last stores: the compiler's wait at the loop head, which
+    // must suit both ways in, then leaves those stores in flight.
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
     for (; t0 + 2 <= j1; t0 += 2) {
         finish_row(t0, cur, other, bp[0], bq[0], bvp[0], bvq[0]);
         finish_row(t0 + 1, other, cur, bp[s1], bq[s1], bvp[s1], bvq[s1]);
