@@ -66,6 +66,8 @@ struct StepScalars {
     int32_t rows, n_strips, n_chunks, n_ext;
     int32_t zero;               // always 0 (an opaque row offset of LDS reads)
     int32_t keep;               // 1: the new state is written with ordinary stores (selects the kernel instance)
+    int32_t order;              // two-step pass: tile order (kTileOrder*)
+    int32_t pad_;
     int64_t plane;              // nth * pitch: offset of the Pi plane in a state
     double dt, hdt, dt_dr, hdt_dr;
     double inv_dth2, inv_2dth;  // USER mode scalings
@@ -73,6 +75,15 @@ struct StepScalars {
     // sf[4s .. 4s+3] = f(t_n), f(t_n + dt/2) (re, im) of its step s = 0, 1
     double sf[8];
 };
+
+// Tile order of the single-grid two-step pass.  Dispatch: tile = workgroup
+// x waves + wave, strips fastest; workgroups go round-robin over the 8 XCDs.
+// XCD strips: each XCD takes one contiguous run of strips (its 1/8) in every
+// theta chunk, so neighbouring strips (which share halo columns and 128-byte
+// lines) and the chunks of a strip (which share the radial tables) meet in
+// one L2; strips fastest (kTileOrderXcdStrip) or chunks fastest
+// (kTileOrderXcdChunk) within the XCD.
+constexpr int kTileOrderDispatch = 0, kTileOrderXcdStrip = 1, kTileOrderXcdChunk = 2;
 
 struct StepArgs {
     const double2* u_in;     // state: [Phi, Pi][nth][pitch]

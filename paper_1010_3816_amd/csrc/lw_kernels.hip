@@ -656,9 +656,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
                     const double2* __restrict__ src_h, StepScalars A) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
-    const int tile = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x / kWave));
-    const int strip = tile % A.n_strips;
-    const int chunk = tile / A.n_strips;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    int strip, chunk;
+    if (A.order == kTileOrderDispatch) {
+        const int tile = blockIdx.x * wpb + wave;
+        strip = tile % A.n_strips;
+        chunk = tile / A.n_strips;
+    } else {  // XCD strips: workgroup b runs on XCD b % 8
+        const int x = blockIdx.x % 8, q = (blockIdx.x / 8) * wpb + wave;
+        const int s_lo = x * A.n_strips / 8, n_x = (x + 1) * A.n_strips / 8 - s_lo;
+        if (n_x == 0) return;  // fewer strips than XCDs
+        if (A.order == kTileOrderXcdStrip) {
+            strip = s_lo + q % n_x;
+            chunk = q / n_x;
+        } else {
+            strip = s_lo + q / A.n_chunks;
+            chunk = q % A.n_chunks;
+            if (strip >= s_lo + n_x) return;
+        }
+    }
     extern __shared__ double rad_s[];
     if (chunk >= A.n_chunks) return;  // tiles beyond the last
     sweep_tile2<KERR, SRC, KEEP>((gin_t)u_in, (gout_t)u_out, (ctab_t)rad, (ctab_t)ang, (ctab_t)uci, (ctab_t)uch,
@@ -901,7 +917,12 @@ hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStr
 }
 
 hipError_t launch_step2(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s) {
-    const int nb = (a.k.n_strips * a.k.n_chunks + waves_per_block - 1) / waves_per_block;
+    // XCD orders: 8 equal shares of workgroups, each covering the tiles of
+    // the largest XCD run of strips
+    const int per_xcd = (a.k.n_strips + 7) / 8 * a.k.n_chunks;
+    const int nb = a.k.order == kTileOrderDispatch
+                       ? (a.k.n_strips * a.k.n_chunks + waves_per_block - 1) / waves_per_block
+                       : 8 * ((per_xcd + waves_per_block - 1) / waves_per_block);
     const dim3 block(kWave * waves_per_block), grid(nb);
     const bool src = a.src_i != nullptr;
     const int keep = a.k.keep ? 1 : 0;

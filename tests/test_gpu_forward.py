@@ -193,6 +193,9 @@ def test_step_split_invariance_and_zero_steps(gpu):
     (0.5, 2, 0, 3, 2, 5, (1, 1)),        # smallest grid, one-row chunks
     (0.3, -2, -2, 63, 2, 4, (2, 4)),     # both rows are pole rows
     (0.8, -2, 1, 300, 41, 10, (41, 8)),  # one chunk; eight waves requested, four used
+    # at least 64 strips: tiles in runs of strips per XCD, uneven runs
+    (0.7, -2, 2, 3845, 12, 5, (5, 4)),   # 65 strips (runs of 8 and one of 9), chunks of 5, 5, 2
+    (0.9, 0, -3, 4323, 7, 4, (3, 1)),    # 73 strips, one wave per workgroup, chunks of 3, 3, 1
 ])
 def test_two_step_passes_bit_identical(gpu, a, s, m, nr, nth, n, tile):
     """Two steps per pass (temporal blocking) give exactly the single-step
