@@ -279,7 +279,9 @@ def workload_leg(name):
     rows, wpb = g.tile()
     out = {"workload": name, "steps": n, "n_extract": g.n_extract, "ms_per_step": ms / n,
            "value": w["nr"] * w["ntheta"] * n / (ms * 1e-3), "unit": "grid-point updates/s",
-           "tile_rows": rows, "waves_per_block": wpb}
+           "tile_rows": rows, "waves_per_block": wpb,
+           # small grids: steps per launch of the block pass (0: the sweeps, with the tile above)
+           "block_steps": g.block_steps()}
     g.close()
     return out
 

@@ -67,7 +67,10 @@ struct StepScalars {
     int32_t zero;               // always 0 (an opaque row offset of LDS reads)
     int32_t keep;               // 1: the new state is written with ordinary stores (selects the kernel instance)
     int32_t order;              // two-step pass: tile order (kTileOrder*)
+    int32_t bsteps;             // block pass: steps per launch
+    int32_t bcols;              // block pass: columns a workgroup holds (bsteps halo columns each side)
     int32_t pad_;
+    int64_t row0;               // block pass: series row of the launch's first input state (-1: not sampled)
     int64_t plane;              // nth * pitch: offset of the Pi plane in a state
     double dt, hdt, dt_dr, hdt_dr;
     double inv_dth2, inv_2dth;  // USER mode scalings
@@ -159,6 +162,12 @@ struct AdjArgs {
 hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s);
 // Two steps in one pass (k.n_strips counted in kStripCols2-column strips).
 hipError_t launch_step2(const StepArgs& a, bool kerr, int waves_per_block, hipStream_t s);
+// Small grids (ntheta <= kMaxBlockRows, Kerr coefficients): k.bsteps steps in
+// one launch, each workgroup holding k.bcols columns x all rows in LDS
+// (a.series: samples of the launch's input states, rows k.row0 + s).
+constexpr int kMaxBlockRows = 64;
+constexpr int kMaxBlockExt = 8;
+hipError_t launch_block(const StepArgs& a, hipStream_t s);
 // Zero n ints (a fill kernel: usable where a memset node is not).
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 // two = true: two steps per launch (work list of tile_begin2 / n_strips2).

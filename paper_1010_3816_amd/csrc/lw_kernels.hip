@@ -683,6 +683,122 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
                            (gin_t)src_i, (gin_t)src_h);
 }
 
+// Small grids: k = A.bsteps steps in one launch.  A workgroup holds
+// A.bcols = W + 2k consecutive columns by all ntheta rows in LDS, one point
+// per thread, and takes k steps there; each step consumes one column at each
+// edge (the stencil's radial reach), so after k steps its W middle columns
+// hold the new state, which it writes back.  Every point's coefficients are
+// built once per launch (the sweeps rebuild them every step), so a step is
+// the stencil arithmetic alone: stage 1 in two phases (the averages of row t
+// are needed by rows t-1 and t+1 before the Pi half-step of row t), stage 2
+// in a third, with a barrier after each.  The expressions are those of
+// sweep_tile's fresh() and finish_row(), operand for operand, so the results
+// equal the sweeps' bit for bit; columns outside the grid read the clamped
+// edge column and, as in the sweeps, reach only the zeroed boundary columns.
+// Extraction: the samples of each step's input state, in the sweeps' order.
+template <int KEEP>
+__global__ void __launch_bounds__(1024)
+    lw_block_kernel(const double2* __restrict__ u_in, double2* __restrict__ u_out, const double* __restrict__ rad,
+                    const double* __restrict__ ang, const ExtPoint* __restrict__ ext, double2* __restrict__ series,
+                    StepScalars A) {
+    const int B = A.bcols, K = A.bsteps, W = B - 2 * K;
+    const int nr = A.nr, nth = A.nth, P = A.pitch;
+    const int j = threadIdx.x % B, t = threadIdx.x / B;  // blockDim.x == B * nth
+    const int c0 = blockIdx.x * W;                       // first column written
+    const int col = c0 - K + j;
+    const int ci = min(max(col, 0), nr - 1), hi = min(max(col, 0), nr - 2);
+    const int jl = max(j - 1, 0), jr = min(j + 1, B - 1);  // neighbours (clamped at the block's edges)
+    const int me = t * B + j;
+    const bool boundary = (col == 0) || (col == nr - 1);
+    const double sg = (double)A.sigma;
+    extern __shared__ double2 lds2[];
+    cd* sp = reinterpret_cast<cd*>(lds2);  // [nth][B] Phi, Pi, ubar_Phi, h_Phi, h_Pi; then 2 per point samples
+    cd* sq = sp + nth * B;
+    cd* su = sq + nth * B;
+    cd* sh = su + nth * B;
+    cd* shq = sh + nth * B;
+    cd* se = shq + nth * B;
+
+    cd p = ld(u_in, (size_t)t * P + ci), q = ld(u_in, (size_t)t * P + ci + A.plane);
+    const Ang G = load_ang(ang, nth, t);
+    const Rad Rh = load_rad(rad, P, 1, hi), Ri = load_rad(rad, P, 0, ci);
+    const Coef kh = kerr_coef(Rh, G, kerr_sigma(Rh, G));
+    const Coef ki = kerr_coef(Ri, G, kerr_sigma(Ri, G));
+    sp[me] = p;
+    sq[me] = q;
+    __syncthreads();
+
+    for (int s = 0; s < K; ++s) {
+        // stage 1 at (i+1/2, t): averages and the Phi half-step; samples
+        const cd pr = sp[t * B + jr], qr = sq[t * B + jr];
+        const cd ubp = cavg(p, pr);
+        const cd ubq = cavg(q, qr);
+        const cd dp = csub(pr, p);
+        const double tb = A.hdt_dr * kh.b;
+        const cd hp = {fma(-tb, dp.re, fma(A.hdt, ubq.re, ubp.re)), fma(-tb, dp.im, fma(A.hdt, ubq.im, ubp.im))};
+        const cd dq = csub(qr, q);
+        su[me] = ubp;
+        sh[me] = hp;
+        for (int e = 0; e < A.n_ext; ++e) {  // the points whose column this workgroup writes
+            const ExtPoint E = ext[e];
+            if (E.col >= c0 && E.col < c0 + W && col == E.col && (t == E.rowa || t == E.rowb))
+                se[2 * e + (t == E.rowa ? 0 : 1)] = {fma(E.wr, pr.re - p.re, p.re), fma(E.wr, pr.im - p.im, p.im)};
+        }
+        __syncthreads();
+
+        // stage 1, Pi half-step of row t (rows t -/+ 1 or the pole ghost rows)
+        const cd um = (t == 0) ? cscale(sg, ubp) : su[me - B];
+        const cd ubp_p = (t == nth - 1) ? cscale(sg, ubp) : su[me + B];
+        const cd dq1 = d_pi(kh, dp, dq);
+        const cd s1 = s_pi(kh, um, ubp, cd{0.0, 0.0}, ubq);
+        const cd x = {fma(A.hdt, s1.re, fma(-A.hdt_dr, dq1.re, ubq.re)), fma(A.hdt, s1.im, fma(-A.hdt_dr, dq1.im, ubq.im))};
+        const double wp = A.hdt * (kh.a2s + kh.a1s);
+        const cd hq = {fma(wp, ubp_p.re, x.re), fma(wp, ubp_p.im, x.im)};
+        shq[me] = hq;
+        if ((int)threadIdx.x < A.n_ext && A.row0 + s >= 0) {  // one thread per point writes its sample
+            const ExtPoint E = ext[threadIdx.x];
+            if (E.col >= c0 && E.col < c0 + W) {
+                const cd va = se[2 * threadIdx.x];
+                cd acc = {fma(E.wa, va.re, 0.0), fma(E.wa, va.im, 0.0)};
+                if (E.rowb >= 0) {
+                    const cd vb = se[2 * threadIdx.x + 1];
+                    acc = {fma(E.wb, vb.re, acc.re), fma(E.wb, vb.im, acc.im)};
+                }
+                series[(size_t)(A.row0 + s) * A.n_ext + threadIdx.x] = double2{acc.re, acc.im};
+            }
+        }
+        __syncthreads();
+
+        // stage 2 at (i, t)
+        const cd hpl = sh[t * B + jl];
+        const cd hbp = cavg(hp, hpl);
+        const cd dhp = csub(hp, hpl);
+        const cd hbp_m = (t == 0) ? cscale(sg, hbp) : cavg(sh[me - B], sh[(t - 1) * B + jl]);
+        const cd hbp_p = (t == nth - 1) ? cscale(sg, hbp) : cavg(sh[me + B], sh[(t + 1) * B + jl]);
+        const cd hql = shq[t * B + jl];
+        const cd hbq = cavg(hq, hql);
+        const cd dhq = csub(hq, hql);
+        const double tb2 = A.dt_dr * ki.b;
+        cd np = {fma(-tb2, dhp.re, fma(A.dt, hbq.re, p.re)), fma(-tb2, dhp.im, fma(A.dt, hbq.im, p.im))};
+        const cd dq2 = d_pi(ki, dhp, dhq);
+        const cd s2 = s_pi(ki, hbp_m, hbp, hbp_p, hbq);
+        cd nq = {fma(A.dt, s2.re, fma(-A.dt_dr, dq2.re, q.re)), fma(A.dt, s2.im, fma(-A.dt_dr, dq2.im, q.im))};
+        if (boundary) {
+            np = {0.0, 0.0};
+            nq = {0.0, 0.0};
+        }
+        p = np;
+        q = nq;
+        sp[me] = p;
+        sq[me] = q;
+        __syncthreads();
+    }
+    if (j >= K && j < K + W && col < nr) {
+        st_state<KEEP>(u_out, (size_t)t * P + col, p);
+        st_state<KEEP>(u_out, (size_t)t * P + col + A.plane, q);
+    }
+}
+
 __global__ void zero_ints_kernel(int* p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -913,6 +1029,15 @@ hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStr
                             : pick(lw_step_kernel<false, false, 0>, lw_step_kernel<false, false, 1>));
     hipLaunchKernelGGL(kern, grid, block, 0, s, a.u_in, a.u_out, a.rad, a.ang, a.uci, a.uch,
                        a.ext, a.series, a.win, a.src_i, a.src_h, a.k);
+    return hipGetLastError();
+}
+
+hipError_t launch_block(const StepArgs& a, hipStream_t s) {
+    const int w = a.k.bcols - 2 * a.k.bsteps;
+    const dim3 grid((a.k.nr + w - 1) / w), block(a.k.bcols * a.k.nth);
+    const size_t lds = (size_t)(5 * a.k.nth * a.k.bcols + 2 * kMaxBlockExt) * sizeof(double2);
+    hipLaunchKernelGGL(a.k.keep ? lw_block_kernel<1> : lw_block_kernel<0>, grid, block, lds, s, a.u_in, a.u_out,
+                       a.rad, a.ang, a.ext, a.series, a.k);
     return hipGetLastError();
 }
 

@@ -44,6 +44,7 @@ constexpr int kMaxExtract = 4096;
 constexpr int kMaxFusedAdjointExtract = 16;  // extraction points handled inside the adjoint kernel
 constexpr int64_t kMaxNr = int64_t(1) << 24;
 constexpr int64_t kMaxNth = int64_t(1) << 20;
+constexpr int kMinDefaultBlockSteps = 4;  // the default block pass takes at least this many steps a launch
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -204,6 +205,8 @@ struct teuk_grid {
     bool fused_ext = true;
     int steps_per_pass = 2;  // 2: pairs of steps in one pass (temporal blocking)
     bool fused_ext2 = true;  // extraction fusable with the two-step strips
+    int block_steps = 0;     // teuk_set_block_steps: steps per launch of the block pass (0: off)
+    int block_cols = 0;      // columns a block-pass workgroup holds (0: the grid has too many rows)
     int64_t check_every = 0;  // teuk_set_finite_check: steps between device checks of the state (0: off)
     char* sws = nullptr;      // source profile (teuk_set_source): [integer, half][nth][pitch] complex128
     bool coef_set = false;
@@ -489,6 +492,21 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
             cus = 256;
         default_tile(nr, nth, cus, &g->rows, &g->wpb);
     }
+    // the block pass: one thread per point of (columns x all rows), at most
+    // 1024 threads and 64 columns a workgroup.  Default: the most steps a
+    // launch whose workgroups (one a CU) fit the device in one round, if at
+    // least 4 (measured on 400 x 16 .. 3200 x 32 and 1600 x 64: fastest where
+    // it applies; 2 steps a launch are slower than the sweeps).
+    if (nth <= kMaxBlockRows) g->block_cols = std::min(64, (int)(1024 / nth));
+    if (g->block_cols > 0 && g->p.coef_mode == TEUK_COEF_KERR) {
+        for (int k = (g->block_cols - 2) / 2; k >= kMinDefaultBlockSteps; --k) {
+            const int64_t w = g->block_cols - 2 * k;
+            if ((nr + w - 1) / w <= cus) {
+                g->block_steps = k;
+                break;
+            }
+        }
+    }
     // a device holds two adjoint wavefronts per SIMD (8 per CU).  The
     // spin-gradient kernel leaves one slot in eight to the recompute that
     // the reverse pass runs beside it; the two-step cotangent kernel, which
@@ -658,7 +676,29 @@ int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window, const d
         sampled = j;
         return TEUK_OK;
     };
+    // Small grids: launches of the block pass (not with a window, a source
+    // term or more extraction points than it samples).
+    const bool block = g->block_steps > 0 && kerr && !win && !h_f && ne <= kMaxBlockExt;
     for (int64_t k = 0; k < n;) {
+        if (block) {
+            const int m = (int)std::min<int64_t>(g->block_steps, n - k);
+            double2* out = next_buffer(k + m);
+            StepArgs ab = a;
+            ab.u_in = in;
+            ab.u_out = out;
+            ab.k.bsteps = m;
+            ab.k.bcols = g->block_cols;
+            ab.k.n_ext = series ? ne : 0;
+            ab.k.row0 = k - 1;  // state k + s goes to series row k + s - 1
+            ab.series = series;
+            HIP_TRY(launch_block(ab, g->stream));
+            if (series) sampled = k + m - 1;
+            advance(out);
+            k += m;
+            g->steps += m;
+            if (int rc = chk.maybe(in)) return rc;
+            continue;
+        }
         if (two && k + 2 <= n && !(win && k == 0)) {
             double2* out = next_buffer(k + 2);
             a2.u_in = in;
@@ -888,6 +928,28 @@ int teuk_set_steps_per_pass(teuk_grid* g, int32_t steps_per_pass) {
 int teuk_get_steps_per_pass(const teuk_grid* g, int32_t* steps_per_pass) {
     if (int rc = check_grid(g)) return rc;
     if (steps_per_pass) *steps_per_pass = g->steps_per_pass;
+    return TEUK_OK;
+}
+
+int teuk_set_block_steps(teuk_grid* g, int32_t steps) {
+    if (int rc = check_grid(g)) return rc;
+    if (steps == 0) {
+        g->block_steps = 0;
+        return TEUK_OK;
+    }
+    if (g->p.coef_mode != TEUK_COEF_KERR || g->block_cols == 0)
+        return fail(TEUK_E_INVALID_ARG, "the block pass needs Kerr coefficients and ntheta <= %d", kMaxBlockRows);
+    const int max_steps = (g->block_cols - 2) / 2;
+    if (steps < 0 || steps > max_steps)
+        return fail(TEUK_E_INVALID_ARG, "block steps=%d outside [0, %d] for ntheta=%lld", steps, max_steps,
+                    (long long)g->p.ntheta);
+    g->block_steps = steps;
+    return TEUK_OK;
+}
+
+int teuk_get_block_steps(const teuk_grid* g, int32_t* steps) {
+    if (int rc = check_grid(g)) return rc;
+    if (steps) *steps = g->block_steps;
     return TEUK_OK;
 }
 

@@ -16,7 +16,7 @@ def rel_err(gpu, ref):
 
 
 def run_gpu(binding, w, phi0, pi0, n, tile=None, coef=None, mode=None, steps_per_pass=None, check_every=None,
-            cache_policy=None):
+            cache_policy=None, block_steps=None):
     import torch
 
     g = binding.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"],
@@ -32,6 +32,12 @@ def run_gpu(binding, w, phi0, pi0, n, tile=None, coef=None, mode=None, steps_per
         g.set_finite_check(check_every)
     if cache_policy is not None:
         g.set_cache_policy(cache_policy)
+    # A test that picks the sweeps' launch shape or steps per pass is about
+    # the sweeps: the small-grid block pass is off unless asked for.
+    if block_steps is None and (steps_per_pass is not None or tile is not None):
+        block_steps = 0
+    if block_steps is not None:
+        g.set_block_steps(block_steps)
     g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
     ser = g.step(n)
     phi, pi = g.state()

@@ -25,11 +25,12 @@ pytestmark = pytest.mark.gpu
     (0.5, 2, 0, 3, 2),         # smallest grid: one interior column
     (0.3, -2, -2, 63, 2),
 ])
-def test_random_state_parity(gpu, a, s, m, nr, nth):
+@pytest.mark.parametrize("block", [None, 0])  # the default (the block pass on grids it takes) and the sweeps
+def test_random_state_parity(gpu, a, s, m, nr, nth, block):
     w = small_case(a, s, m, nr, nth)
     phi0, pi0 = inputs.random_state(nr, nth, seed=nr * 131 + nth)
     n = 25
-    g = run_gpu(gpu, w, phi0, pi0, n)
+    g = run_gpu(gpu, w, phi0, pi0, n, block_steps=block)
     o = run_oracle(w, phi0, pi0, n)
     assert rel_err(g[0], o[0]) <= TOL
     assert rel_err(g[1], o[1]) <= TOL
@@ -46,7 +47,7 @@ def test_schwarzschild_400x32_full_run(gpu):
     w["extract_rstar"] = w["extract_rstar"] + [w["center"] + 0.5 * t_end]
     w["extract_theta"] = w["extract_theta"] + [math.pi / 2]
     phi0, pi0 = inputs.initial_data(w)
-    g = run_gpu(gpu, w, phi0, pi0, w["steps"])
+    g = run_gpu(gpu, w, phi0, pi0, w["steps"], block_steps=0)  # the sweeps (test_gpu_block: the block pass)
     o = run_oracle(w, phi0, pi0, w["steps"])
     assert np.all(np.isfinite(g[0]))
     assert rel_err(g[0], o[0]) <= TOL
@@ -66,13 +67,15 @@ def test_tile_shapes_bit_identical(gpu, tile):
         assert np.array_equal(out[k], ref[k])
 
 
-def test_extraction_points_and_fallback(gpu):
-    """Poles, grid ends and two points sharing a column (separate-kernel path)."""
+@pytest.mark.parametrize("block", [None, 0])  # the block pass (default here) and the sweeps
+def test_extraction_points_and_fallback(gpu, block):
+    """Poles, grid ends and two points sharing a column (the sweeps: the
+    separate-kernel path)."""
     ext = ((20.0, math.pi / 2), (20.0, math.pi / 2 + 0.2), (-30.0, 0.0), (60.0, math.pi), (1.23, 0.05))
     for m in (2, 3):
         w = small_case(0.6, -2, m, 150, 24, ext=ext)
         phi0, pi0 = inputs.random_state(150, 24, seed=m)
-        g = run_gpu(gpu, w, phi0, pi0, 9)
+        g = run_gpu(gpu, w, phi0, pi0, 9, block_steps=block)
         o = run_oracle(w, phi0, pi0, 9)
         assert g[2].shape == (9, len(ext))
         assert rel_err(g[2], o[2]) <= TOL
@@ -159,7 +162,8 @@ def test_state_round_trip_and_finite_check(gpu):
     g.close()
 
 
-def test_step_split_invariance_and_zero_steps(gpu):
+@pytest.mark.parametrize("block", [None, 0])  # the default (the block pass here) and the sweeps
+def test_step_split_invariance_and_zero_steps(gpu, block):
     """n steps in one call equal the same steps split over several calls, bit
     for bit, series included (the sample of each call's first input state is
     fused into the next kernel, the last one taken after the loop); a call
@@ -168,9 +172,11 @@ def test_step_split_invariance_and_zero_steps(gpu):
 
     w = small_case(0.9, -2, 3, 211, 37, ext=((20.0, math.pi / 2), (-12.0, 0.3)))
     phi0, pi0 = inputs.random_state(211, 37, seed=17)
-    ref = run_gpu(gpu, w, phi0, pi0, 12)
+    ref = run_gpu(gpu, w, phi0, pi0, 12, block_steps=block)
     g = gpu.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"],
                      extract_rstar=w["extract_rstar"], extract_theta=w["extract_theta"])
+    if block is not None:
+        g.set_block_steps(block)
     g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
     parts = []
     for n in (1, 0, 5, 6):
@@ -461,6 +467,7 @@ def test_in_loop_finite_check(gpu):
     bad = phi0.copy()
     bad[7, 40] = np.nan
     g = gpu.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"])
+    g.set_block_steps(0)  # the sweeps' check points (test_gpu_block: the block pass's)
     g.set_finite_check(10)
     g.set_initial_data(torch.from_numpy(bad).cuda(), torch.from_numpy(pi0).cuda())
     with pytest.raises(gpu.TeukError) as ei:
@@ -471,7 +478,7 @@ def test_in_loop_finite_check(gpu):
     g.step(25)  # finite: no error, and the flag of the failed call was cleared
     checked = [t.cpu().numpy() for t in g.state()]
     g.close()
-    ref = run_gpu(gpu, w, phi0, pi0, 25)
+    ref = run_gpu(gpu, w, phi0, pi0, 25, block_steps=0)
     assert np.array_equal(checked[0], ref[0]) and np.array_equal(checked[1], ref[1])
 
     # blow-up at the literal time step
@@ -490,6 +497,7 @@ def test_in_loop_finite_check(gpu):
     assert first is not None and first > 20
     every = 7
     g = gpu.TeukGrid(wl["a"], wl["s"], wl["m"], wl["nr"], wl["ntheta"], wl["rstar_min"], wl["rstar_max"], wl["dt"])
+    g.set_block_steps(0)
     g.set_finite_check(every)
     g.set_initial_data(torch.from_numpy(p0).cuda(), torch.from_numpy(q0).cuda())
     with pytest.raises(gpu.TeukError) as ei:

@@ -101,3 +101,15 @@ def test_hot_kernels_fit_two_wavefronts_per_simd(kernels):
                 assert regs <= 256, (name, regs)
                 assert spill <= max_spill, (name, spill)
     assert seen == set(HOT), set(HOT) - seen
+
+
+def test_block_kernel_fits_its_workgroup(kernels):
+    """The small-grid block pass runs workgroups of up to 1024 threads, 16
+    wavefronts on one CU: four per SIMD, so at most 128 VGPRs, no spills."""
+    found = [n for n in kernels if n.startswith("lw_block_kernel")]
+    assert found
+    for name in found:
+        md = kernels[name]
+        regs = int(md.get("vgpr_count", 0)) + int(md.get("agpr_count", 0))
+        assert regs <= 128, (name, regs)
+        assert int(md.get("vgpr_spill_count", 0)) == 0, name
