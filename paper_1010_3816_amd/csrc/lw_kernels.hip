@@ -689,9 +689,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
 // edge (the stencil's radial reach), so after k steps its W middle columns
 // hold the new state, which it writes back.  Every point's coefficients are
 // built once per launch (the sweeps rebuild them every step), so a step is
-// the stencil arithmetic alone: stage 1 in two phases (the averages of row t
-// are needed by rows t-1 and t+1 before the Pi half-step of row t), stage 2
-// in a third, with a barrier after each.  The expressions are those of
+// the stencil arithmetic alone, in two phases with a barrier after each:
+// stage 1 (the Pi half-step of row t needs the averages of rows t -/+ 1,
+// which each thread forms itself from the state) and stage 2.  The
+// expressions are those of
 // sweep_tile's fresh() and finish_row(), operand for operand, so the results
 // equal the sweeps' bit for bit; columns outside the grid read the clamped
 // edge column and, as in the sweeps, reach only the zeroed boundary columns.
@@ -712,10 +713,9 @@ __global__ void __launch_bounds__(1024)
     const bool boundary = (col == 0) || (col == nr - 1);
     const double sg = (double)A.sigma;
     extern __shared__ double2 lds2[];
-    cd* sp = reinterpret_cast<cd*>(lds2);  // [nth][B] Phi, Pi, ubar_Phi, h_Phi, h_Pi; then 2 per point samples
+    cd* sp = reinterpret_cast<cd*>(lds2);  // [nth][B] Phi, Pi, h_Phi, h_Pi; then 2 per point samples
     cd* sq = sp + nth * B;
-    cd* su = sq + nth * B;
-    cd* sh = su + nth * B;
+    cd* sh = sq + nth * B;
     cd* shq = sh + nth * B;
     cd* se = shq + nth * B;
 
@@ -729,7 +729,9 @@ __global__ void __launch_bounds__(1024)
     __syncthreads();
 
     for (int s = 0; s < K; ++s) {
-        // stage 1 at (i+1/2, t): averages and the Phi half-step; samples
+        // stage 1 at (i+1/2, t): averages, the Phi half-step and the Pi
+        // half-step, with the Phi averages of rows t -/+ 1 (or the pole
+        // ghost rows) formed here from the state; samples
         const cd pr = sp[t * B + jr], qr = sq[t * B + jr];
         const cd ubp = cavg(p, pr);
         const cd ubq = cavg(q, qr);
@@ -737,25 +739,24 @@ __global__ void __launch_bounds__(1024)
         const double tb = A.hdt_dr * kh.b;
         const cd hp = {fma(-tb, dp.re, fma(A.hdt, ubq.re, ubp.re)), fma(-tb, dp.im, fma(A.hdt, ubq.im, ubp.im))};
         const cd dq = csub(qr, q);
-        su[me] = ubp;
         sh[me] = hp;
         for (int e = 0; e < A.n_ext; ++e) {  // the points whose column this workgroup writes
             const ExtPoint E = ext[e];
             if (E.col >= c0 && E.col < c0 + W && col == E.col && (t == E.rowa || t == E.rowb))
                 se[2 * e + (t == E.rowa ? 0 : 1)] = {fma(E.wr, pr.re - p.re, p.re), fma(E.wr, pr.im - p.im, p.im)};
         }
-        __syncthreads();
-
-        // stage 1, Pi half-step of row t (rows t -/+ 1 or the pole ghost rows)
-        const cd um = (t == 0) ? cscale(sg, ubp) : su[me - B];
-        const cd ubp_p = (t == nth - 1) ? cscale(sg, ubp) : su[me + B];
+        const cd um = (t == 0) ? cscale(sg, ubp) : cavg(sp[me - B], sp[(t - 1) * B + jr]);
+        const cd ubp_p = (t == nth - 1) ? cscale(sg, ubp) : cavg(sp[me + B], sp[(t + 1) * B + jr]);
         const cd dq1 = d_pi(kh, dp, dq);
         const cd s1 = s_pi(kh, um, ubp, cd{0.0, 0.0}, ubq);
         const cd x = {fma(A.hdt, s1.re, fma(-A.hdt_dr, dq1.re, ubq.re)), fma(A.hdt, s1.im, fma(-A.hdt_dr, dq1.im, ubq.im))};
         const double wp = A.hdt * (kh.a2s + kh.a1s);
         const cd hq = {fma(wp, ubp_p.re, x.re), fma(wp, ubp_p.im, x.im)};
         shq[me] = hq;
-        if ((int)threadIdx.x < A.n_ext && A.row0 + s >= 0) {  // one thread per point writes its sample
+        __syncthreads();
+
+        // stage 2 at (i, t); one thread per point writes its sample
+        if ((int)threadIdx.x < A.n_ext && A.row0 + s >= 0) {
             const ExtPoint E = ext[threadIdx.x];
             if (E.col >= c0 && E.col < c0 + W) {
                 const cd va = se[2 * threadIdx.x];
@@ -767,9 +768,6 @@ __global__ void __launch_bounds__(1024)
                 series[(size_t)(A.row0 + s) * A.n_ext + threadIdx.x] = double2{acc.re, acc.im};
             }
         }
-        __syncthreads();
-
-        // stage 2 at (i, t)
         const cd hpl = sh[t * B + jl];
         const cd hbp = cavg(hp, hpl);
         const cd dhp = csub(hp, hpl);
@@ -1035,7 +1033,7 @@ hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStr
 hipError_t launch_block(const StepArgs& a, hipStream_t s) {
     const int w = a.k.bcols - 2 * a.k.bsteps;
     const dim3 grid((a.k.nr + w - 1) / w), block(a.k.bcols * a.k.nth);
-    const size_t lds = (size_t)(5 * a.k.nth * a.k.bcols + 2 * kMaxBlockExt) * sizeof(double2);
+    const size_t lds = (size_t)(4 * a.k.nth * a.k.bcols + 2 * kMaxBlockExt) * sizeof(double2);
     hipLaunchKernelGGL(a.k.keep ? lw_block_kernel<1> : lw_block_kernel<0>, grid, block, lds, s, a.u_in, a.u_out,
                        a.rad, a.ang, a.ext, a.series, a.k);
     return hipGetLastError();
