@@ -571,7 +571,7 @@ __device__ __forceinline__ void sweep_tile2(gin_t __restrict__ u_in, gout_t __re
     // live in two copies that swap roles from row to row: ac/bc/khc/kic
     // hold row r's, the next row's arrive in an/bn/khn/kin.
     static_assert(kRowsInFlight2 == 2, "the row loop takes rows in pairs");
-    // POLE: row r may be the grid's last (the pair loop's rows never are)
+    // POLE: row r may be the grid's last (so may the pair loop's second row, in the last chunk)
     auto step_row = [&](int r, cd& rp, cd& rq, Row& ac, Row& an, Row& bc, Row& bn, Coef& khc, Coef& khn, Coef& kic,
                         Coef& kin, bool pole) {
         cd ubp_p, hbp_p;

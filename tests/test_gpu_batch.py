@@ -107,6 +107,17 @@ def test_autotuners_pick_valid_shapes(gpu, tmp_path, monkeypatch):
     assert g.tile() == (res["rows"], res["waves"])
     again = autotune.tune_grid(g, rows=(8, 16), waves=(2, 4), steps=5)
     assert again.get("cached") and (again["rows"], again["waves"]) == (res["rows"], res["waves"])
+    assert res["block"] == 0 and g.block_steps() == 0  # 256 rows: no block pass
+    g.close()
+    # a small grid: sweeps' shapes with the block pass off, and its steps per launch
+    g = gpu.TeukGrid(0.0, -2, 2, 400, 32, -50.0, 150.0, 0.01)
+    res = autotune.tune_grid(g, rows=(1, 4), waves=(1,), steps=5)
+    kinds = {e["block"] for e in res["table"]}
+    assert 0 in kinds and len(kinds) > 1, kinds
+    assert g.tile() == (res["rows"], res["waves"]) and g.block_steps() == res["block"]
+    assert res["block"] in autotune.block_candidates(400, 32, torch.cuda.get_device_properties(0).multi_processor_count) + [0]
+    again = autotune.tune_grid(g, rows=(1, 4), waves=(1,), steps=5)
+    assert again.get("cached") and again["block"] == res["block"] and g.block_steps() == res["block"]
     g.close()
     b = gpu.TeukBatch(_members())
     res = autotune.tune_batch(b, rows=(8, 16), waves=(4,), blocks_per_cu=(1, 2), steps=3)
