@@ -228,9 +228,9 @@ int teuk_get_steps_per_pass(const teuk_grid* g, int32_t* steps_per_pass);
  * takes that many steps per launch (Sec. 3.2, Eqs. (lw1)-(lw2), the same
  * per-point arithmetic as the sweeps, so results are identical); each step
  * consumes one halo column at each side, and the c - 2 x steps middle
- * columns are written back.  teuk_step_n uses it when set, except with more
- * than 8 extraction points; teuk_step_n_store and the source-term and
- * adjoint calls keep the sweeps.  Default: the most steps a launch, at
+ * columns are written back.  teuk_step_n uses it when set, except for a
+ * series of more than 8 extraction points; teuk_step_n_store and the
+ * source-term and adjoint calls keep the sweeps.  Default: the most steps a launch, at
  * least 4, whose workgroups (one per compute unit) fit the device in one
  * round, else 0 (400 x 32 on 256 compute units: 15; 6400 x 64: 0).
  * TEUK_E_INVALID_ARG for another value or a grid the pass does not take. */

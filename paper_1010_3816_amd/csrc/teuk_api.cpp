@@ -677,8 +677,8 @@ int step_n_impl(teuk_grid* g, int64_t n, void* d_series, void* d_window, const d
         return TEUK_OK;
     };
     // Small grids: launches of the block pass (not with a window, a source
-    // term or more extraction points than it samples).
-    const bool block = g->block_steps > 0 && kerr && !win && !h_f && ne <= kMaxBlockExt;
+    // term or a series of more extraction points than it samples).
+    const bool block = g->block_steps > 0 && kerr && !win && !h_f && (!series || ne <= kMaxBlockExt);
     for (int64_t k = 0; k < n;) {
         if (block) {
             const int m = (int)std::min<int64_t>(g->block_steps, n - k);

@@ -90,6 +90,17 @@ def test_block_pass_many_points_falls_back(gpu):
     blk = run_gpu(gpu, w, phi0, pi0, 9, block_steps=6)
     for i in range(3):
         assert np.array_equal(blk[i], ref[i]), i
+    # without a series the block pass runs whatever the number of points
+    import torch
+
+    g = gpu.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"],
+                     extract_rstar=w["extract_rstar"], extract_theta=w["extract_theta"])
+    g.set_block_steps(6)
+    g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
+    assert g.step(9, series=False) is None
+    phi, pi = (t.cpu().numpy() for t in g.state())
+    assert np.array_equal(phi, ref[0]) and np.array_equal(pi, ref[1])
+    g.close()
 
 
 def _default_steps(nr, nth, cus):
