@@ -15,16 +15,19 @@ Prints one JSON line.  `value` is grid-point updates per second (one update
 `roofline` describes the dominant kernel, the two-step pass: it moves 64
 algorithmic bytes per point per pass (Phi, Pi read and written once,
 complex128), i.e. 32 B per update, against HBM (`bound` "hbm", 8 TB/s), with
-its FP64 rate and vector-instruction issue rate beside it.  `repeats` are
+its FP64 rate and vector-instruction issue rate beside it, and the rates of
+two plain copies (torch's and the library's own) for reference.  `repeats` are
 five more windows as long as the timed one, `sustained` a window of 2000
 steps (the device's steady state; short windows after an idle period run
 slower while the clocks come up).  `c1` and `c2` are the 400 x 32 and
-6400 x 256 workloads for all their steps with their extraction points;
+6400 x 256 workloads for all their steps with their extraction points, in
+the library's default launch (the small-grid block pass on 400 x 32);
 `batched` the 64-member uneven batch in one persistent launch per pass and
 its ratio to `value`; `waveform` nine modes of one problem and their sum;
-`adjoint` the backward (recompute + adjoint) over forward time of a
-checkpointed waveform-loss gradient on the 6400 x 256 grid, by the default
-stored-tangent route and by the stored-state route.  `cpu_baseline` times
+`adjoint` a waveform-loss gradient with respect to the initial data and the
+spin on the 6400 x 256 grid: `ratio` = (forward + backward - plain
+forward) / plain forward by the default route (the spin derivative carried
+forward), and the checkpointed adjoint's routes beside it.  `cpu_baseline` times
 the CPU oracle (test infrastructure, plain C + OpenMP) on a bounded number of
 steps of the same grid.
 """
@@ -45,7 +48,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 BYTES_PER_POINT_PASS = 64   # Phi, Pi read and written once per pass (complex128)
 FLOPS_PER_UPDATE = {1: 230, 2: 192}  # FP64 flops per point and step, single-step and two-step kernels
-VALU_PER_UPDATE = {1: 217, 2: 183}   # vector ALU instructions per point and step (steady-state loop)
+VALU_PER_UPDATE = {1: 217, 2: 180}   # vector ALU instructions per point and step (from the SQ counters)
 # vector instruction issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per 4 cycles per SIMD
 VALU_PEAK_T = 256 * 4 * 2.4e9 * 64 / 4 / 1e12
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1010_3816_amd", "csrc", f)
