@@ -284,7 +284,8 @@ def workload_leg(name):
            "value": w["nr"] * w["ntheta"] * n / (ms * 1e-3), "unit": "grid-point updates/s",
            "tile_rows": rows, "waves_per_block": wpb,
            # small grids: steps per launch of the block pass (0: the sweeps, with the tile above)
-           "block_steps": g.block_steps()}
+           # and the columns a workgroup holds
+           "block_steps": g.block_launch()[0], "block_cols": g.block_launch()[1]}
     g.close()
     return out
 

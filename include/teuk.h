@@ -221,21 +221,25 @@ int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per
 int teuk_set_steps_per_pass(teuk_grid* g, int32_t steps_per_pass);
 int teuk_get_steps_per_pass(const teuk_grid* g, int32_t* steps_per_pass);
 
-/* Small grids: steps per launch of the block pass, 0 (off) or 1 .. (c-2)/2,
- * c = min(64, 1024 / ntheta) the columns one workgroup holds.  The block
- * pass (grids with ntheta <= 64 and Kerr coefficients) keeps c columns by
- * all rows of the state in a workgroup's LDS, one point per thread, and
- * takes that many steps per launch (Sec. 3.2, Eqs. (lw1)-(lw2), the same
- * per-point arithmetic as the sweeps, so results are identical); each step
- * consumes one halo column at each side, and the c - 2 x steps middle
- * columns are written back.  teuk_step_n uses it when set, except for a
- * series of more than 8 extraction points; teuk_step_n_store and the
- * source-term and adjoint calls keep the sweeps.  Default: the most steps a launch, at
- * least 4, whose workgroups (one per compute unit) fit the device in one
- * round, else 0 (400 x 32 on 256 compute units: 15; 6400 x 64: 0).
- * TEUK_E_INVALID_ARG for another value or a grid the pass does not take. */
-int teuk_set_block_steps(teuk_grid* g, int32_t steps);
-int teuk_get_block_steps(const teuk_grid* g, int32_t* steps);
+/* Small grids: the block pass's launch.  The block pass (grids with
+ * ntheta <= 64 and Kerr coefficients) keeps `cols` consecutive columns by all
+ * rows of the state in one workgroup's LDS, one point per thread
+ * (cols x ntheta <= 1024 threads, 4 <= cols <= 64), and takes `steps` steps
+ * per launch (Sec. 3.2, Eqs. (lw1)-(lw2), the same per-point arithmetic as
+ * the sweeps, so results are identical); each step consumes one halo column
+ * at each side, and the cols - 2 x steps middle columns are written back, so
+ * 1 <= steps <= (cols - 2) / 2; steps = 0 turns it off (the sweeps), and
+ * cols = 0 keeps the grid's columns (or takes min(64, 1024 / ntheta) if none
+ * are set).  teuk_step_n uses it when on, except for a series of more than 8
+ * extraction points; teuk_step_n_store and the source-term and adjoint calls
+ * keep the sweeps.  Default: among workgroups of up to 256, 512 and 1024
+ * threads, the most steps (at least 4) whose workgroups fit the device one
+ * per compute unit, the pair scored by the per-step time measured on small
+ * grids; off where none fits (400 x 32 on 256 compute units: 16 columns,
+ * 7 steps; 6400 x 64: off).  TEUK_E_INVALID_ARG for values out of range or a
+ * grid the pass does not take.  The getter reports cols = 0 when unset. */
+int teuk_set_block_launch(teuk_grid* g, int32_t steps, int32_t cols);
+int teuk_get_block_launch(const teuk_grid* g, int32_t* steps, int32_t* cols);
 
 /* Cache policy of the stores that write the next state (teuk_step_n and its
  * variants, teuk_step_n_tangent) and the next cotangents

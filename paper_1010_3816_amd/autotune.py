@@ -91,59 +91,63 @@ def round_rows(nr, ntheta, cus, strip_cols=60, waves_per_simd=2, rounds=(1, 2, 3
 
 
 def block_candidates(nr, ntheta, cus, lo=4):
-    """Steps per launch of the block pass worth timing on a grid (empty when
-    the pass does not apply): from `lo` up to the most whose workgroups, one
-    per CU, fit the device in one round."""
+    """(steps, cols) launches of the block pass worth timing on a grid (empty
+    when the pass does not apply): workgroups of up to 256, 512 or 1024
+    threads (at most 64 columns), from `lo` steps up to the most whose
+    workgroups, one per CU, fit the device in one round."""
     if ntheta > 64:
         return []
-    c = min(64, 1024 // ntheta)
-    return [k for k in range(lo, (c - 2) // 2 + 1) if -(-nr // (c - 2 * k)) <= cus]
+    out = []
+    for c in sorted({min(64, t // ntheta) for t in (256, 512, 1024)}):
+        out += [(k, c) for k in range(lo, (c - 2) // 2 + 1) if -(-nr // (c - 2 * k)) <= cus]
+    return out
 
 
 def tune_grid(grid, rows=None, waves=GRID_WAVES, steps=20, use_cache=True, margin=0.02, blocks=None):
     """Pick the launch of a TeukGrid: (rows_per_tile, waves_per_block) of the
-    sweeps and, on grids the block pass takes, its steps per launch (0: the
-    sweeps); returns {"rows": r, "waves": w, "block": k, "ms": t, "table":
-    [...]}.  rows=None: GRID_ROWS and the heights of round_rows; blocks=None:
-    block_candidates.  The library's default launch is kept unless a
-    candidate is faster by more than `margin` (a fraction): run to run spread
-    on the device is a few per cent, and the default is the round-filling
-    shape."""
+    sweeps and, on grids the block pass takes, its (steps, cols) launch
+    (steps 0: the sweeps); returns {"rows": r, "waves": w, "block": k,
+    "cols": c, "ms": t, "table": [...]}.  rows=None: GRID_ROWS and the
+    heights of round_rows; blocks=None: block_candidates.  The library's
+    default launch is kept unless a candidate is faster by more than
+    `margin` (a fraction): run to run spread on the device is a few per cent,
+    and the default is the round-filling shape."""
     torch = grid.torch
     key = f"grid|{_device_key(torch, grid.device)}|{grid.nr}x{grid.ntheta}"
     if use_cache:
         hit = _load_cache().get(key)
         if hit:
             grid.set_tile(min(hit["rows"], grid.ntheta), hit["waves"])
-            grid.set_block_steps(hit.get("block", 0))
+            grid.set_block_launch(hit.get("block", 0), hit.get("cols", 0))
             return dict(hit, cached=True)
     cus = torch.cuda.get_device_properties(grid.device).multi_processor_count
     if rows is None:
         rows = tuple(GRID_ROWS) + tuple(round_rows(grid.nr, grid.ntheta, cus))
     if blocks is None:
         blocks = block_candidates(grid.nr, grid.ntheta, cus)
-    default = grid.tile() + (grid.block_steps(),)
+    default = grid.tile() + grid.block_launch()
     table = []
 
-    def timed(r, w, k):
+    def timed(r, w, k, c):
         grid.set_tile(r, w)
-        grid.set_block_steps(k)
+        grid.set_block_launch(k, c)
         ms = _time(torch, grid.stream, lambda n: binding.teuk_step_n(grid.handle, n, None), steps)
-        table.append({"rows": r, "waves": w, "block": k, "ms": ms})
+        table.append({"rows": r, "waves": w, "block": k, "cols": c, "ms": ms})
 
-    cands = {(min(r, grid.ntheta), w, 0) for r in rows for w in waves}
-    cands |= {default[:2] + (k,) for k in blocks} | {default}
+    cands = {(min(r, grid.ntheta), w, 0, default[3]) for r in rows for w in waves}
+    cands |= {default[:2] + (k, c) for k, c in blocks} | {default}
     for c in sorted(cands):
         timed(*c)
     best = min(table, key=lambda e: e["ms"])
-    dflt = next(e for e in table if (e["rows"], e["waves"], e["block"]) == default)
+    dflt = next(e for e in table if (e["rows"], e["waves"], e["block"], e["cols"]) == default)
     if dflt["ms"] <= best["ms"] * (1.0 + margin):
         best = dflt
     grid.set_tile(best["rows"], best["waves"])
-    grid.set_block_steps(best["block"])
-    out = {"rows": best["rows"], "waves": best["waves"], "block": best["block"], "ms": best["ms"], "table": table}
+    grid.set_block_launch(best["block"], best["cols"])
+    out = {k: best[k] for k in ("rows", "waves", "block", "cols", "ms")}
     if use_cache:
-        _store_cache(key, {"rows": best["rows"], "waves": best["waves"], "block": best["block"], "ms": best["ms"]})
+        _store_cache(key, dict(out))
+    out["table"] = table
     return out
 
 

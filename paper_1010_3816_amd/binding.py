@@ -71,8 +71,8 @@ def _load():
         "teuk_get_tile": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "teuk_set_steps_per_pass": (ctypes.c_int, [V, I32]),
         "teuk_get_steps_per_pass": (ctypes.c_int, [V, ctypes.POINTER(I32)]),
-        "teuk_set_block_steps": (ctypes.c_int, [V, I32]),
-        "teuk_get_block_steps": (ctypes.c_int, [V, ctypes.POINTER(I32)]),
+        "teuk_set_block_launch": (ctypes.c_int, [V, I32, I32]),
+        "teuk_get_block_launch": (ctypes.c_int, [V, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "teuk_set_cache_policy": (ctypes.c_int, [V, I32]),
         "teuk_spin_tangent_workspace_bytes": (ctypes.c_size_t, [V]),
         "teuk_enable_spin_tangent": (ctypes.c_int, [V, V, ctypes.c_size_t]),
@@ -127,7 +127,7 @@ EXPORTED = ("teuk_workspace_bytes", "teuk_init_grid", "teuk_set_coefficients", "
             "teuk_get_dt", "teuk_set_tile", "teuk_get_tile", "teuk_suggest_dt", "teuk_free",
             "teuk_last_error", "teuk_window_bytes", "teuk_step_n_store", "teuk_adjoint_workspace_bytes",
             "teuk_enable_adjoint", "teuk_adjoint_step_n", "teuk_set_adjoint_tile", "teuk_get_adjoint_tile",
-            "teuk_set_steps_per_pass", "teuk_get_steps_per_pass", "teuk_set_block_steps", "teuk_get_block_steps",
+            "teuk_set_steps_per_pass", "teuk_get_steps_per_pass", "teuk_set_block_launch", "teuk_get_block_launch",
             "teuk_set_cache_policy", "teuk_get_cache_policy",
             "teuk_batch_workspace_bytes", "teuk_batch_init",
             "teuk_batch_set_initial_data", "teuk_batch_get_state", "teuk_batch_step_n", "teuk_batch_set_launch",
@@ -273,14 +273,15 @@ def teuk_get_steps_per_pass(h):
     return v.value
 
 
-def teuk_set_block_steps(h, steps):
-    return _check(_lib.teuk_set_block_steps(h, int(steps)))
+def teuk_set_block_launch(h, steps, cols=0):
+    return _check(_lib.teuk_set_block_launch(h, int(steps), int(cols)))
 
 
-def teuk_get_block_steps(h):
-    v = ctypes.c_int32()
-    _check(_lib.teuk_get_block_steps(h, ctypes.byref(v)))
-    return v.value
+def teuk_get_block_launch(h):
+    """(steps, cols) of the block pass (cols 0: unset)."""
+    k, c = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.teuk_get_block_launch(h, ctypes.byref(k), ctypes.byref(c)))
+    return k.value, c.value
 
 
 def teuk_set_finite_check(h, every):
@@ -606,12 +607,20 @@ class TeukGrid:
     def steps_per_pass(self):
         return teuk_get_steps_per_pass(self.handle)
 
+    def set_block_launch(self, steps, cols=0):
+        """Small-grid block pass: steps per launch (0: off) and columns a
+        workgroup holds (0: keep the grid's)."""
+        teuk_set_block_launch(self.handle, steps, cols)
+
+    def block_launch(self):
+        return teuk_get_block_launch(self.handle)
+
     def set_block_steps(self, steps):
-        """Steps per launch of the small-grid block pass (0: off)."""
-        teuk_set_block_steps(self.handle, steps)
+        """Steps per launch of the block pass with the grid's columns (0: off)."""
+        teuk_set_block_launch(self.handle, steps, 0)
 
     def block_steps(self):
-        return teuk_get_block_steps(self.handle)
+        return teuk_get_block_launch(self.handle)[0]
 
     def set_cache_policy(self, policy):
         teuk_set_cache_policy(self.handle, policy)

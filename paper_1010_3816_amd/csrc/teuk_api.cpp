@@ -205,8 +205,8 @@ struct teuk_grid {
     bool fused_ext = true;
     int steps_per_pass = 2;  // 2: pairs of steps in one pass (temporal blocking)
     bool fused_ext2 = true;  // extraction fusable with the two-step strips
-    int block_steps = 0;     // teuk_set_block_steps: steps per launch of the block pass (0: off)
-    int block_cols = 0;      // columns a block-pass workgroup holds (0: the grid has too many rows)
+    int block_steps = 0;     // teuk_set_block_launch: steps per launch of the block pass (0: off)
+    int block_cols = 0;      // columns a block-pass workgroup holds (0: not set)
     int64_t check_every = 0;  // teuk_set_finite_check: steps between device checks of the state (0: off)
     char* sws = nullptr;      // source profile (teuk_set_source): [integer, half][nth][pitch] complex128
     bool coef_set = false;
@@ -492,18 +492,27 @@ int teuk_init_grid(const teuk_params* p, void* hip_stream, void* d_workspace, si
             cus = 256;
         default_tile(nr, nth, cus, &g->rows, &g->wpb);
     }
-    // the block pass: one thread per point of (columns x all rows), at most
-    // 1024 threads and 64 columns a workgroup.  Default: the most steps a
-    // launch whose workgroups (one a CU) fit the device in one round, if at
-    // least 4 (measured on 400 x 16 .. 3200 x 32 and 1600 x 64: fastest where
-    // it applies; 2 steps a launch are slower than the sweeps).
-    if (nth <= kMaxBlockRows) g->block_cols = std::min(64, (int)(1024 / nth));
-    if (g->block_cols > 0 && g->p.coef_mode == TEUK_COEF_KERR) {
-        for (int k = (g->block_cols - 2) / 2; k >= kMinDefaultBlockSteps; --k) {
-            const int64_t w = g->block_cols - 2 * k;
-            if ((nr + w - 1) / w <= cus) {
-                g->block_steps = k;
-                break;
+    // The block pass: one thread per point of (columns x all rows).  Default
+    // launch: over workgroups of up to 256, 512 or 1024 threads (at most 64
+    // columns), the most steps a launch (at least 4) whose workgroups fit the
+    // device one per CU, scored by the per-step time measured on small grids
+    // (400 x 16 .. 3200 x 32, 1600 x 64): about 0.8 ns per point a workgroup
+    // holds plus 3.6 us per launch spread over its steps.
+    if (nth <= kMaxBlockRows && g->p.coef_mode == TEUK_COEF_KERR) {
+        double best = 0.0;
+        for (int threads : {256, 512, 1024}) {
+            const int c = std::min(64, threads / nth);
+            if (c < 2 * kMinDefaultBlockSteps + 2) continue;
+            for (int k = (c - 2) / 2; k >= kMinDefaultBlockSteps; --k) {
+                const int64_t w = c - 2 * k;
+                if ((nr + w - 1) / w > cus) continue;
+                const double score = 0.8e-3 * c * nth + 3.6 / k;  // us per step
+                if (g->block_steps == 0 || score < best) {
+                    best = score;
+                    g->block_steps = k;
+                    g->block_cols = c;
+                }
+                break;  // the most steps for this width
             }
         }
     }
@@ -931,25 +940,29 @@ int teuk_get_steps_per_pass(const teuk_grid* g, int32_t* steps_per_pass) {
     return TEUK_OK;
 }
 
-int teuk_set_block_steps(teuk_grid* g, int32_t steps) {
+int teuk_set_block_launch(teuk_grid* g, int32_t steps, int32_t cols) {
     if (int rc = check_grid(g)) return rc;
     if (steps == 0) {
         g->block_steps = 0;
         return TEUK_OK;
     }
-    if (g->p.coef_mode != TEUK_COEF_KERR || g->block_cols == 0)
+    const int nth = (int)g->p.ntheta;
+    if (g->p.coef_mode != TEUK_COEF_KERR || nth > kMaxBlockRows)
         return fail(TEUK_E_INVALID_ARG, "the block pass needs Kerr coefficients and ntheta <= %d", kMaxBlockRows);
-    const int max_steps = (g->block_cols - 2) / 2;
-    if (steps < 0 || steps > max_steps)
-        return fail(TEUK_E_INVALID_ARG, "block steps=%d outside [0, %d] for ntheta=%lld", steps, max_steps,
-                    (long long)g->p.ntheta);
+    if (cols == 0) cols = g->block_cols > 0 ? g->block_cols : std::min(64, 1024 / nth);
+    if (cols < 4 || cols > 64 || cols * nth > 1024)
+        return fail(TEUK_E_INVALID_ARG, "block cols=%d outside [4, min(64, 1024/ntheta=%d)]", cols, 1024 / nth);
+    if (steps < 0 || steps > (cols - 2) / 2)
+        return fail(TEUK_E_INVALID_ARG, "block steps=%d outside [0, %d] for %d columns", steps, (cols - 2) / 2, cols);
     g->block_steps = steps;
+    g->block_cols = cols;
     return TEUK_OK;
 }
 
-int teuk_get_block_steps(const teuk_grid* g, int32_t* steps) {
+int teuk_get_block_launch(const teuk_grid* g, int32_t* steps, int32_t* cols) {
     if (int rc = check_grid(g)) return rc;
     if (steps) *steps = g->block_steps;
+    if (cols) *cols = g->block_cols;
     return TEUK_OK;
 }
 

@@ -16,7 +16,7 @@ def rel_err(gpu, ref):
 
 
 def run_gpu(binding, w, phi0, pi0, n, tile=None, coef=None, mode=None, steps_per_pass=None, check_every=None,
-            cache_policy=None, block_steps=None):
+            cache_policy=None, block_steps=None, block_cols=0):
     import torch
 
     g = binding.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"],
@@ -37,7 +37,7 @@ def run_gpu(binding, w, phi0, pi0, n, tile=None, coef=None, mode=None, steps_per
     if block_steps is None and (steps_per_pass is not None or tile is not None):
         block_steps = 0
     if block_steps is not None:
-        g.set_block_steps(block_steps)
+        g.set_block_launch(block_steps, block_cols)
     g.set_initial_data(torch.from_numpy(phi0).cuda(), torch.from_numpy(pi0).cuda())
     ser = g.step(n)
     phi, pi = g.state()

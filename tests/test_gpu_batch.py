@@ -115,7 +115,10 @@ def test_autotuners_pick_valid_shapes(gpu, tmp_path, monkeypatch):
     kinds = {e["block"] for e in res["table"]}
     assert 0 in kinds and len(kinds) > 1, kinds
     assert g.tile() == (res["rows"], res["waves"]) and g.block_steps() == res["block"]
-    assert res["block"] in autotune.block_candidates(400, 32, torch.cuda.get_device_properties(0).multi_processor_count) + [0]
+    cands = autotune.block_candidates(400, 32, torch.cuda.get_device_properties(0).multi_processor_count)
+    assert res["block"] == 0 or (res["block"], res["cols"]) in cands
+    if res["block"]:
+        assert g.block_launch() == (res["block"], res["cols"])
     again = autotune.tune_grid(g, rows=(1, 4), waves=(1,), steps=5)
     assert again.get("cached") and again["block"] == res["block"] and g.block_steps() == res["block"]
     g.close()
