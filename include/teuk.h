@@ -204,7 +204,8 @@ double teuk_get_dt(const teuk_grid* g);
  * keep a tile within 64 rows (so a grid that fits one round gets the
  * shortest tiles that do, down to one row); 4 wavefronts per workgroup, or 1
  * when the grid has fewer tiles than the device has SIMDs.  Results do not
- * depend on it (every point's arithmetic is the same). */
+ * depend on it (every point's arithmetic is the same).  It applies to the
+ * sweeps, not to the small-grid block pass (teuk_set_block_launch). */
 int teuk_set_tile(teuk_grid* g, int32_t rows_per_tile, int32_t waves_per_block);
 int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per_block);
 
@@ -216,8 +217,9 @@ int teuk_get_tile(const teuk_grid* g, int32_t* rows_per_tile, int32_t* waves_per
  * intermediate state of a pass in its window slot; its first step runs
  * alone (it also copies its input).  Runs whose extraction points share a
  * tile of the two-step kernel run one step per pass.  The tile rows of
- * teuk_set_tile apply; at most 4 wavefronts per workgroup are used.
- * TEUK_E_INVALID_ARG for other values. */
+ * teuk_set_tile apply; at most 4 wavefronts per workgroup are used.  Where
+ * the small-grid block pass is on (teuk_set_block_launch), teuk_step_n takes
+ * it instead of these passes.  TEUK_E_INVALID_ARG for other values. */
 int teuk_set_steps_per_pass(teuk_grid* g, int32_t steps_per_pass);
 int teuk_get_steps_per_pass(const teuk_grid* g, int32_t* steps_per_pass);
 
