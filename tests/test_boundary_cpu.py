@@ -168,3 +168,25 @@ def test_round_rows_fill_whole_rounds():
             tiles = strips * -(-nth // r)
             assert tiles <= k * 2048, (nr, nth, k, r)
             assert r == 1 or strips * -(-nth // (r - 1)) > k * 2048, (nr, nth, k, r)
+
+
+def test_block_candidates():
+    """Autotuner candidates of the small-grid block pass: (steps, columns)
+    for workgroups of up to 256, 512 and 1024 threads (at most 64 columns),
+    at least 4 steps, and no more workgroups than CUs."""
+    from paper_1010_3816_amd.autotune import block_candidates
+
+    c400 = block_candidates(400, 32, 256)
+    # 8 columns allow 3 steps at most: no candidate; 16 columns: 4..7 steps
+    # (7 writes 2 columns a workgroup: 200 workgroups); 32 columns: 4..15
+    assert [k for k, c in c400 if c == 16] == [4, 5, 6, 7]
+    assert [k for k, c in c400 if c == 32] == list(range(4, 16))
+    assert {c for _, c in c400} == {16, 32}
+    # 3200 x 32 on 256 CUs: at least 13 written columns a workgroup
+    assert max(k for k, c in block_candidates(3200, 32, 256) if c == 32) == 9
+    assert not [k for k, c in block_candidates(3200, 32, 256) if c == 16]
+    assert block_candidates(400, 65, 256) == [] and block_candidates(6400, 64, 256) == []
+    for nr, nth in ((400, 32), (800, 32), (1600, 64), (130, 20), (3, 2)):
+        for k, c in block_candidates(nr, nth, 256):
+            assert 4 <= k <= (c - 2) // 2 and c * nth <= 1024 and c <= 64
+            assert -(-nr // (c - 2 * k)) <= 256
