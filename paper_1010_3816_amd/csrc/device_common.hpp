@@ -27,21 +27,12 @@ constexpr int kDppWaveShl1 = 0x130;
 #ifndef TEUK_ROWS_IN_FLIGHT
 #define TEUK_ROWS_IN_FLIGHT 3
 #endif
-// Tile order of the single-grid launch: 0 = strip-fastest (the wavefronts
-// of a workgroup take neighbouring strips), 1 = chunk-fastest (they take
-// consecutive theta chunks of one strip).
-#ifndef TEUK_CHUNK_FASTEST
-#define TEUK_CHUNK_FASTEST 0
-#endif
 #ifndef TEUK_WAVES_PER_SIMD
 #define TEUK_WAVES_PER_SIMD 2
 #endif
 constexpr int kRowsInFlight = TEUK_ROWS_IN_FLIGHT;
-// The same for the two-step pass.
-#ifndef TEUK_ROWS_IN_FLIGHT2
-#define TEUK_ROWS_IN_FLIGHT2 2
-#endif
-constexpr int kRowsInFlight2 = TEUK_ROWS_IN_FLIGHT2;
+// The same for the two-step pass, whose row loop takes rows in pairs.
+constexpr int kRowsInFlight2 = 2;
 constexpr int kDppWaveShr1 = 0x138;
 
 // bound_ctrl: a lane whose source lane does not exist reads 0, so the

@@ -819,15 +819,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TEUK_W
     // that everything derived from it (rows, table reads, loop control) is
     // scalar.
     const int tile = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x / kWave));
-#if TEUK_CHUNK_FASTEST
-    const int strip = tile / A.n_chunks;
-    const int chunk = tile % A.n_chunks;
-    if (strip >= A.n_strips) return;  // tiles beyond the last
-#else
     const int strip = tile % A.n_strips;
     const int chunk = tile / A.n_strips;
     if (chunk >= A.n_chunks) return;  // tiles beyond the last
-#endif
     sweep_tile<KERR, SRC, KEEP>((gin_t)u_in, (gout_t)u_out, (ctab_t)rad, (ctab_t)ang, (ctab_t)uci, (ctab_t)uch,
                           (cext_t)ext, series, (gout_t)win, A, strip, chunk, lane, (gin_t)src_i, (gin_t)src_h);
 }

@@ -214,9 +214,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
             nxt = cur;  // unused: the sweep ends with this row
         }
         load_row(min(t + 1 + kFtRing, last), rp, rq, rvp, rvq);
-#if TEUK_SPIN_TANGENT_SCHED_BARRIER
-        __builtin_amdgcn_sched_barrier(0);
-#endif
         const Rad Vi = rad_from_lds(rvi, t & A.zero);
         const Sig si = kerr_sigma(Vi, cur.g);
         const Coef ki = kerr_coef(Vi, cur.g, si);
