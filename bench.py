@@ -27,7 +27,10 @@ its ratio to `value`; `waveform` nine modes of one problem and their sum;
 `adjoint` a waveform-loss gradient with respect to the initial data and the
 spin on the 6400 x 256 grid: `ratio` = (forward + backward - plain
 forward) / plain forward by the default route (the spin derivative carried
-forward), and the checkpointed adjoint's routes beside it.  `cpu_baseline` times
+forward), and the checkpointed adjoint's routes beside it.  `source` is the
+inhomogeneous variant (a localised source f(t) g(r*, theta) in the Pi
+equation) on the default workload in the timed run's tile, 48 algorithmic
+bytes per update, and its ratio to `value`.  `cpu_baseline` times
 the CPU oracle (test infrastructure, plain C + OpenMP) on a bounded number of
 steps of the same grid.
 """
@@ -47,6 +50,9 @@ METRIC = "FP64 grid-point updates/s + % HBM roofline; adjoint/forward time ratio
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 BYTES_PER_POINT_PASS = 64   # Phi, Pi read and written once per pass (complex128)
+# the inhomogeneous variant at two steps a pass: the state's 64 B and the
+# source profile's 32 B (g at the column and the half point) per point and pass
+SOURCE_BYTES_PER_UPDATE = (BYTES_PER_POINT_PASS + 32) / 2
 FLOPS_PER_UPDATE = {1: 230, 2: 192}  # FP64 flops per point and step, single-step and two-step kernels
 VALU_PER_UPDATE = {1: 217, 2: 180}   # vector ALU instructions per point and step (from the SQ counters)
 # vector instruction issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per 4 cycles per SIMD
@@ -290,6 +296,48 @@ def workload_leg(name):
     return out
 
 
+def source_leg(name="kerr_a0.99_25600x512", steps=1000, tile=None):
+    """The inhomogeneous variant: a standard workload's pulse plus a
+    localised source f(t) g(r*, theta) (a blob at r* = centre + 20 on the
+    equator, f = 50 exp(0.4 i t)), `steps` steps of teuk_step_n_source in the
+    tile `tile` (rows, waves_per_block), timed with HIP events on the grid's
+    stream.  Algorithmic bytes: the state's 64 B per point per pass of two
+    steps and the profile's 32 B (g at the column and at the half point, read
+    once a pass), 48 B per update."""
+    import torch
+
+    from paper_1010_3816_amd import binding, inputs
+
+    w = inputs.workload(name)
+    g = binding.TeukGrid(w["a"], w["s"], w["m"], w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["dt"])
+    if tile is not None:
+        g.set_tile(*tile)
+    gi, gh = inputs.localised_source(w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["center"] + 20.0)
+    g.set_source(torch.from_numpy(gi).cuda(), torch.from_numpy(gh).cuda())
+    del gi, gh
+    phi0, pi0 = (torch.from_numpy(x).cuda() for x in inputs.initial_data(w))
+    f = inputs.oscillating_factors(steps, w["dt"])
+    g.set_initial_data(phi0, pi0)
+    g.step_source(f[: min(steps, 100)], series=False)  # warm-up
+    g.set_initial_data(phi0, pi0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(g.stream)
+    g.step_source(f, series=False)
+    e1.record(g.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    assert g.check_finite(), "state became non-finite"
+    ups = w["nr"] * w["ntheta"] * steps / (ms * 1e-3)
+    rows, wpb = g.tile()
+    out = {"workload": name, "source": "localised blob at r* = centre + 20, theta = pi/2; f = 50 exp(0.4 i t)",
+           "steps": steps, "ms_per_step": ms / steps, "value": ups, "unit": "grid-point updates/s",
+           "steps_per_pass": g.steps_per_pass(), "bytes_per_update": SOURCE_BYTES_PER_UPDATE,
+           "hbm_frac": SOURCE_BYTES_PER_UPDATE * ups / 1e9 / HBM_PEAK_GBS, "tile_rows": rows, "waves_per_block": wpb}
+    g.close()
+    return out
+
+
 def adjoint_leg(n_steps=None, checkpoint_every=None):
     """Loss and gradients of the waveform misfit on the adjoint workload:
     6400 x 256, a = 0.7, 8000 steps, target = series of the perturbed run
@@ -376,7 +424,7 @@ def main():
     ap.add_argument("--workload", default="kerr_a0.99_25600x512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint legs")
-    ap.add_argument("--only", choices=["batched", "adjoint", "waveform", "c1", "c2"],
+    ap.add_argument("--only", choices=["batched", "adjoint", "waveform", "c1", "c2", "source"],
                     help="run only this leg and print its JSON object (for profiling)")
     ap.add_argument("--batch-launch", default=None,
                     help="rows,waves_per_block,blocks for the batched leg (default: autotune)")
@@ -408,6 +456,10 @@ def main():
         return
     if args.only == "adjoint":
         print(json.dumps(adjoint_leg(n_steps=args.adjoint_steps)), flush=True)
+        return
+    if args.only == "source":
+        print(json.dumps(source_leg(tile=tuple(int(x) for x in args.tile.split(",")) if args.tile else None)),
+              flush=True)
         return
     if args.only in ("c1", "c2"):
         name = {"c1": "schwarzschild_400x32", "c2": "kerr_a0.9_6400x256"}[args.only]
@@ -549,6 +601,9 @@ def main():
         wl["ratio_to_single"] = wl["value"] / ups
         out["waveform"] = wl
         out["adjoint"] = adjoint_leg()
+        sl = source_leg(args.workload, tile=(rows, wpb))
+        sl["ratio_to_homogeneous"] = sl["value"] / ups
+        out["source"] = sl
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

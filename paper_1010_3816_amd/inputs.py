@@ -189,3 +189,29 @@ def initial_data(w, profile=None):
     """(phi0, pi0) for a workload dict."""
     return gaussian_pulse(w["nr"], w["ntheta"], w["rstar_min"], w["rstar_max"], w["center"], w["width"],
                           profile or w["profile"], w["m"], w["s"])
+
+
+# ---------------------------------------------------------------------------
+# a source for the inhomogeneous variant (the paper gives no source model)
+# ---------------------------------------------------------------------------
+
+
+def localised_source(nr, ntheta, rstar_min, rstar_max, center, width=1.0, theta0=math.pi / 2, theta_width=0.1):
+    """(gi, gh) complex128 profiles of a separable source f(t) g(r*, theta):
+    g = exp(-(r* - center)^2 / (2 width^2)) exp(-(theta - theta0)^2 / (2
+    theta_width^2)), a blob standing in for a particle's neighbourhood,
+    sampled at the grid columns (gi, shape (ntheta, nr)) and at the half
+    positions between them (gh, shape (ntheta, nr - 1))."""
+    x = rstar_grid(nr, rstar_min, rstar_max)
+    xh = 0.5 * (x[1:] + x[:-1])
+    ang = np.exp(-((theta_grid(ntheta) - theta0) ** 2) / (2.0 * theta_width**2))[:, None]
+    gi = ang * np.exp(-((x - center) ** 2) / (2.0 * width**2))[None, :] + 0j
+    gh = ang * np.exp(-((xh - center) ** 2) / (2.0 * width**2))[None, :] + 0j
+    return gi, gh
+
+
+def oscillating_factors(n, dt, omega=0.4, amplitude=50.0, t0=0.0):
+    """Time factors of n steps for teuk_step_n_source: row k holds
+    (f(t_k), f(t_k + dt/2)) with f(t) = amplitude exp(i omega t), t_k = t0 + k dt."""
+    t = t0 + np.arange(n) * dt
+    return amplitude * np.stack([np.exp(1j * omega * t), np.exp(1j * omega * (t + 0.5 * dt))], axis=1)

@@ -190,3 +190,27 @@ def test_block_candidates():
         for k, c in block_candidates(nr, nth, 256):
             assert 4 <= k <= (c - 2) // 2 and c * nth <= 1024 and c <= 64
             assert -(-nr // (c - 2 * k)) <= 256
+
+
+def test_source_inputs():
+    """The source-term inputs: profile shapes, the blob's peak at the column
+    and row nearest its centre, the half-position samples between the
+    columns' values, and the time factors (f(t_k), f(t_k + dt/2))."""
+    import numpy as np
+
+    from paper_1010_3816_amd import inputs
+
+    nr, nth = 201, 32
+    gi, gh = inputs.localised_source(nr, nth, -50.0, 150.0, 30.0, width=2.0)
+    assert gi.shape == (nth, nr) and gh.shape == (nth, nr - 1)
+    assert gi.dtype == np.complex128 and gh.dtype == np.complex128
+    j, i = np.unravel_index(np.argmax(np.abs(gi)), gi.shape)
+    assert i == 80 and j in (15, 16)  # r* = 30 is column 80; theta = pi/2 lies between rows 15 and 16
+    # at the half positions the (concave near the peak) Gaussian exceeds the columns' mean there
+    assert gh[j, 80] > 0.5 * (gi[j, 80] + gi[j, 81]).real and gh[j, 79] > 0.5 * (gi[j, 79] + gi[j, 80]).real
+    # 41 or more units of r* from the centre: below exp(-41^2 / 8) ~ 6e-92
+    assert np.max(np.abs(gi[:, :40])) < 1e-91 and np.max(np.abs(gh[:, 121:])) < 1e-91
+    f = inputs.oscillating_factors(5, 0.1, omega=2.0, amplitude=3.0, t0=1.0)
+    assert f.shape == (5, 2)
+    assert np.allclose(f[2, 0], 3.0 * np.exp(2j * 1.2), rtol=0, atol=1e-15)
+    assert np.allclose(f[2, 1], 3.0 * np.exp(2j * 1.25), rtol=0, atol=1e-15)
