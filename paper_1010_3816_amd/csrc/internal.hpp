@@ -167,6 +167,7 @@ hipError_t launch_step2(const StepArgs& a, bool kerr, int waves_per_block, hipSt
 // (a.series: samples of the launch's input states, rows k.row0 + s).
 constexpr int kMaxBlockRows = 64;
 constexpr int kMaxBlockExt = 8;
+constexpr int kMaxBlockSteps = 31;  // (64 columns - 2) / 2
 hipError_t launch_block(const StepArgs& a, hipStream_t s);
 // Zero n ints (a fill kernel: usable where a memset node is not).
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);

@@ -697,6 +697,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
 // equal the sweeps' bit for bit; columns outside the grid read the clamped
 // edge column and, as in the sweeps, reach only the zeroed boundary columns.
 // Extraction: the samples of each step's input state, in the sweeps' order.
+// The points are read once per launch into LDS, each thread works out once
+// which samples it takes, and the launch's series values stay in LDS until
+// its last step: no global memory access inside the step loop, whose
+// barriers would otherwise wait for it every step.
 template <int KEEP>
 __global__ void __launch_bounds__(1024)
     lw_block_kernel(const double2* __restrict__ u_in, double2* __restrict__ u_out, const double* __restrict__ rad,
@@ -717,7 +721,9 @@ __global__ void __launch_bounds__(1024)
     cd* sq = sp + nth * B;
     cd* sh = sq + nth * B;
     cd* shq = sh + nth * B;
-    cd* se = shq + nth * B;
+    cd* se = shq + nth * B;                      // [2 per point] this step's row samples
+    cd* sbuf = se + 2 * kMaxBlockExt;            // [step][point] the launch's series values
+    ExtPoint* sx = reinterpret_cast<ExtPoint*>(sbuf + kMaxBlockSteps * kMaxBlockExt);  // the points
 
     cd p = ld(u_in, (size_t)t * P + ci), q = ld(u_in, (size_t)t * P + ci + A.plane);
     const Ang G = load_ang(ang, nth, t);
@@ -726,6 +732,17 @@ __global__ void __launch_bounds__(1024)
     const Coef ki = kerr_coef(Ri, G, kerr_sigma(Ri, G));
     sp[me] = p;
     sq[me] = q;
+    if ((int)threadIdx.x < A.n_ext) sx[threadIdx.x] = ext[threadIdx.x];
+    // this thread's samples: bit 2e (row a of point e) and bit 2e + 1 (row
+    // b), for the points whose column the workgroup writes
+    unsigned duty = 0;
+    for (int e = 0; e < A.n_ext; ++e) {
+        const ExtPoint E = ext[e];
+        if (E.col >= c0 && E.col < c0 + W && col == E.col) {
+            if (t == E.rowa) duty |= 1u << (2 * e);
+            else if (t == E.rowb) duty |= 2u << (2 * e);
+        }
+    }
     __syncthreads();
 
     for (int s = 0; s < K; ++s) {
@@ -740,10 +757,10 @@ __global__ void __launch_bounds__(1024)
         const cd hp = {fma(-tb, dp.re, fma(A.hdt, ubq.re, ubp.re)), fma(-tb, dp.im, fma(A.hdt, ubq.im, ubp.im))};
         const cd dq = csub(qr, q);
         sh[me] = hp;
-        for (int e = 0; e < A.n_ext; ++e) {  // the points whose column this workgroup writes
-            const ExtPoint E = ext[e];
-            if (E.col >= c0 && E.col < c0 + W && col == E.col && (t == E.rowa || t == E.rowb))
-                se[2 * e + (t == E.rowa ? 0 : 1)] = {fma(E.wr, pr.re - p.re, p.re), fma(E.wr, pr.im - p.im, p.im)};
+        for (unsigned d = duty; d != 0; d &= d - 1) {
+            const int b = __builtin_ctz(d);
+            const double wr = sx[b >> 1].wr;
+            se[b] = {fma(wr, pr.re - p.re, p.re), fma(wr, pr.im - p.im, p.im)};
         }
         const cd um = (t == 0) ? cscale(sg, ubp) : cavg(sp[me - B], sp[(t - 1) * B + jr]);
         const cd ubp_p = (t == nth - 1) ? cscale(sg, ubp) : cavg(sp[me + B], sp[(t + 1) * B + jr]);
@@ -755,9 +772,9 @@ __global__ void __launch_bounds__(1024)
         shq[me] = hq;
         __syncthreads();
 
-        // stage 2 at (i, t); one thread per point writes its sample
-        if ((int)threadIdx.x < A.n_ext && A.row0 + s >= 0) {
-            const ExtPoint E = ext[threadIdx.x];
+        // stage 2 at (i, t); one thread per point forms its sample
+        if ((int)threadIdx.x < A.n_ext) {
+            const ExtPoint E = sx[threadIdx.x];
             if (E.col >= c0 && E.col < c0 + W) {
                 const cd va = se[2 * threadIdx.x];
                 cd acc = {fma(E.wa, va.re, 0.0), fma(E.wa, va.im, 0.0)};
@@ -765,7 +782,7 @@ __global__ void __launch_bounds__(1024)
                     const cd vb = se[2 * threadIdx.x + 1];
                     acc = {fma(E.wb, vb.re, acc.re), fma(E.wb, vb.im, acc.im)};
                 }
-                series[(size_t)(A.row0 + s) * A.n_ext + threadIdx.x] = double2{acc.re, acc.im};
+                sbuf[s * kMaxBlockExt + threadIdx.x] = acc;
             }
         }
         const cd hpl = sh[t * B + jl];
@@ -794,6 +811,17 @@ __global__ void __launch_bounds__(1024)
     if (j >= K && j < K + W && col < nr) {
         st_state<KEEP>(u_out, (size_t)t * P + col, p);
         st_state<KEEP>(u_out, (size_t)t * P + col + A.plane, q);
+    }
+    // the series values of the launch's steps (state row0 + s + 1 at series
+    // row row0 + s; none for the initial state)
+    if ((int)threadIdx.x < A.n_ext) {
+        const ExtPoint E = sx[threadIdx.x];
+        if (E.col >= c0 && E.col < c0 + W)
+            for (int s = 0; s < K; ++s)
+                if (A.row0 + s >= 0) {
+                    const cd v = sbuf[s * kMaxBlockExt + threadIdx.x];
+                    series[(size_t)(A.row0 + s) * A.n_ext + threadIdx.x] = double2{v.re, v.im};
+                }
     }
 }
 
@@ -1027,7 +1055,11 @@ hipError_t launch_step(const StepArgs& a, bool kerr, int waves_per_block, hipStr
 hipError_t launch_block(const StepArgs& a, hipStream_t s) {
     const int w = a.k.bcols - 2 * a.k.bsteps;
     const dim3 grid((a.k.nr + w - 1) / w), block(a.k.bcols * a.k.nth);
-    const size_t lds = (size_t)(4 * a.k.nth * a.k.bcols + 2 * kMaxBlockExt) * sizeof(double2);
+    static_assert(sizeof(ExtPoint) == 3 * sizeof(double2), "the points' LDS area");
+    if (a.k.bsteps > kMaxBlockSteps || a.k.n_ext > kMaxBlockExt) return hipErrorInvalidValue;
+    const size_t lds =
+        (size_t)(4 * a.k.nth * a.k.bcols + 2 * kMaxBlockExt + kMaxBlockSteps * kMaxBlockExt + 3 * kMaxBlockExt) *
+        sizeof(double2);
     hipLaunchKernelGGL(a.k.keep ? lw_block_kernel<1> : lw_block_kernel<0>, grid, block, lds, s, a.u_in, a.u_out,
                        a.rad, a.ang, a.ext, a.series, a.k);
     return hipGetLastError();
