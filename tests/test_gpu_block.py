@@ -200,3 +200,25 @@ def test_block_pass_finite_check(gpu):
     assert ei.value.code == gpu.TEUK_E_NONFINITE and "after step 10" in str(ei.value), str(ei.value)
     assert g.steps == 24
     g.close()
+
+
+@pytest.mark.parametrize("k,c", [(5, 16), (7, 32), (2, 8)])
+def test_block_pass_points_sharing_rows(gpu, k, c):
+    """Points whose samples fall on the same thread: at one r*, point A on
+    rows 3, 4 and point B on rows 4, 5 (the thread of row 4 samples for
+    both), a copy of A (two samples of one row in one step), and a point in
+    the first column of a workgroup; the sweeps' series bit for bit."""
+    nth = 16
+    dth = math.pi / nth
+    ra = -30.0 + 37.3 * 90.0 / 199
+    ext = ((ra, 3.8 * dth), (ra, 5.1 * dth), (ra, 3.8 * dth), (-30.0 + (c - 2 * k) * 90.0 / 199, 0.9))
+    w = small_case(0.6, -2, 2, 200, nth, rmin=-30.0, rmax=60.0, ext=ext)
+    phi0, pi0 = inputs.random_state(200, nth, seed=700 + c)
+    n = 3 * k + 1
+    ref = run_gpu(gpu, w, phi0, pi0, n, block_steps=0)
+    blk = run_gpu(gpu, w, phi0, pi0, n, block_steps=k, block_cols=c)
+    for i in range(3):
+        assert np.array_equal(blk[i], ref[i]), i
+    assert np.array_equal(blk[2][:, 0], blk[2][:, 2])  # the copy of A
+    o = run_oracle(w, phi0, pi0, n)
+    assert rel_err(blk[2], o[2]) <= TOL
